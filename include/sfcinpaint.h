@@ -1,0 +1,235 @@
+/*
+ * sfcinpaint.h -- C ABI of the MI355X (gfx950) masked-L2 patch search for
+ * exemplar-based inpainting, after Dahmen et al., "Space-Filling Curve
+ * Indices as Acceleration Structure for Exemplar-Based Inpainting".
+ *
+ * The library answers the per-iteration question of exemplar-based inpainting
+ * (Section I): which fully known patch of the image (the dictionary) best
+ * matches the known pixels of a target patch under the masked L2 cost. It
+ * does so either by a full scan of the dictionary (Section I) or through the
+ * space-filling-curve multi-index of Section II (pixel subsets, PCA to D
+ * dimensions, several shifted curves, binary search, a candidate window per
+ * curve, exact rescoring of the candidates in image space).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (HIP device memory) unless the
+ *    argument name ends in _host. All work is enqueued on the stream given in
+ *    sfc_options (NULL = the default stream) or in a `stream` argument
+ *    (a hipStream_t passed as void*). Outputs are valid once that stream has
+ *    synchronised; functions that return a host value synchronise it.
+ *  - Layouts: a volume is float32 [shape[0], ..., shape[ndim-1], channels],
+ *    channel innermost, spatial dims slowest first. A mask is uint8
+ *    [shape...], 1 = known, 0 = missing. A voxel id is the row-major linear
+ *    index over the spatial dims. A patch has K^ndim pixels (K odd, centred
+ *    on its voxel id); pixel rho is the row-major index in the K^ndim box;
+ *    element e = rho*channels + ch. A target is float32 [Q, K^ndim, channels]
+ *    and its mask uint8 [Q, K^ndim].
+ *  - Every function returns an sfc_status (0 = success, negative = error),
+ *    never throws, and leaves its outputs untouched on argument errors.
+ *    sfc_last_error() gives a message for the calling thread's last error.
+ *  - Results are deterministic: the same inputs give the same bits. The
+ *    selected patch is the minimum of (cost, id), so ties go to the lowest id.
+ */
+#ifndef SFCINPAINT_H
+#define SFCINPAINT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFC_ABI_VERSION 1
+
+typedef enum {
+    SFC_OK = 0,
+    SFC_EINVAL = -1,       /* invalid argument (null pointer, bad geometry, range) */
+    SFC_ENOMEM = -2,       /* device allocation failed */
+    SFC_EDEVICE = -3,      /* a HIP call or kernel launch failed */
+    SFC_EEMPTY = -4,       /* the dictionary has no fully known patch */
+    SFC_EUNSUPPORTED = -5  /* valid but outside what this build handles */
+} sfc_status;
+
+typedef enum { SFC_CURVE_MORTON = 0, SFC_CURVE_HILBERT = 1 } sfc_curve;
+
+typedef enum {
+    SFC_MODE_BRUTE_FP32 = 0,  /* full scan, float32 fixed-order cost */
+    SFC_MODE_BRUTE_BF16 = 1,  /* full scan, bf16 MFMA filter + exact rescoring */
+    SFC_MODE_BRUTE_FP8 = 2,   /* full scan, fp8 MFMA filter + exact rescoring */
+    SFC_MODE_INDEX = 3        /* space-filling-curve multi-index */
+} sfc_mode;
+
+typedef enum { SFC_ORDER_CRIMINISI = 0, SFC_ORDER_RASTER = 1 } sfc_order;
+
+typedef struct {
+    int32_t ndim;       /* 2 or 3 */
+    int32_t channels;   /* C >= 1 */
+    int64_t shape[3];   /* spatial extent, slowest first; unused entries ignored */
+} sfc_geometry;
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(sfc_options); older callers pass less */
+    int32_t key_bits;      /* b, bits per principal coordinate (1..31), default 8 */
+    int32_t window;        /* W, candidates taken from each curve, default 32 */
+    int32_t curve;         /* sfc_curve, default SFC_CURVE_MORTON */
+    int32_t rescore_top;   /* T, candidates rescored per query by the
+                              reduced-precision scans, default 16 */
+    int32_t certify;       /* 1 (default): a reduced-precision answer whose
+                              certificate fails is recomputed by the float32 scan */
+    int32_t query_block;   /* queries per float32-scan pass, 0 = library choice */
+    int32_t reserved;
+    void *stream;          /* hipStream_t; NULL = default stream */
+} sfc_options;
+
+typedef struct sfc_index sfc_index;  /* opaque */
+
+typedef struct {
+    int64_t n;             /* dictionary size */
+    int64_t n_sub;         /* PCA subsample size (0 without an SFC index) */
+    int32_t ndim, channels, K, P;
+    int32_t has_sfc;       /* 0: dictionary only (full-scan modes) */
+    int32_t n_subsets, reduced_dim, n_curves, key_bits, key_words, window, curve;
+    float vmin, qscale;    /* byte-quantisation parameters */
+} sfc_index_info;
+
+typedef struct {
+    int64_t cap;           /* entries the arrays hold */
+    int64_t len;           /* entries written (<= cap) */
+    int64_t *centre_host;  /* target centre of each iteration */
+    int64_t *source_host;  /* chosen dictionary centre */
+    float *cost_host;      /* its cost */
+} sfc_fill_log;
+
+/* Library ABI version (SFC_ABI_VERSION). */
+int32_t sfc_abi_version(void);
+
+/* Message for the calling thread's last error ("" if none). */
+const char *sfc_last_error(void);
+
+/* Fill the defaults documented in sfc_options. */
+void sfc_options_default(sfc_options *opt);
+
+/* Fill front (Fig. 1a: known pixels adjacent to unknown ones; adjacency =
+ * shared face). Writes the front's voxel ids in ascending order to
+ * centres[0 .. min(count, capacity)), and the total to *count_host.
+ * mask: device uint8 [shape]. Synchronises `stream`. */
+sfc_status sfc_fill_front(const uint8_t *mask, const sfc_geometry *g, int64_t *centres,
+                          int64_t capacity, int64_t *count_host, void *stream);
+
+/* Target patches (Fig. 1a: the search area is the known part of the patch
+ * at a front voxel). For each centre: targets = volume value of in-bounds
+ * known pixels, 0 elsewhere; target_masks = 1 where in bounds and known.
+ * centres: device int64 [Q]; targets float32 [Q, K^ndim, C]; masks uint8
+ * [Q, K^ndim]. Q = 0 is a no-op. */
+sfc_status sfc_extract_targets(const float *volume, const uint8_t *mask,
+                               const sfc_geometry *g, int32_t K, const int64_t *centres,
+                               int64_t Q, float *targets, uint8_t *target_masks,
+                               void *stream);
+
+/* Dictionary only (Section I: every fully known K^ndim patch lying inside the
+ * volume), for the full-scan modes. The handle BORROWS `volume`: it must stay
+ * alive and its dictionary patches unchanged until sfc_index_free. The mask
+ * is read once. Returns SFC_EEMPTY if no patch is fully known. */
+sfc_status sfc_dictionary_build(const float *volume, const uint8_t *mask,
+                                const sfc_geometry *g, int32_t K, const sfc_options *opt,
+                                sfc_index **out);
+
+/* Full SFC multi-index (Section II): byte quantisation, 3^ndim - 1 pixel
+ * subsets of ceil(0.6 K^ndim) pixels each (Fig. 2), exact integer covariance,
+ * float64 Jacobi eigendecomposition and an int8 basis of the first
+ * reduced_dim components per subset (Section II.A), and n_curves shifted
+ * curves per subset whose (key, id) arrays are sorted on the device
+ * (Section II.C). Also usable for the full-scan modes. Same borrowing rule
+ * as sfc_dictionary_build. Errors: SFC_EINVAL for K even, K > a side,
+ * reduced_dim < 1 or > a subset's element count, n_curves < 1 or >
+ * reduced_dim + 1, key_bits * reduced_dim > 256; SFC_EUNSUPPORTED for a
+ * subset with more than 518 elements (the exact-integer bound of the bf16
+ * projection) or more than 2^32 voxels. */
+sfc_status sfc_index_build(const float *volume, const uint8_t *mask, const sfc_geometry *g,
+                           int32_t K, int32_t reduced_dim, int32_t n_curves,
+                           const sfc_options *opt, sfc_index **out);
+
+/* As sfc_index_build, but with the int8 bases given instead of computed:
+ * bases_host holds, subset after subset, m_s x reduced_dim int8 row-major
+ * (m_s = the subset's element count). */
+sfc_status sfc_index_build_with_basis(const float *volume, const uint8_t *mask,
+                                      const sfc_geometry *g, int32_t K, int32_t reduced_dim,
+                                      int32_t n_curves, const sfc_options *opt,
+                                      const int8_t *bases_host, sfc_index **out);
+
+/* Best dictionary patch for each target (Fig. 1). cost = float32 sum over
+ * known rho ascending, channel ascending, of d*d (d = target - patch value)
+ * as a fused-multiply-add chain from +0; the answer minimises (cost, id).
+ * SFC_MODE_BRUTE_* modes return the global minimum over the dictionary (the
+ * reduced-precision ones certify it or fall back); SFC_MODE_INDEX returns the
+ * minimum over the index's candidates. best_id int64 [Q], best_cost float32
+ * [Q]. Q = 0 is a no-op. SFC_EINVAL for SFC_MODE_INDEX on a dictionary-only
+ * handle. */
+sfc_status sfc_query(sfc_index *idx, const float *targets, const uint8_t *target_masks,
+                     int64_t Q, sfc_mode mode, int64_t *best_id, float *best_cost);
+
+/* Candidate sets of the index query: cand int64 [Q, n_curves*window], the
+ * sorted unique dictionary ids per query padded with -1; ncand int32 [Q]. */
+sfc_status sfc_query_candidates(sfc_index *idx, const float *targets,
+                                const uint8_t *target_masks, int64_t Q, int64_t *cand,
+                                int32_t *ncand);
+
+/* Per-query subset choice and real principal coordinates (diagnostics):
+ * subset int32 [Q], coords float64 [Q, reduced_dim]. */
+sfc_status sfc_query_coords(sfc_index *idx, const float *targets,
+                            const uint8_t *target_masks, int64_t Q, int32_t *subset,
+                            double *coords);
+
+/* Statistics of the last sfc_query call on this handle (host values):
+ * n_fallback = queries a reduced-precision scan could not certify. */
+sfc_status sfc_query_stats(const sfc_index *idx, int64_t *n_fallback_host);
+
+/* Handle description. */
+sfc_status sfc_index_info_get(const sfc_index *idx, sfc_index_info *info_host);
+
+/* Dictionary ids, ascending: device int64 [n]. */
+sfc_status sfc_index_dictionary(const sfc_index *idx, int64_t *ids);
+
+/* Byte-quantised volume: device uint8 [shape, C]. */
+sfc_status sfc_index_quantized(const sfc_index *idx, uint8_t *xq);
+
+/* A subset's int8 basis (host, m_s x reduced_dim) and element count. */
+sfc_status sfc_index_get_basis(const sfc_index *idx, int32_t subset, int8_t *basis_host,
+                               int32_t *rows_host);
+
+/* A subset's grid parameters: lo_host int64 [reduced_dim], span_host. */
+sfc_status sfc_index_get_params(const sfc_index *idx, int32_t subset, int64_t *lo_host,
+                                int64_t *span_host);
+
+/* Principal coordinates of every dictionary patch for one subset, exact
+ * integers: device int64 [n, reduced_dim] in dictionary order. */
+sfc_status sfc_index_projection(const sfc_index *idx, int32_t subset, int64_t *y);
+
+/* One sorted curve: keys uint64 [n, key_words] (word 0 most significant)
+ * and ids int64 [n], in (key, id) order. */
+sfc_status sfc_index_export(const sfc_index *idx, int32_t subset, int32_t curve,
+                            uint64_t *keys, int64_t *ids);
+
+/* Release the handle and its device memory. NULL is a no-op. */
+void sfc_index_free(sfc_index *idx);
+
+/* Fill loop (Section I, Criminisi order): while a voxel is unknown, pick the
+ * front voxel of highest (priority, confidence, -id) (SFC_ORDER_CRIMINISI)
+ * or the lowest front id (SFC_ORDER_RASTER), query its target patch in
+ * `mode`, copy the chosen patch into the unknown in-bounds pixels of the
+ * target, mark them known. volume and mask are updated in place. The
+ * dictionary is fixed at the start: `idx` if given (it must have been built
+ * from this volume and mask), else a private one (with an SFC index when
+ * mode == SFC_MODE_INDEX, using reduced_dim 8 and 4 curves). *n_iters_host
+ * receives the iteration count; log (nullable, host arrays) the first cap
+ * iterations. SFC_EINVAL if K < 3; SFC_EEMPTY if the dictionary is empty or
+ * unknown voxels remain with an empty front. */
+sfc_status sfc_inpaint(float *volume, uint8_t *mask, const sfc_geometry *g, int32_t K,
+                       sfc_order order, sfc_mode mode, sfc_index *idx,
+                       const sfc_options *opt, int64_t *n_iters_host, sfc_fill_log *log);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFCINPAINT_H */

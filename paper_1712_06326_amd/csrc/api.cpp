@@ -1,0 +1,372 @@
+// C ABI: argument checks, handle lifetime and orchestration of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "index.hpp"
+
+namespace sfc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+sfc_status fail(sfc_status code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+sfc_status check_hip(hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return fail(SFC_ENOMEM, m);
+    return fail(SFC_EDEVICE, m);
+}
+
+// Allocation with an optional injected failure: SFC_FAULT_INJECT=alloc:<n>
+// makes the n-th device allocation of the process fail (for error-path tests).
+static long g_alloc_count = 0;
+static long fault_alloc_at() {
+    static long at = -2;
+    if (at == -2) {
+        at = -1;
+        const char* s = std::getenv("SFC_FAULT_INJECT");
+        if (s && std::strncmp(s, "alloc:", 6) == 0) at = std::atol(s + 6);
+    }
+    return at;
+}
+
+sfc_status dev_alloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    long at = fault_alloc_at();
+    g_alloc_count++;
+    if (at >= 0 && g_alloc_count == at)
+        return fail(SFC_ENOMEM, std::string(what) + ": injected allocation failure");
+    if (bytes == 0) bytes = 1;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SFC_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    return SFC_OK;
+}
+
+void dev_free(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+sfc_status Scratch::reserve(size_t bytes, const char* what) {
+    if (bytes <= cap) return SFC_OK;
+    dev_free(ptr);
+    ptr = nullptr;
+    cap = 0;
+    SFC_TRY(dev_alloc(&ptr, bytes, what));
+    cap = bytes;
+    return SFC_OK;
+}
+
+Scratch::~Scratch() { dev_free(ptr); }
+
+static sfc_status check_geometry(const sfc_geometry* g, int K) {
+    if (!g) return fail(SFC_EINVAL, "geometry is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(SFC_EINVAL, "ndim must be 2 or 3");
+    if (g->channels < 1 || g->channels > 16) return fail(SFC_EINVAL, "channels must be 1..16");
+    int64_t nvox = 1;
+    for (int i = 0; i < g->ndim; i++) {
+        if (g->shape[i] < 1) return fail(SFC_EINVAL, "shape entries must be >= 1");
+        nvox *= g->shape[i];
+    }
+    if (nvox > (int64_t)0xffffffffLL)
+        return fail(SFC_EUNSUPPORTED, "more than 2^32 voxels (ids are 32-bit inside kernels)");
+    if (K >= 0) {
+        if (K < 1 || (K & 1) == 0) return fail(SFC_EINVAL, "patch size K must be odd and >= 1");
+        if (K > 31) return fail(SFC_EUNSUPPORTED, "patch size K above 31");
+        for (int i = 0; i < g->ndim; i++)
+            if (K > g->shape[i]) return fail(SFC_EINVAL, "patch size K larger than a side");
+    }
+    return SFC_OK;
+}
+
+sfc_options resolve_options(const sfc_options* in) {
+    sfc_options o;
+    sfc_options_default(&o);
+    if (in) {
+        size_t n = in->struct_size;
+        if (n > sizeof(sfc_options)) n = sizeof(sfc_options);
+        if (n >= sizeof(uint32_t)) std::memcpy(&o, in, n);
+        o.struct_size = sizeof(sfc_options);
+    }
+    return o;
+}
+
+sfc_status validate_options(const sfc_options& o) {
+    if (o.key_bits < 1 || o.key_bits > 31) return fail(SFC_EINVAL, "key_bits must be 1..31");
+    if (o.window < 1) return fail(SFC_EINVAL, "window must be >= 1");
+    if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT)
+        return fail(SFC_EINVAL, "unknown curve");
+    if (o.rescore_top < 1 || o.rescore_top > 64) return fail(SFC_EINVAL, "rescore_top must be 1..64");
+    if (o.query_block < 0) return fail(SFC_EINVAL, "query_block must be >= 0");
+    return SFC_OK;
+}
+
+// Dictionary of a handle: validity map + ascending id list.
+sfc_status build_dictionary(sfc_index* ix, const uint8_t* mask) {
+    const Grid& g = ix->g;
+    hipStream_t st = ix->st;
+    SFC_TRY(dev_alloc((void**)&ix->valid, (size_t)g.nvox, "dictionary validity map"));
+    Scratch tmp;
+    SFC_TRY(tmp.reserve((size_t)g.nvox + compact_scratch_bytes(g.nvox) + 64, "dictionary scratch"));
+    uint8_t* t8 = static_cast<uint8_t*>(tmp.ptr);
+    SFC_TRY(launch_valid_centres(mask, g, ix->valid, t8, st));
+    // count, allocate, compact
+    uint8_t* after = t8 + ((g.nvox + 63) / 64) * 64;
+    int64_t* count_dev = reinterpret_cast<int64_t*>(after);
+    void* cscratch = after + 64;
+    SFC_TRY(launch_compact(ix->valid, g.nvox, nullptr, nullptr, 0, count_dev, cscratch, st));
+    int64_t n = 0;
+    SFC_HIP(hipMemcpyAsync(&n, count_dev, sizeof(n), hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    if (n == 0) return fail(SFC_EEMPTY, "no fully known patch: the dictionary is empty");
+    ix->n = n;
+    SFC_TRY(dev_alloc((void**)&ix->dict, (size_t)n * sizeof(uint32_t), "dictionary ids"));
+    SFC_TRY(launch_compact(ix->valid, g.nvox, nullptr, ix->dict, n, count_dev, cscratch, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    return SFC_OK;
+}
+
+}  // namespace sfc
+
+sfc_index::~sfc_index() {
+    sfc::dev_free(valid);
+    sfc::dev_free(dict);
+    sfc::release_sfc(this);
+}
+
+namespace sfc {
+
+sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
+                            uint64_t* best_dev) {
+    const Grid& g = ix->g;
+    SFC_TRY(ix->rowmask.reserve((size_t)Q * g.rows * sizeof(uint32_t), "row masks"));
+    uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
+    SFC_TRY(launch_pack_rowmask(m, g, Q, rm, ix->st));
+    SFC_TRY(launch_fill_u64(best_dev, Q, ~0ull, ix->st));
+    ScanArgs a{ix->vol, ix->valid, t, rm, Q, best_dev, ix->opt.query_block};
+    return launch_scan_fp32(g, a, ix->st);
+}
+
+}  // namespace sfc
+
+using namespace sfc;
+
+extern "C" {
+
+int32_t sfc_abi_version(void) { return SFC_ABI_VERSION; }
+
+const char* sfc_last_error(void) { return g_last_error.c_str(); }
+
+void sfc_options_default(sfc_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(sfc_options);
+    o->key_bits = 8;
+    o->window = 32;
+    o->curve = SFC_CURVE_MORTON;
+    o->rescore_top = 16;
+    o->certify = 1;
+    o->query_block = 0;
+    o->stream = nullptr;
+}
+
+sfc_status sfc_fill_front(const uint8_t* mask, const sfc_geometry* g, int64_t* centres,
+                          int64_t capacity, int64_t* count_host, void* stream) {
+    clear_error();
+    SFC_TRY(check_geometry(g, -1));
+    if (!mask || !count_host || (capacity > 0 && !centres) || capacity < 0)
+        return fail(SFC_EINVAL, "sfc_fill_front: null pointer or negative capacity");
+    Grid gr = make_grid(g, 1);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch tmp;
+    SFC_TRY(tmp.reserve((size_t)gr.nvox + 64 + compact_scratch_bytes(gr.nvox), "front scratch"));
+    uint8_t* flags = static_cast<uint8_t*>(tmp.ptr);
+    uint8_t* after = flags + ((gr.nvox + 63) / 64) * 64;
+    int64_t* count_dev = reinterpret_cast<int64_t*>(after);
+    SFC_TRY(launch_front_flags(mask, gr, flags, st));
+    SFC_TRY(launch_compact(flags, gr.nvox, centres ? centres : count_dev, nullptr, capacity,
+                           count_dev, after + 64, st));
+    int64_t n = 0;
+    SFC_HIP(hipMemcpyAsync(&n, count_dev, sizeof(n), hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    *count_host = n;
+    return SFC_OK;
+}
+
+sfc_status sfc_extract_targets(const float* volume, const uint8_t* mask, const sfc_geometry* g,
+                               int32_t K, const int64_t* centres, int64_t Q, float* targets,
+                               uint8_t* target_masks, void* stream) {
+    clear_error();
+    SFC_TRY(check_geometry(g, K));
+    if (Q < 0) return fail(SFC_EINVAL, "Q must be >= 0");
+    if (Q == 0) return SFC_OK;
+    if (!volume || !mask || !centres || !targets || !target_masks)
+        return fail(SFC_EINVAL, "sfc_extract_targets: null pointer");
+    Grid gr = make_grid(g, K);
+    return launch_extract(volume, mask, gr, centres, Q, targets, target_masks,
+                          static_cast<hipStream_t>(stream));
+}
+
+static sfc_status new_handle(const float* volume, const uint8_t* mask, const sfc_geometry* g,
+                             int32_t K, const sfc_options* opt, sfc_index** out) {
+    if (!out) return fail(SFC_EINVAL, "out is NULL");
+    *out = nullptr;
+    SFC_TRY(check_geometry(g, K));
+    if (!volume || !mask) return fail(SFC_EINVAL, "volume or mask is NULL");
+    sfc_options o = resolve_options(opt);
+    SFC_TRY(validate_options(o));
+    sfc_index* ix = new sfc_index();
+    ix->g = make_grid(g, K);
+    ix->opt = o;
+    ix->st = static_cast<hipStream_t>(o.stream);
+    ix->vol = volume;
+    sfc_status s = build_dictionary(ix, mask);
+    if (s != SFC_OK) {
+        delete ix;
+        return s;
+    }
+    *out = ix;
+    return SFC_OK;
+}
+
+sfc_status sfc_dictionary_build(const float* volume, const uint8_t* mask, const sfc_geometry* g,
+                                int32_t K, const sfc_options* opt, sfc_index** out) {
+    clear_error();
+    return new_handle(volume, mask, g, K, opt, out);
+}
+
+sfc_status sfc_index_build(const float* volume, const uint8_t* mask, const sfc_geometry* g,
+                           int32_t K, int32_t reduced_dim, int32_t n_curves,
+                           const sfc_options* opt, sfc_index** out) {
+    return sfc_index_build_with_basis(volume, mask, g, K, reduced_dim, n_curves, opt, nullptr,
+                                      out);
+}
+
+sfc_status sfc_index_build_with_basis(const float* volume, const uint8_t* mask,
+                                      const sfc_geometry* g, int32_t K, int32_t reduced_dim,
+                                      int32_t n_curves, const sfc_options* opt,
+                                      const int8_t* bases_host, sfc_index** out) {
+    clear_error();
+    if (!out) return fail(SFC_EINVAL, "out is NULL");
+    *out = nullptr;
+    SFC_TRY(check_geometry(g, K));
+    sfc_options o = resolve_options(opt);
+    SFC_TRY(validate_options(o));
+    SFC_TRY(check_sfc_args(g, K, reduced_dim, n_curves, o));
+    sfc_index* ix = nullptr;
+    SFC_TRY(new_handle(volume, mask, g, K, opt, &ix));
+    sfc_status s = build_sfc(ix, mask, reduced_dim, n_curves, bases_host);
+    if (s != SFC_OK) {
+        delete ix;
+        return s;
+    }
+    *out = ix;
+    return SFC_OK;
+}
+
+void sfc_index_free(sfc_index* idx) { delete idx; }
+
+sfc_status sfc_index_info_get(const sfc_index* ix, sfc_index_info* info) {
+    clear_error();
+    if (!ix || !info) return fail(SFC_EINVAL, "null pointer");
+    std::memset(info, 0, sizeof(*info));
+    info->n = ix->n;
+    info->ndim = ix->g.nd;
+    info->channels = ix->g.C;
+    info->K = ix->g.K;
+    info->P = ix->g.Kd * ix->g.C;
+    info->has_sfc = ix->has_sfc ? 1 : 0;
+    info->window = ix->opt.window;
+    info->curve = ix->opt.curve;
+    info->key_bits = ix->opt.key_bits;
+    if (ix->has_sfc) {
+        info->n_sub = ix->nsub;
+        info->n_subsets = ix->S;
+        info->reduced_dim = ix->D;
+        info->n_curves = ix->L;
+        info->key_words = ix->W64;
+        info->vmin = ix->vmin;
+        info->qscale = ix->qscale;
+    }
+    return SFC_OK;
+}
+
+sfc_status sfc_index_dictionary(const sfc_index* ix, int64_t* ids) {
+    clear_error();
+    if (!ix || !ids) return fail(SFC_EINVAL, "null pointer");
+    return launch_u32_to_i64(ix->dict, ids, ix->n, ix->st);
+}
+
+sfc_status sfc_query(sfc_index* ix, const float* targets, const uint8_t* target_masks, int64_t Q,
+                     sfc_mode mode, int64_t* best_id, float* best_cost) {
+    clear_error();
+    if (!ix) return fail(SFC_EINVAL, "index is NULL");
+    if (Q < 0) return fail(SFC_EINVAL, "Q must be >= 0");
+    if (Q == 0) return SFC_OK;
+    if (!targets || !target_masks || !best_id || !best_cost)
+        return fail(SFC_EINVAL, "sfc_query: null pointer");
+    ix->last_fallback = 0;
+    switch (mode) {
+    case SFC_MODE_BRUTE_FP32: {
+        SFC_TRY(ix->best.reserve((size_t)Q * sizeof(uint64_t), "query results"));
+        uint64_t* best = static_cast<uint64_t*>(ix->best.ptr);
+        SFC_TRY(query_brute_fp32(ix, targets, target_masks, Q, best));
+        return launch_unpack_best(best, Q, best_id, best_cost, ix->st);
+    }
+    case SFC_MODE_BRUTE_BF16:
+    case SFC_MODE_BRUTE_FP8:
+        return query_brute_reduced(ix, targets, target_masks, Q, mode, best_id, best_cost);
+    case SFC_MODE_INDEX:
+        if (!ix->has_sfc) return fail(SFC_EINVAL, "index mode needs an SFC index handle");
+        return query_index(ix, targets, target_masks, Q, best_id, best_cost, nullptr, nullptr);
+    default:
+        return fail(SFC_EINVAL, "unknown mode");
+    }
+}
+
+sfc_status sfc_query_candidates(sfc_index* ix, const float* targets, const uint8_t* target_masks,
+                                int64_t Q, int64_t* cand, int32_t* ncand) {
+    clear_error();
+    if (!ix) return fail(SFC_EINVAL, "index is NULL");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "candidates need an SFC index handle");
+    if (Q < 0) return fail(SFC_EINVAL, "Q must be >= 0");
+    if (Q == 0) return SFC_OK;
+    if (!targets || !target_masks || !cand || !ncand)
+        return fail(SFC_EINVAL, "sfc_query_candidates: null pointer");
+    return query_index(ix, targets, target_masks, Q, nullptr, nullptr, cand, ncand);
+}
+
+sfc_status sfc_query_coords(sfc_index* ix, const float* targets, const uint8_t* target_masks,
+                            int64_t Q, int32_t* subset, double* coords) {
+    clear_error();
+    if (!ix) return fail(SFC_EINVAL, "index is NULL");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "coordinates need an SFC index handle");
+    if (Q < 0) return fail(SFC_EINVAL, "Q must be >= 0");
+    if (Q == 0) return SFC_OK;
+    if (!targets || !target_masks || !subset || !coords)
+        return fail(SFC_EINVAL, "sfc_query_coords: null pointer");
+    return query_coords(ix, targets, target_masks, Q, subset, coords);
+}
+
+sfc_status sfc_query_stats(const sfc_index* ix, int64_t* n_fallback) {
+    clear_error();
+    if (!ix || !n_fallback) return fail(SFC_EINVAL, "null pointer");
+    *n_fallback = ix->last_fallback;
+    return SFC_OK;
+}
+
+}  // extern "C"

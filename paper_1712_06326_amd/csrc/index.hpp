@@ -1,0 +1,78 @@
+// The handle behind the opaque sfc_index and the host-side entry points of
+// the build and query paths.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace sfc {
+
+sfc_status dev_alloc(void** p, size_t bytes, const char* what);
+void dev_free(void* p);
+
+// Grow-only device scratch buffer owned by a handle.
+struct Scratch {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    sfc_status reserve(size_t bytes, const char* what);
+    ~Scratch();
+};
+
+sfc_options resolve_options(const sfc_options* in);
+
+}  // namespace sfc
+
+struct sfc_index {
+    sfc::Grid g{};
+    sfc_options opt{};
+    hipStream_t st = nullptr;
+    const float* vol = nullptr;      // borrowed
+    uint8_t* valid = nullptr;        // [nvox] 1 = dictionary centre
+    uint32_t* dict = nullptr;        // [n] ascending centre ids
+    int64_t n = 0;
+
+    // ---- SFC multi-index (Section II)
+    bool has_sfc = false;
+    int S = 0, D = 0, L = 0, b = 0, W64 = 0;
+    int64_t R = 0;
+    float vmin = 0.0f, qscale = 0.0f;
+    int64_t nsub = 0;
+    uint8_t* xq = nullptr;           // [nvox*C] byte codes
+    int64_t* sum = nullptr;          // [P] subsample sums
+    int32_t* npix = nullptr;         // [S]
+    int32_t* pix = nullptr;          // [S][Kd]
+    int32_t* elem_off = nullptr;     // [S+1] row offsets of the subsets' bases
+    int8_t* basis = nullptr;         // [sum m_s][D] int8, subset after subset
+    int64_t* lo = nullptr;           // [S][D]
+    int64_t* span = nullptr;         // [S]
+    uint64_t* keys = nullptr;        // [S][L][W64][n] sorted key words (SoA per word)
+    uint32_t* ids = nullptr;         // [S][L][n] sorted ids
+    std::vector<int32_t> h_npix, h_pix, h_elem_off;
+    std::vector<int8_t> h_basis;
+    std::vector<int64_t> h_lo, h_span;
+    void* proj_w = nullptr;          // bf16 projection weights [S*D][Pp] (see k_build)
+    int Pp = 0;                      // padded element count of the projection GEMM
+
+    // ---- per-call scratch
+    sfc::Scratch rowmask, best, qtmp, cand, rp_a, rp_b;
+    int64_t last_fallback = 0;
+
+    ~sfc_index();
+};
+
+namespace sfc {
+
+sfc_status check_sfc_args(const sfc_geometry* g, int K, int D, int L, const sfc_options& o);
+sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int8_t* bases_host);
+void release_sfc(sfc_index* ix);
+sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
+                            uint64_t* best_dev);
+sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
+                               sfc_mode mode, int64_t* best_id, float* best_cost);
+sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
+                       int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
+sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
+                        int32_t* subset, double* coords);
+
+}  // namespace sfc

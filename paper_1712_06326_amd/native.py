@@ -1,0 +1,300 @@
+"""Thin Python binding of libsfcinpaint.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module only turns torch
+tensors into device pointers and sizes and checks status codes. PyTorch is
+used for device memory and streams. If the library is missing this module
+raises at import time: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfcinpaint.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_1712_06326_amd/build.py` first")
+
+_L = C.CDLL(LIB_PATH)
+
+SFC_OK, SFC_EINVAL, SFC_ENOMEM, SFC_EDEVICE, SFC_EEMPTY, SFC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+MODES = {"fp32": 0, "bf16": 1, "fp8": 2, "index": 3}
+CURVES = {"morton": 0, "hilbert": 1}
+ORDERS = {"criminisi": 0, "raster": 1}
+
+
+class Geometry(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("channels", C.c_int32), ("shape", C.c_int64 * 3)]
+
+
+class Options(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("key_bits", C.c_int32), ("window", C.c_int32),
+                ("curve", C.c_int32), ("rescore_top", C.c_int32), ("certify", C.c_int32),
+                ("query_block", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_sub", C.c_int64), ("ndim", C.c_int32),
+                ("channels", C.c_int32), ("K", C.c_int32), ("P", C.c_int32),
+                ("has_sfc", C.c_int32), ("n_subsets", C.c_int32), ("reduced_dim", C.c_int32),
+                ("n_curves", C.c_int32), ("key_bits", C.c_int32), ("key_words", C.c_int32),
+                ("window", C.c_int32), ("curve", C.c_int32), ("vmin", C.c_float),
+                ("qscale", C.c_float)]
+
+
+class FillLog(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("len", C.c_int64), ("centre_host", C.c_void_p),
+                ("source_host", C.c_void_p), ("cost_host", C.c_void_p)]
+
+
+P = C.c_void_p
+I32, I64 = C.c_int32, C.c_int64
+ST = C.c_int
+_SIG = {
+    "sfc_abi_version": (I32, []),
+    "sfc_last_error": (C.c_char_p, []),
+    "sfc_options_default": (None, [C.POINTER(Options)]),
+    "sfc_fill_front": (ST, [P, C.POINTER(Geometry), P, I64, C.POINTER(C.c_int64), P]),
+    "sfc_extract_targets": (ST, [P, P, C.POINTER(Geometry), I32, P, I64, P, P, P]),
+    "sfc_dictionary_build": (ST, [P, P, C.POINTER(Geometry), I32, C.POINTER(Options),
+                                  C.POINTER(P)]),
+    "sfc_index_build": (ST, [P, P, C.POINTER(Geometry), I32, I32, I32, C.POINTER(Options),
+                             C.POINTER(P)]),
+    "sfc_index_build_with_basis": (ST, [P, P, C.POINTER(Geometry), I32, I32, I32,
+                                        C.POINTER(Options), P, C.POINTER(P)]),
+    "sfc_query": (ST, [P, P, P, I64, C.c_int, P, P]),
+    "sfc_query_candidates": (ST, [P, P, P, I64, P, P]),
+    "sfc_query_coords": (ST, [P, P, P, I64, P, P]),
+    "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
+    "sfc_index_info_get": (ST, [P, C.POINTER(IndexInfo)]),
+    "sfc_index_dictionary": (ST, [P, P]),
+    "sfc_index_quantized": (ST, [P, P]),
+    "sfc_index_get_basis": (ST, [P, I32, P, C.POINTER(C.c_int32)]),
+    "sfc_index_get_params": (ST, [P, I32, P, C.POINTER(C.c_int64)]),
+    "sfc_index_projection": (ST, [P, I32, P]),
+    "sfc_index_export": (ST, [P, I32, I32, P, P]),
+    "sfc_index_free": (None, [P]),
+    "sfc_inpaint": (ST, [P, P, C.POINTER(Geometry), I32, C.c_int, C.c_int, P,
+                         C.POINTER(Options), C.POINTER(C.c_int64), C.POINTER(FillLog)]),
+}
+for _name, (_res, _args) in _SIG.items():
+    _f = getattr(_L, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class SfcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sfc status {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != SFC_OK:
+        raise SfcError(code, _L.sfc_last_error().decode())
+
+
+def lib():
+    return _L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def geometry(mask: torch.Tensor, channels: int) -> Geometry:
+    g = Geometry()
+    g.ndim = mask.dim()
+    g.channels = channels
+    for i, s in enumerate(mask.shape):
+        g.shape[i] = s
+    return g
+
+
+def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
+            query_block=0) -> Options:
+    o = Options()
+    _L.sfc_options_default(C.byref(o))
+    o.key_bits = key_bits
+    o.window = window
+    o.curve = CURVES[curve] if isinstance(curve, str) else int(curve)
+    o.rescore_top = rescore_top
+    o.certify = 1 if certify else 0
+    o.query_block = query_block
+    o.stream = _stream()
+    return o
+
+
+def fill_front(mask: torch.Tensor) -> torch.Tensor:
+    g = geometry(mask, 1)
+    n = C.c_int64()
+    _check(_L.sfc_fill_front(_ptr(mask), C.byref(g), None, 0, C.byref(n), _stream()))
+    out = torch.empty(max(n.value, 1), dtype=torch.int64, device=mask.device)
+    _check(_L.sfc_fill_front(_ptr(mask), C.byref(g), _ptr(out), n.value, C.byref(n), _stream()))
+    return out[:n.value]
+
+
+def extract_targets(volume: torch.Tensor, mask: torch.Tensor, K: int, centres: torch.Tensor):
+    Cc = volume.shape[-1]
+    Q = centres.numel()
+    Kd = K ** mask.dim()
+    t = torch.empty((Q, Kd, Cc), dtype=torch.float32, device=volume.device)
+    m = torch.empty((Q, Kd), dtype=torch.uint8, device=volume.device)
+    g = geometry(mask, Cc)
+    _check(_L.sfc_extract_targets(_ptr(volume), _ptr(mask), C.byref(g), K, _ptr(centres), Q,
+                                  _ptr(t), _ptr(m), _stream()))
+    return t, m
+
+
+class Index:
+    """Owner of an sfc_index handle. The volume tensor is kept referenced for
+    the handle's lifetime (the library reads dictionary patches in place)."""
+
+    def __init__(self, volume: torch.Tensor, mask: torch.Tensor, K: int, reduced_dim: int = 0,
+                 n_curves: int = 0, bases: list | None = None, **opts):
+        self.volume, self.mask, self.K = volume, mask, K
+        self._opts = options(**opts)
+        g = geometry(mask, volume.shape[-1])
+        h = C.c_void_p()
+        if reduced_dim <= 0:
+            _check(_L.sfc_dictionary_build(_ptr(volume), _ptr(mask), C.byref(g), K,
+                                           C.byref(self._opts), C.byref(h)))
+        elif bases is None:
+            _check(_L.sfc_index_build(_ptr(volume), _ptr(mask), C.byref(g), K, reduced_dim,
+                                      n_curves, C.byref(self._opts), C.byref(h)))
+        else:
+            import numpy as np
+            flat = np.ascontiguousarray(np.concatenate([np.asarray(b, np.int8).ravel()
+                                                        for b in bases]))
+            _check(_L.sfc_index_build_with_basis(
+                _ptr(volume), _ptr(mask), C.byref(g), K, reduced_dim, n_curves,
+                C.byref(self._opts), flat.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _L.sfc_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> IndexInfo:
+        i = IndexInfo()
+        _check(_L.sfc_index_info_get(self._h, C.byref(i)))
+        return i
+
+    def dictionary(self) -> torch.Tensor:
+        out = torch.empty(self.info.n, dtype=torch.int64, device=self.volume.device)
+        _check(_L.sfc_index_dictionary(self._h, _ptr(out)))
+        return out
+
+    def query(self, t: torch.Tensor, m: torch.Tensor, mode: str = "fp32"):
+        Q = m.shape[0]
+        bi = torch.empty(Q, dtype=torch.int64, device=t.device)
+        bc = torch.empty(Q, dtype=torch.float32, device=t.device)
+        _check(_L.sfc_query(self._h, _ptr(t), _ptr(m), Q, MODES[mode], _ptr(bi), _ptr(bc)))
+        return bi, bc
+
+    def fallbacks(self) -> int:
+        n = C.c_int64()
+        _check(_L.sfc_query_stats(self._h, C.byref(n)))
+        return n.value
+
+    def candidates(self, t: torch.Tensor, m: torch.Tensor):
+        i = self.info
+        Q = m.shape[0]
+        cand = torch.empty((Q, i.n_curves * i.window), dtype=torch.int64, device=t.device)
+        nc = torch.empty(Q, dtype=torch.int32, device=t.device)
+        _check(_L.sfc_query_candidates(self._h, _ptr(t), _ptr(m), Q, _ptr(cand), _ptr(nc)))
+        return cand, nc
+
+    def coords(self, t: torch.Tensor, m: torch.Tensor):
+        i = self.info
+        Q = m.shape[0]
+        sub = torch.empty(Q, dtype=torch.int32, device=t.device)
+        y = torch.empty((Q, i.reduced_dim), dtype=torch.float64, device=t.device)
+        _check(_L.sfc_query_coords(self._h, _ptr(t), _ptr(m), Q, _ptr(sub), _ptr(y)))
+        return sub, y
+
+    def quantized(self) -> torch.Tensor:
+        out = torch.empty(self.volume.shape, dtype=torch.uint8, device=self.volume.device)
+        _check(_L.sfc_index_quantized(self._h, _ptr(out)))
+        return out
+
+    def basis(self, subset: int):
+        import numpy as np
+        i = self.info
+        buf = np.zeros((self.K ** self.mask.dim() * i.channels, i.reduced_dim), np.int8)
+        rows = C.c_int32()
+        _check(_L.sfc_index_get_basis(self._h, subset, buf.ctypes.data_as(C.c_void_p),
+                                      C.byref(rows)))
+        return buf[:rows.value].copy()
+
+    def params(self, subset: int):
+        import numpy as np
+        i = self.info
+        lo = np.zeros(i.reduced_dim, np.int64)
+        span = C.c_int64()
+        _check(_L.sfc_index_get_params(self._h, subset, lo.ctypes.data_as(C.c_void_p),
+                                       C.byref(span)))
+        return lo, span.value
+
+    def projection(self, subset: int) -> torch.Tensor:
+        i = self.info
+        y = torch.empty((i.n, i.reduced_dim), dtype=torch.int64, device=self.volume.device)
+        _check(_L.sfc_index_projection(self._h, subset, _ptr(y)))
+        return y
+
+    def export(self, subset: int, curve: int):
+        i = self.info
+        keys = torch.empty((i.n, i.key_words), dtype=torch.int64, device=self.volume.device)
+        ids = torch.empty(i.n, dtype=torch.int64, device=self.volume.device)
+        _check(_L.sfc_index_export(self._h, subset, curve, _ptr(keys), _ptr(ids)))
+        return keys, ids
+
+
+def inpaint(volume: torch.Tensor, mask: torch.Tensor, K: int, order="criminisi", mode="fp32",
+            index: Index | None = None, log_cap: int = 0, **opts):
+    """Fill in place; returns (iterations, log dict of numpy arrays)."""
+    import numpy as np
+    o = options(**opts)
+    g = geometry(mask, volume.shape[-1])
+    n = C.c_int64()
+    log = None
+    arrs = None
+    if log_cap > 0:
+        arrs = (np.zeros(log_cap, np.int64), np.zeros(log_cap, np.int64),
+                np.zeros(log_cap, np.float32))
+        log = FillLog()
+        log.cap = log_cap
+        log.centre_host = arrs[0].ctypes.data
+        log.source_host = arrs[1].ctypes.data
+        log.cost_host = arrs[2].ctypes.data
+    _check(_L.sfc_inpaint(_ptr(volume), _ptr(mask), C.byref(g), K, ORDERS[order], MODES[mode],
+                          index._h if index is not None else None, C.byref(o), C.byref(n),
+                          C.byref(log) if log is not None else None))
+    out = {}
+    if arrs is not None:
+        k = min(log.len, log_cap)
+        out = dict(centre=arrs[0][:k].copy(), source=arrs[1][:k].copy(), cost=arrs[2][:k].copy())
+    return n.value, out

@@ -1,0 +1,47 @@
+"""The C-ABI library loads and exports every function include/sfcinpaint.h
+declares (CPU only: no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfcinpaint.h")
+LIB = os.path.join(ROOT, "paper_1712_06326_amd", "libsfcinpaint.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("sfc_index_build", "sfc_query", "sfc_inpaint", "sfc_index_free",
+                 "sfc_last_error", "sfc_fill_front", "sfc_extract_targets"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_only_calls():
+    lib = ctypes.CDLL(LIB)
+    lib.sfc_abi_version.restype = ctypes.c_int32
+    assert lib.sfc_abi_version() == 1
+    lib.sfc_last_error.restype = ctypes.c_char_p
+    assert lib.sfc_last_error() == b""
+    # argument errors are reported before any device work
+    lib.sfc_index_build.restype = ctypes.c_int
+    out = ctypes.c_void_p()
+    rc = lib.sfc_index_build(None, None, None, 9, 8, 4, None, ctypes.byref(out))
+    assert rc == -1 and b"geometry" in lib.sfc_last_error()
+    lib.sfc_query.restype = ctypes.c_int
+    assert lib.sfc_query(None, None, None, 1, 0, None, None) == -1
