@@ -153,7 +153,7 @@ namespace sfc {
 sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                             uint64_t* best_dev) {
     const Grid& g = ix->g;
-    SFC_TRY(ix->rowmask.reserve((size_t)Q * g.rows * sizeof(uint32_t), "row masks"));
+    SFC_TRY(ix->rowmask.reserve((size_t)scan_qpad(Q) * g.rows * sizeof(uint32_t), "row masks"));
     uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
     SFC_TRY(launch_pack_rowmask(m, g, Q, rm, ix->st));
     SFC_TRY(launch_fill_u64(best_dev, Q, ~0ull, ix->st));

@@ -79,7 +79,7 @@ struct ScanArgs {
     const float* vol;
     const uint8_t* valid;
     const float* t;
-    const uint32_t* rowmask;   // [Q, rows] bit dx set when (row, dx) known
+    const uint32_t* rowmask;   // [rows, scan_qpad(Q)] bit dx set when (row, dx) is known
     int64_t Q;
     uint64_t* best;            // [Q], pre-filled with ~0
     int query_block;           // 0 = default
@@ -87,6 +87,7 @@ struct ScanArgs {
 sfc_status launch_pack_rowmask(const uint8_t* m, const Grid& g, int64_t Q, uint32_t* rowmask,
                                hipStream_t st);
 sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st);
+int64_t scan_qpad(int64_t Q);  // row-mask query stride
 sfc_status launch_unpack_best(const uint64_t* best, int64_t Q, int64_t* id, float* cost,
                               hipStream_t st);
 

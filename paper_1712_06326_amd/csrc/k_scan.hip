@@ -20,6 +20,7 @@ namespace sfc {
 namespace {
 
 constexpr int kLanes = 256;
+constexpr int kScanQB = 16;
 
 typedef const __attribute__((address_space(4))) float cfloat_as4;
 typedef const __attribute__((address_space(4))) uint32_t cu32_as4;
@@ -42,14 +43,11 @@ struct ScanParams {
     int64_t n_tiles;
     int64_t tiles_per_wg;
     int64_t q_per_wg;
+    int64_t qpad;            // row-mask stride (queries padded to the block size)
 };
 
-__device__ inline float wave_min(float x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
-    return x;
-}
-
+// Lane-level running best over the tiles of a workgroup: candidates of later
+// tiles have larger ids, so a strict comparison keeps the lowest id on ties.
 template <int ND, int K, int C, int QB>
 __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     constexpr int H = (K - 1) / 2;
@@ -59,7 +57,7 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     constexpr int TILE = ROWS * TW * C;
     extern __shared__ float smem[];
     float* tile = smem;
-    uint64_t* sbest = reinterpret_cast<uint64_t*>(smem + ((TILE + 1) & ~1));
+    uint32_t* sred = reinterpret_cast<uint32_t*>(smem + TILE);  // [4 waves][QB][2]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -67,52 +65,59 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     const int64_t q0 = (int64_t)blockIdx.y * p.q_per_wg;
     const int64_t q1 = min(p.Q, q0 + p.q_per_wg);
     if (q0 >= q1) return;
-    for (int64_t i = tid; i < q1 - q0; i += kLanes) sbest[i] = ~0ull;
-
     const int64_t tl0 = (int64_t)blockIdx.x * p.tiles_per_wg;
     const int64_t tl1 = min(p.n_tiles, tl0 + p.tiles_per_wg);
-    for (int64_t tl = tl0; tl < tl1; tl++) {
-        const int64_t line = tl / p.tiles_per_line;
-        const int64_t x0 = (tl - line * p.tiles_per_line) * kLanes;
-        int64_t base;
-        if (ND == 2) {
-            base = (line + H) * p.stride[0];
-        } else {
-            const int64_t iy = p.shape[1] - 2 * H;
-            const int64_t z = line / iy, y = line - z * iy;
-            base = (z + H) * p.stride[0] + (y + H) * p.stride[1];
-        }
-        __syncthreads();
-        for (int i = tid; i < TILE; i += kLanes) {
-            const int r = i / (TW * C);
-            const int rem = i - r * TW * C;
-            const int j = rem / C;
-            const int ch = rem - j * C;
-            const int64_t xv = x0 + j;
-            float val = 0.0f;
-            if (xv < p.shape[ND - 1]) {
-                int64_t roff;
-                if (ND == 2) roff = (int64_t)(r - H) * p.stride[0];
-                else roff = (int64_t)(r / K - H) * p.stride[0] + (int64_t)(r % K - H) * p.stride[1];
-                val = p.vol[(base + roff + xv) * C + ch];
-            }
-            tile[i] = val;
-        }
-        __syncthreads();
-        const int64_t xi = x0 + tid;
-        const bool cvalid = (xi < p.line_len) && p.valid[base + xi + H];
-        const int64_t id_wave0 = base + x0 + H + wave * 64;
 
-        for (int64_t qb = q0; qb < q1; qb += QB) {
+    for (int64_t qb = q0; qb < q1; qb += QB) {
+        uint32_t bcost[QB], bid[QB];
+#pragma unroll
+        for (int qi = 0; qi < QB; qi++) {
+            bcost[qi] = 0xffffffffu;
+            bid[qi] = 0xffffffffu;
+        }
+        for (int64_t tl = tl0; tl < tl1; tl++) {
+            const int64_t line = tl / p.tiles_per_line;
+            const int64_t x0 = (tl - line * p.tiles_per_line) * kLanes;
+            int64_t base;
+            if (ND == 2) {
+                base = (line + H) * p.stride[0];
+            } else {
+                const int64_t iy = p.shape[1] - 2 * H;
+                const int64_t z = line / iy, y = line - z * iy;
+                base = (z + H) * p.stride[0] + (y + H) * p.stride[1];
+            }
+            __syncthreads();
+            for (int i = tid; i < TILE; i += kLanes) {
+                const int r = i / (TW * C);
+                const int rem = i - r * TW * C;
+                const int j = rem / C;
+                const int ch = rem - j * C;
+                const int64_t xv = x0 + j;
+                float val = 0.0f;
+                if (xv < p.shape[ND - 1]) {
+                    int64_t roff;
+                    if (ND == 2) roff = (int64_t)(r - H) * p.stride[0];
+                    else roff = (int64_t)(r / K - H) * p.stride[0] + (int64_t)(r % K - H) * p.stride[1];
+                    val = p.vol[(base + roff + xv) * C + ch];
+                }
+                tile[i] = val;
+            }
+            __syncthreads();
+            const int64_t xi = x0 + tid;
+            const bool cvalid = (xi < p.line_len) && p.valid[base + xi + H];
+            const uint32_t cid = (uint32_t)(base + xi + H);
+
             float acc[QB];
 #pragma unroll
             for (int qi = 0; qi < QB; qi++) acc[qi] = 0.0f;
             for (int r = 0; r < ROWS; r++) {
+                // masks of the QB queries for row r are contiguous (row-major [rows][Qpad])
+                const uint32_t* mrb = p.rowmask + (int64_t)r * p.qpad + qb;
                 uint32_t mrow[QB];
                 uint32_t orm = 0;
 #pragma unroll
                 for (int qi = 0; qi < QB; qi++) {
-                    mrow[qi] = (qb + qi < q1) ? ldu(p.rowmask + (qb + qi) * ROWS + r) : 0u;
+                    mrow[qi] = ldu(mrb + qi);
                     orm |= mrow[qi];
                 }
                 if (orm == 0) continue;
@@ -120,56 +125,79 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
                 const float* trow = tile + (r * TW + tid) * C;
 #pragma unroll
                 for (int i = 0; i < RW; i++) v[i] = trow[i];
+                const float* tb = p.t + (qb * ROWS + r) * RW;
 #pragma unroll
                 for (int qi = 0; qi < QB; qi++) {
                     const uint32_t mr = mrow[qi];
                     if (mr == 0) continue;
-                    const float* tq = p.t + ((qb + qi) * ROWS + r) * RW;
+                    float tr[RW];
+#pragma unroll
+                    for (int i = 0; i < RW; i++) tr[i] = ldu(tb + qi * ROWS * RW + i);
 #pragma unroll
                     for (int dx = 0; dx < K; dx++) {
                         if (mr & (1u << dx)) {
 #pragma unroll
                             for (int ch = 0; ch < C; ch++) {
-                                const float d = ldu(tq + dx * C + ch) - v[dx * C + ch];
+                                const float d = tr[dx * C + ch] - v[dx * C + ch];
                                 acc[qi] = __builtin_fmaf(d, d, acc[qi]);
                             }
                         }
                     }
                 }
             }
+            if (cvalid) {
 #pragma unroll
-            for (int qi = 0; qi < QB; qi++) {
-                if (qb + qi >= q1) break;
-                const float c = cvalid ? acc[qi] : __builtin_inff();
-                const float m = wave_min(c);
-                if (m != __builtin_inff()) {
-                    const uint64_t bal = __ballot(c == m);
-                    const int first = __ffsll((unsigned long long)bal) - 1;
-                    if (lane == 0) {
-                        const uint64_t id = (uint64_t)(id_wave0 + first);
-                        const uint64_t packed = ((uint64_t)__float_as_uint(m) << 32) | id;
-                        atomicMin((unsigned long long*)&sbest[qb + qi - q0],
-                                  (unsigned long long)packed);
+                for (int qi = 0; qi < QB; qi++) {
+                    const uint32_t cb = __float_as_uint(acc[qi]);
+                    if (cb < bcost[qi]) {
+                        bcost[qi] = cb;
+                        bid[qi] = cid;
                     }
                 }
             }
         }
+        // (cost, id) minimum over the workgroup, then one global atomic per query
+#pragma unroll
+        for (int qi = 0; qi < QB; qi++) {
+            uint32_t c = bcost[qi];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) c = min(c, (uint32_t)__shfl_xor((int)c, off, 64));
+            const uint64_t bal = __ballot(bcost[qi] == c);
+            const int first = __ffsll((unsigned long long)bal) - 1;
+            const uint32_t id = (uint32_t)__shfl((int)bid[qi], first, 64);
+            if (lane == 0) {
+                sred[(wave * QB + qi) * 2] = c;
+                sred[(wave * QB + qi) * 2 + 1] = id;
+            }
+        }
+        __syncthreads();
+        if (tid < QB && qb + tid < q1) {
+            uint64_t best = ~0ull;
+            for (int w = 0; w < kLanes / 64; w++) {
+                const uint32_t c = sred[(w * QB + tid) * 2], id = sred[(w * QB + tid) * 2 + 1];
+                if (c != 0xffffffffu) {
+                    const uint64_t pk = ((uint64_t)c << 32) | id;
+                    if (pk < best) best = pk;
+                }
+            }
+            if (best != ~0ull)
+                atomicMin((unsigned long long*)&p.best[qb + tid], (unsigned long long)best);
+        }
     }
-    __syncthreads();
-    for (int64_t i = tid; i < q1 - q0; i += kLanes)
-        if (sbest[i] != ~0ull)
-            atomicMin((unsigned long long*)&p.best[q0 + i], (unsigned long long)sbest[i]);
 }
 
-// rowmask[q][r] bit dx = target_masks[q][r*K + dx]
-__global__ void pack_rowmask_kernel(const uint8_t* __restrict__ m, int64_t Q, int rows, int K,
-                                    uint32_t* __restrict__ rowmask) {
+// rowmask[r][q] bit dx = target_masks[q][r*K + dx]; queries Q..qpad-1 get 0.
+__global__ void pack_rowmask_kernel(const uint8_t* __restrict__ m, int64_t Q, int64_t qpad,
+                                    int rows, int K, uint32_t* __restrict__ rowmask) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Q * rows) return;
-    const uint8_t* src = m + i * K;
+    if (i >= qpad * rows) return;
+    const int64_t r = i / qpad, q = i - r * qpad;
     uint32_t bits = 0;
-    for (int dx = 0; dx < K; dx++)
-        if (src[dx]) bits |= 1u << dx;
+    if (q < Q) {
+        const uint8_t* src = m + (q * rows + r) * K;
+        for (int dx = 0; dx < K; dx++)
+            if (src[dx]) bits |= 1u << dx;
+    }
     rowmask[i] = bits;
 }
 
@@ -191,7 +219,7 @@ using ScanFn = void (*)(ScanParams);
 
 template <int ND, int K, int C>
 constexpr int scan_qb() {
-    return (K * C >= 27) ? 16 : 16;
+    return kScanQB;
 }
 
 template <int ND, int K, int C>
@@ -229,10 +257,14 @@ bool scan_supported(int nd, int K, int C) {
     return false;
 }
 
+int64_t scan_qpad(int64_t Q) { return ((Q + kScanQB - 1) / kScanQB) * kScanQB; }
+
 sfc_status launch_pack_rowmask(const uint8_t* m, const Grid& g, int64_t Q, uint32_t* rowmask,
                                hipStream_t st) {
     if (Q == 0) return SFC_OK;
-    pack_rowmask_kernel<<<blocks_for(Q * g.rows), 256, 0, st>>>(m, Q, g.rows, g.K, rowmask);
+    const int64_t qpad = scan_qpad(Q);
+    pack_rowmask_kernel<<<blocks_for(qpad * g.rows), 256, 0, st>>>(m, Q, qpad, g.rows, g.K,
+                                                                   rowmask);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFC_OK : check_hip(e, "pack_rowmask_kernel");
 }
@@ -270,10 +302,11 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     p.tiles_per_line = (p.line_len + kLanes - 1) / kLanes;
     p.n_tiles = n_lines * p.tiles_per_line;
     // queries per workgroup (LDS holds one 8-byte best per query)
-    int64_t qpw = a.query_block > 0 ? a.query_block : 2048;
+    int64_t qpw = a.query_block > 0 ? a.query_block : 1024;
     qpw = ((qpw + ent->qb - 1) / ent->qb) * ent->qb;
     if (qpw > a.Q) qpw = ((a.Q + ent->qb - 1) / ent->qb) * ent->qb;
     p.q_per_wg = qpw;
+    p.qpad = scan_qpad(a.Q);
     const int64_t qsplit = (a.Q + qpw - 1) / qpw;
     int64_t tpw = (p.n_tiles * qsplit + 2047) / 2048;
     if (tpw < 1) tpw = 1;
@@ -281,7 +314,7 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     const int64_t chunks = (p.n_tiles + tpw - 1) / tpw;
     const int rows = g.rows;
     const size_t tile_floats = (size_t)rows * (kLanes + g.K - 1) * g.C;
-    const size_t lds = ((tile_floats + 1) & ~size_t(1)) * sizeof(float) + (size_t)qpw * 8;
+    const size_t lds = tile_floats * sizeof(float) + (size_t)(kLanes / 64) * ent->qb * 8;
     if (lds > 160 * 1024)
         return fail(SFC_EUNSUPPORTED, "float32 scan: LDS tile too large");
     if (qsplit > 65535) return fail(SFC_EUNSUPPORTED, "float32 scan: too many queries");
