@@ -79,6 +79,7 @@ def _declare(L):
         "orc_keys": (None, [P, I64, I32, P, I64, I32, I32, I32, I32, P]),
         "orc_sort": (None, [P, P, I64, I32]),
         "orc_query": (None, [C.POINTER(OrcIndex), P, P, P, I64, P, P, P, P, P]),
+        "orc_query_point": (I32, [C.POINTER(OrcIndex), P, P, P]),
         "orc_inpaint": (I64, [P, P, I32, P, I32, I32, I32, I32, P, I64,
                               C.POINTER(OrcIndex), I64, P, P, P]),
     }
@@ -346,6 +347,19 @@ class Index:
             st.keys, st.ids = _p(self.keys), _p(self.ids)
             self._struct = st
         return self._struct
+
+    def query_point(self, t, m):
+        """Subset choice and real principal coordinates of each query."""
+        t, m = _c(t, np.float32), _c(m, np.uint8)
+        Q = m.shape[0]
+        sub = np.empty(Q, dtype=np.int32)
+        ys = np.empty((Q, self.D), dtype=np.float64)
+        buf = np.empty(64, dtype=np.float64)
+        st = C.byref(self.struct())
+        for q in range(Q):
+            sub[q] = lib().orc_query_point(st, _p(t[q]), _p(m[q]), _p(buf))
+            ys[q] = buf[:self.D]
+        return sub, ys
 
     def query(self, volume, t, m):
         """Returns (best_id, best_cost, candidates [Q, L*W] padded -1,

@@ -1,0 +1,36 @@
+// Kernels of the index build (quantisation, covariance, eigendecomposition,
+// basis, projection, keys) and of the radix sort.
+#pragma once
+
+#include "common.hpp"
+
+namespace sfc {
+
+// ---- byte quantisation (vmin/vmax over known voxels, FP32 scale)
+// params: float[2] = {vmin, scale} on the device
+sfc_status launch_quantize(const float* vol, const uint8_t* mask, const Grid& g, uint8_t* xq,
+                           float* params, uint32_t* tmp2, hipStream_t st);
+
+// ---- covariance sums over the strided subsample of dictionary ranks
+// elem_off[e] = (voxel offset of pixel e/C) * C + e%C relative to centre*C
+// Xt: [P][nsp4] u32, 4 samples per word; nsp4 = ceil(nsub/4)
+sfc_status launch_gather_samples(const uint8_t* xq, const uint32_t* dict, int64_t stride,
+                                 int64_t nsub, const int32_t* elem_off, int P, int C,
+                                 uint32_t* Xt, int64_t nsp4, hipStream_t st);
+// sum[e] (u64) and gram[e][f] (u64, full P x P) accumulated; both pre-zeroed
+sfc_status launch_gram(const uint32_t* Xt, int P, int64_t nsp4, uint64_t* sum, uint64_t* gram,
+                       hipStream_t st);
+
+// ---- per-subset covariance matrix, Jacobi eigensolver and int8 basis
+// A: [S][mmax*mmax] doubles; elems: [S][mmax] element ids; m: [S]
+sfc_status launch_cov_matrix(const uint64_t* sum, const uint64_t* gram, int64_t nsub, int P,
+                             const int32_t* elems, const int32_t* m, int S, int mmax, double* A,
+                             hipStream_t st);
+// Eigenvectors into V, eigenvalues on A's diagonal; sweeps[S] (int32)
+sfc_status launch_jacobi(double* A, double* V, double* B, const int32_t* m, int S, int mmax,
+                         int32_t* sweeps, hipStream_t st);
+// int8 basis [S][mmax][D] (row-major per subset) from A/V
+sfc_status launch_basis(const double* A, const double* V, const int32_t* m, int S, int mmax,
+                        int D, int8_t* basis, hipStream_t st);
+
+}  // namespace sfc

@@ -34,25 +34,29 @@ struct sfc_index {
 
     // ---- SFC multi-index (Section II)
     bool has_sfc = false;
-    int S = 0, D = 0, L = 0, b = 0, W64 = 0;
+    int S = 0, D = 0, L = 0, b = 0, W64 = 0, mmax = 0;
     int64_t R = 0;
     float vmin = 0.0f, qscale = 0.0f;
     int64_t nsub = 0;
     uint8_t* xq = nullptr;           // [nvox*C] byte codes
-    int64_t* sum = nullptr;          // [P] subsample sums
-    int32_t* npix = nullptr;         // [S]
-    int32_t* pix = nullptr;          // [S][Kd]
-    int32_t* elem_off = nullptr;     // [S+1] row offsets of the subsets' bases
-    int8_t* basis = nullptr;         // [sum m_s][D] int8, subset after subset
+    float* qparams = nullptr;        // device {vmin, scale}
+    int64_t* sum = nullptr;          // [P] subsample sums (stored as u64)
+    int32_t* npix = nullptr;         // [S] pixels per subset
+    int32_t* pix = nullptr;          // [S][Kd] pixel offsets, ascending
+    int32_t* elems = nullptr;        // [S][mmax] element ids
+    int32_t* msz = nullptr;          // [S] element counts
+    int32_t* elem_off = nullptr;     // [Pp] element offset relative to centre*C
+    int8_t* basis = nullptr;         // [S][mmax][D] int8
+    int64_t* wtw = nullptr;          // [S][D][D] W^T W
     int64_t* lo = nullptr;           // [S][D]
     int64_t* span = nullptr;         // [S]
-    uint64_t* keys = nullptr;        // [S][L][W64][n] sorted key words (SoA per word)
+    uint64_t* keys = nullptr;        // [S][L][W64][n] sorted key words (one array per word)
     uint32_t* ids = nullptr;         // [S][L][n] sorted ids
-    std::vector<int32_t> h_npix, h_pix, h_elem_off;
+    std::vector<int32_t> h_npix, h_pix;
     std::vector<int8_t> h_basis;
     std::vector<int64_t> h_lo, h_span;
-    void* proj_w = nullptr;          // bf16 projection weights [S*D][Pp] (see k_build)
-    int Pp = 0;                      // padded element count of the projection GEMM
+    void* proj_w = nullptr;          // bf16 projection weights [tiles*32][Pp]
+    int Pp = 0;                      // element count padded to 16
 
     // ---- per-call scratch
     sfc::Scratch rowmask, best, qtmp, cand, rp_a, rp_b;

@@ -1,0 +1,39 @@
+// Arguments of the index-query kernels (Fig. 1 b-d).
+#pragma once
+
+#include "common.hpp"
+
+namespace sfc {
+
+struct QueryIndexView {
+    int nd, K, C, Kd, rows, h;
+    int64_t shape[kMaxDims], stride[kMaxDims];
+    int S, D, L, b, curve, W64, window, mmax;
+    int64_t R, n, nsub;
+    const float* qparams;      // device {vmin, scale}
+    const int32_t* npix;       // [S]
+    const int32_t* pix;        // [S][Kd]
+    const int8_t* basis;       // [S][mmax][D]
+    const int64_t* wtw;        // [S][D][D] = W^T W (exact)
+    const uint64_t* sum;       // [P] subsample sums
+    const int64_t* lo;         // [S][D]
+    const int64_t* span;       // [S]
+    const uint64_t* keys;      // [S][L][W64][n]
+    const uint32_t* ids;       // [S][L][n]
+};
+
+// subset, real coordinates [Q][D] and keys [Q][L][W64] of each query
+sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const uint8_t* m,
+                                 int64_t Q, int32_t* qsub, double* qcoords, uint64_t* qkeys,
+                                 hipStream_t st);
+// window start per (query, curve): wstart [Q][L]
+sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub,
+                               const uint64_t* qkeys, int64_t Q, int64_t* wstart, hipStream_t st);
+// candidates = union of windows (sorted unique); best (cost, id) over them.
+// best_id/best_cost or cand/ncand may be null.
+sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const float* t,
+                                const uint32_t* rowmask, int64_t qpad, const int32_t* qsub,
+                                const int64_t* wstart, int64_t Q, int64_t* best_id,
+                                float* best_cost, int64_t* cand, int32_t* ncand, hipStream_t st);
+
+}  // namespace sfc

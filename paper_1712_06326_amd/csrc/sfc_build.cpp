@@ -1,0 +1,515 @@
+// Host orchestration of the SFC multi-index: build (Sections II, II.A-C) and
+// query (Fig. 1 b-d). All arithmetic runs in the kernels; the host derives
+// the static geometry tables (pixel subsets, element offsets), sizes the
+// buffers and plans the sort passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "build.hpp"
+#include "index.hpp"
+#include "proj.hpp"
+#include "query.hpp"
+
+namespace sfc {
+
+bool scan_supported(int nd, int K, int C);
+bool rescore_supported(int nd, int K, int C);
+
+namespace {
+
+// Pixel subsets (Fig. 2): anchors at the corners and edge midpoints of the
+// patch, a in {0,1,2}^nd without the centre, lexicographic with axis 0
+// slowest; each takes every pixel whose squared distance to the anchor is at
+// most the ceil(0.6*K^nd)-th smallest one (ties at the cut included).
+void make_subsets(int nd, int K, std::vector<int32_t>& npix, std::vector<int32_t>& pix) {
+    int Kd = 1;
+    for (int i = 0; i < nd; i++) Kd *= K;
+    const int h = (K - 1) / 2;
+    const int need = (6 * Kd + 9) / 10;
+    int n3 = 1;
+    for (int i = 0; i < nd; i++) n3 *= 3;
+    npix.clear();
+    pix.clear();
+    std::vector<int> d2(Kd), sorted(Kd);
+    for (int a = 0; a < n3; a++) {
+        int anchor[kMaxDims];
+        bool centre = true;
+        for (int i = nd - 1, r = a; i >= 0; i--, r /= 3) {
+            anchor[i] = (r % 3) * h;
+            if (r % 3 != 1) centre = false;
+        }
+        if (centre) continue;
+        for (int rho = 0; rho < Kd; rho++) {
+            int acc = 0;
+            for (int i = nd - 1, r = rho; i >= 0; i--, r /= K) {
+                const int dd = r % K - anchor[i];
+                acc += dd * dd;
+            }
+            d2[rho] = acc;
+        }
+        sorted = d2;
+        std::nth_element(sorted.begin(), sorted.begin() + (need - 1), sorted.end());
+        const int cut = sorted[need - 1];
+        int cnt = 0;
+        const size_t base = pix.size();
+        pix.resize(base + Kd, -1);
+        for (int rho = 0; rho < Kd; rho++)
+            if (d2[rho] <= cut) pix[base + cnt++] = rho;
+        npix.push_back(cnt);
+    }
+}
+
+template <typename T>
+sfc_status upload(T** dst, const std::vector<T>& src, const char* what, hipStream_t st) {
+    SFC_TRY(dev_alloc((void**)dst, src.size() * sizeof(T), what));
+    SFC_HIP(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return SFC_OK;
+}
+
+struct Temp {
+    std::vector<void*> ptrs;
+    sfc_status alloc(void** p, size_t bytes, const char* what) {
+        SFC_TRY(dev_alloc(p, bytes, what));
+        ptrs.push_back(*p);
+        return SFC_OK;
+    }
+    ~Temp() {
+        for (void* p : ptrs) dev_free(p);
+    }
+};
+
+__global__ void wtw_kernel(const int8_t* __restrict__ basis, const int32_t* __restrict__ msz,
+                           int S, int mmax, int D, int64_t* __restrict__ wtw) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * D * D) return;
+    const int s = i / (D * D), d = (i / D) % D, f = i % D;
+    const int8_t* w = basis + (int64_t)s * mmax * D;
+    int64_t acc = 0;
+    for (int r = 0; r < msz[s]; r++) acc += (int64_t)w[r * D + d] * w[r * D + f];
+    wtw[i] = acc;
+}
+
+__global__ void zero_bytes_kernel(uint8_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+sfc_status zero(void* p, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return SFC_OK;
+    zero_bytes_kernel<<<(unsigned)((bytes + 255) / 256), 256, 0, st>>>((uint8_t*)p, (int64_t)bytes);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFC_OK : check_hip(e, "zero_bytes_kernel");
+}
+
+__global__ void cols_i32_to_i64_kernel(const int32_t* __restrict__ y, int64_t n, int ystride,
+                                       int col0, int D, int64_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * D) return;
+    const int64_t r = i / D;
+    out[i] = y[r * ystride + col0 + (i - r * D)];
+}
+
+__global__ void export_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ ids,
+                              int64_t n, int W64, uint64_t* __restrict__ kout,
+                              int64_t* __restrict__ iout) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int w = 0; w < W64; w++) kout[i * W64 + w] = keys[(int64_t)w * n + i];
+    iout[i] = ids[i];
+}
+
+QueryIndexView view_of(const sfc_index* ix) {
+    QueryIndexView v{};
+    const Grid& g = ix->g;
+    v.nd = g.nd;
+    v.K = g.K;
+    v.C = g.C;
+    v.Kd = g.Kd;
+    v.rows = g.rows;
+    v.h = g.h;
+    for (int i = 0; i < kMaxDims; i++) {
+        v.shape[i] = g.shape[i];
+        v.stride[i] = g.stride[i];
+    }
+    v.S = ix->S;
+    v.D = ix->D;
+    v.L = ix->L;
+    v.b = ix->b;
+    v.curve = ix->opt.curve;
+    v.W64 = ix->W64;
+    v.window = ix->opt.window;
+    v.mmax = ix->mmax;
+    v.R = ix->R;
+    v.n = ix->n;
+    v.nsub = ix->nsub;
+    v.qparams = ix->qparams;
+    v.npix = ix->npix;
+    v.pix = ix->pix;
+    v.basis = ix->basis;
+    v.wtw = ix->wtw;
+    v.sum = reinterpret_cast<const uint64_t*>(ix->sum);
+    v.lo = ix->lo;
+    v.span = ix->span;
+    v.keys = ix->keys;
+    v.ids = ix->ids;
+    return v;
+}
+
+}  // namespace
+
+sfc_status check_sfc_args(const sfc_geometry* g, int K, int D, int L, const sfc_options& o) {
+    if (D < 1) return fail(SFC_EINVAL, "reduced_dim must be >= 1");
+    if (L < 1) return fail(SFC_EINVAL, "n_curves must be >= 1");
+    if (L > D + 1) return fail(SFC_EINVAL, "n_curves must be <= reduced_dim + 1 (shift headroom)");
+    if ((int64_t)D * o.key_bits > 256) return fail(SFC_EINVAL, "reduced_dim * key_bits above 256");
+    if (D > 12 && D != 16) return fail(SFC_EUNSUPPORTED, "reduced_dim must be 1..12 or 16");
+    if ((int64_t)L * o.window > 512) return fail(SFC_EUNSUPPORTED, "n_curves * window above 512");
+    if (!scan_supported(g->ndim, K, g->channels) || !rescore_supported(g->ndim, K, g->channels))
+        return fail(SFC_EUNSUPPORTED, "no kernels for this (ndim, K, channels)");
+    int Kd = 1;
+    for (int i = 0; i < g->ndim; i++) Kd *= K;
+    if (D > (6 * Kd + 9) / 10 * g->channels)
+        return fail(SFC_EINVAL, "reduced_dim larger than a subset's element count");
+    return SFC_OK;
+}
+
+void release_sfc(sfc_index* ix) {
+    void* ps[] = {ix->xq, ix->sum, ix->npix, ix->pix, ix->basis, ix->lo, ix->span, ix->keys,
+                  ix->ids, ix->proj_w, ix->wtw, ix->qparams, ix->elems, ix->msz, ix->elem_off};
+    for (void* p : ps) dev_free(p);
+    ix->xq = nullptr;
+    ix->keys = nullptr;
+    ix->ids = nullptr;
+}
+
+sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int8_t* bases_host) {
+    const Grid& g = ix->g;
+    hipStream_t st = ix->st;
+    const int C = g.C, P = g.Kd * C;
+    ix->D = D;
+    ix->L = L;
+    ix->b = ix->opt.key_bits;
+    ix->W64 = (D * ix->b + 63) / 64;
+    ix->R = (L > 1) ? (int64_t(1) << (ix->b - 1)) : (int64_t(1) << ix->b);
+
+    // static tables: subsets, their elements, element offsets
+    make_subsets(g.nd, g.K, ix->h_npix, ix->h_pix);
+    ix->S = (int)ix->h_npix.size();
+    const int S = ix->S;
+    int mmax = 0;
+    for (int s = 0; s < S; s++) mmax = std::max(mmax, ix->h_npix[s] * C);
+    if (mmax > kMaxSubsetElems)
+        return fail(SFC_EUNSUPPORTED, "a subset has more than 518 elements (exact bf16 bound)");
+    ix->mmax = mmax;
+    std::vector<int32_t> elems((size_t)S * mmax, 0), msz(S);
+    for (int s = 0; s < S; s++) {
+        msz[s] = ix->h_npix[s] * C;
+        for (int i = 0; i < ix->h_npix[s]; i++)
+            for (int ch = 0; ch < C; ch++) elems[(size_t)s * mmax + i * C + ch] = ix->h_pix[(size_t)s * g.Kd + i] * C + ch;
+    }
+    const int Pp = (P + 15) / 16 * 16;
+    ix->Pp = Pp;
+    std::vector<int32_t> eoff(Pp, 0);
+    for (int e = 0; e < P; e++) {
+        int rho = e / C;
+        int64_t off = 0;
+        for (int i = g.nd - 1; i >= 0; i--, rho /= g.K) off += (int64_t)(rho % g.K - g.h) * g.stride[i];
+        eoff[e] = (int32_t)(off * C + e % C);
+    }
+    SFC_TRY(upload(&ix->npix, ix->h_npix, "subset sizes", st));
+    SFC_TRY(upload(&ix->pix, ix->h_pix, "subset pixels", st));
+    SFC_TRY(upload(&ix->elems, elems, "subset elements", st));
+    SFC_TRY(upload(&ix->msz, msz, "subset element counts", st));
+    SFC_TRY(upload(&ix->elem_off, eoff, "element offsets", st));
+
+    // byte quantisation
+    SFC_TRY(dev_alloc((void**)&ix->xq, (size_t)g.nvox * C, "quantised volume"));
+    SFC_TRY(dev_alloc((void**)&ix->qparams, 4 * sizeof(float), "quantisation parameters"));
+    Temp tmp;
+    uint32_t* mm = nullptr;
+    SFC_TRY(tmp.alloc((void**)&mm, 2 * sizeof(uint32_t), "min/max"));
+    SFC_TRY(launch_quantize(ix->vol, mask, g, ix->xq, ix->qparams, mm, st));
+
+    // integer statistics over the strided subsample
+    const int64_t stride = (ix->n + (1 << 20) - 1) >> 20;
+    const int64_t st1 = stride < 1 ? 1 : stride;
+    ix->nsub = (ix->n + st1 - 1) / st1;
+    const int64_t nsp4 = (ix->nsub + 3) / 4;
+    uint32_t* Xt = nullptr;
+    uint64_t* gram = nullptr;
+    SFC_TRY(tmp.alloc((void**)&Xt, (size_t)P * nsp4 * 4, "sample matrix"));
+    SFC_TRY(dev_alloc((void**)&ix->sum, (size_t)P * 8, "sample sums"));
+    SFC_TRY(tmp.alloc((void**)&gram, (size_t)P * P * 8, "gram matrix"));
+    SFC_TRY(zero(gram, (size_t)P * P * 8, st));
+    SFC_TRY(launch_gather_samples(ix->xq, ix->dict, st1, ix->nsub, ix->elem_off, P, C, Xt, nsp4, st));
+    SFC_TRY(launch_gram(Xt, P, nsp4, reinterpret_cast<uint64_t*>(ix->sum), gram, st));
+
+    // basis per subset
+    SFC_TRY(dev_alloc((void**)&ix->basis, (size_t)S * mmax * D, "bases"));
+    if (!bases_host) {
+        double *A = nullptr, *V = nullptr, *B = nullptr;
+        int32_t* sweeps = nullptr;
+        const size_t mat = (size_t)S * mmax * mmax * sizeof(double);
+        SFC_TRY(tmp.alloc((void**)&A, mat, "covariance matrices"));
+        SFC_TRY(tmp.alloc((void**)&V, mat, "eigenvectors"));
+        SFC_TRY(tmp.alloc((void**)&B, mat, "rotation buffer"));
+        SFC_TRY(tmp.alloc((void**)&sweeps, S * sizeof(int32_t), "sweep counts"));
+        SFC_TRY(launch_cov_matrix(reinterpret_cast<uint64_t*>(ix->sum), gram, ix->nsub, P,
+                                  ix->elems, ix->msz, S, mmax, A, st));
+        SFC_TRY(launch_jacobi(A, V, B, ix->msz, S, mmax, sweeps, st));
+        SFC_TRY(launch_basis(A, V, ix->msz, S, mmax, D, ix->basis, st));
+    } else {
+        std::vector<int8_t> hb((size_t)S * mmax * D, 0);
+        size_t off = 0;
+        for (int s = 0; s < S; s++) {
+            std::memcpy(&hb[(size_t)s * mmax * D], bases_host + off, (size_t)msz[s] * D);
+            off += (size_t)msz[s] * D;
+        }
+        SFC_HIP(hipMemcpyAsync(ix->basis, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+        SFC_HIP(hipStreamSynchronize(st));
+    }
+    SFC_TRY(dev_alloc((void**)&ix->wtw, (size_t)S * D * D * 8, "basis gram"));
+    wtw_kernel<<<(S * D * D + 255) / 256, 256, 0, st>>>(ix->basis, ix->msz, S, mmax, D, ix->wtw);
+    SFC_HIP(hipGetLastError());
+
+    // projection weights (bf16) and the projection itself
+    const int ncols = S * D;
+    const int nt = proj_tiles(ncols);
+    if (nt > 16) return fail(SFC_EUNSUPPORTED, "subsets * reduced_dim above 512");
+    const size_t wbytes = (size_t)nt * 32 * Pp * 2;
+    SFC_TRY(dev_alloc(&ix->proj_w, wbytes, "projection weights"));
+    SFC_TRY(zero(ix->proj_w, wbytes, st));
+    SFC_TRY(launch_weights(ix->basis, ix->elems, ix->msz, S, mmax, D, Pp,
+                           static_cast<uint16_t*>(ix->proj_w), st));
+    int32_t *cmin = nullptr, *cmax = nullptr;
+    SFC_TRY(tmp.alloc((void**)&cmin, ncols * 4, "column minima"));
+    SFC_TRY(tmp.alloc((void**)&cmax, ncols * 4, "column maxima"));
+    SFC_TRY(launch_init_minmax(cmin, cmax, ncols, st));
+    const int64_t chunk = std::min<int64_t>(ix->n, int64_t(1) << 24);
+    int32_t* y = nullptr;
+    SFC_TRY(tmp.alloc((void**)&y, (size_t)chunk * ncols * 4, "principal coordinates"));
+    ProjArgs pa{};
+    pa.xq = ix->xq;
+    pa.dict = ix->dict;
+    pa.elem_off = ix->elem_off;
+    pa.P = P;
+    pa.Pp = Pp;
+    pa.C = C;
+    pa.Wt = static_cast<const uint16_t*>(ix->proj_w);
+    pa.ncols = ncols;
+    pa.ystride = ncols;
+    pa.colmin = cmin;
+    pa.colmax = cmax;
+    const bool one_chunk = chunk == ix->n;
+    for (int64_t r0 = 0; r0 < ix->n; r0 += chunk) {
+        pa.r0 = r0;
+        pa.cnt = std::min(chunk, ix->n - r0);
+        pa.y = one_chunk ? y : nullptr;
+        SFC_TRY(launch_projection(pa, st));
+    }
+    SFC_TRY(dev_alloc((void**)&ix->lo, (size_t)S * D * 8, "grid origin"));
+    SFC_TRY(dev_alloc((void**)&ix->span, (size_t)S * 8, "grid span"));
+    SFC_TRY(launch_span(cmin, cmax, S, D, ix->lo, ix->span, st));
+
+    // keys of every (subset, curve)
+    const size_t nkeys = (size_t)S * L * ix->W64 * ix->n;
+    SFC_TRY(dev_alloc((void**)&ix->keys, nkeys * 8, "curve keys"));
+    SFC_TRY(dev_alloc((void**)&ix->ids, (size_t)S * L * ix->n * 4, "curve ids"));
+    KeyArgs ka{};
+    ka.y = y;
+    ka.ystride = ncols;
+    ka.n = ix->n;
+    ka.dict = ix->dict;
+    ka.S = S;
+    ka.D = D;
+    ka.L = L;
+    ka.b = ix->b;
+    ka.curve = ix->opt.curve;
+    ka.W64 = ix->W64;
+    ka.R = ix->R;
+    ka.lo = ix->lo;
+    ka.span = ix->span;
+    ka.keys = ix->keys;
+    ka.ids = ix->ids;
+    for (int64_t r0 = 0; r0 < ix->n; r0 += chunk) {
+        pa.r0 = r0;
+        pa.cnt = std::min(chunk, ix->n - r0);
+        if (!one_chunk) {
+            pa.y = y;
+            pa.colmin = nullptr;
+            pa.colmax = nullptr;
+            SFC_TRY(launch_projection(pa, st));
+        }
+        ka.r0 = r0;
+        ka.cnt = pa.cnt;
+        SFC_TRY(launch_keys(ka, st));
+    }
+
+    // sort every (subset, curve) by (key, id)
+    uint64_t* varying = nullptr;
+    SFC_TRY(tmp.alloc((void**)&varying, (size_t)S * L * ix->W64 * 8, "varying bits"));
+    SFC_TRY(zero(varying, (size_t)S * L * ix->W64 * 8, st));
+    SFC_TRY(launch_varying_bits(ix->keys, ix->n, ix->W64, S * L, varying, st));
+    std::vector<uint64_t> hv((size_t)S * L * ix->W64);
+    SFC_HIP(hipMemcpyAsync(hv.data(), varying, hv.size() * 8, hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    void* sscratch = nullptr;
+    SFC_TRY(tmp.alloc(&sscratch, sort_scratch_bytes(ix->n, ix->W64), "sort scratch"));
+    const int nbits = D * ix->b;
+    for (int a = 0; a < S * L; a++) {
+        SortPlan plan{};
+        for (int pb = 0; pb < nbits; pb += 8) {
+            const int w = ix->W64 - 1 - (pb >> 6);
+            const uint64_t bits = (hv[(size_t)a * ix->W64 + w] >> (pb & 63)) & 0xffull;
+            if (bits) plan.pass_bits[plan.n_passes++] = pb;
+        }
+        SFC_TRY(radix_sort(ix->keys + (size_t)a * ix->W64 * ix->n, ix->ids + (size_t)a * ix->n,
+                           ix->n, ix->W64, plan, sscratch, st));
+    }
+
+    // host copies of the small parameters
+    ix->h_basis.assign((size_t)S * mmax * D, 0);
+    ix->h_lo.assign((size_t)S * D, 0);
+    ix->h_span.assign(S, 0);
+    float qp[2];
+    SFC_HIP(hipMemcpyAsync(ix->h_basis.data(), ix->basis, ix->h_basis.size(), hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipMemcpyAsync(ix->h_lo.data(), ix->lo, ix->h_lo.size() * 8, hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipMemcpyAsync(ix->h_span.data(), ix->span, ix->h_span.size() * 8, hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipMemcpyAsync(qp, ix->qparams, sizeof(qp), hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    ix->vmin = qp[0];
+    ix->qscale = qp[1];
+    ix->has_sfc = true;
+    return SFC_OK;
+}
+
+sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int64_t* best_id,
+                       float* best_cost, int64_t* cand, int32_t* ncand) {
+    const Grid& g = ix->g;
+    hipStream_t st = ix->st;
+    const int64_t qpad = scan_qpad(Q);
+    SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
+    uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
+    SFC_TRY(launch_pack_rowmask(m, g, Q, rm, st));
+    const size_t need = (size_t)Q * (4 + 8 * ix->D + 8 * ix->L * ix->W64 + 8 * ix->L) + 256;
+    SFC_TRY(ix->qtmp.reserve(need, "query scratch"));
+    char* p = static_cast<char*>(ix->qtmp.ptr);
+    double* coords = reinterpret_cast<double*>(p);
+    p += (size_t)Q * 8 * ix->D;
+    uint64_t* qkeys = reinterpret_cast<uint64_t*>(p);
+    p += (size_t)Q * 8 * ix->L * ix->W64;
+    int64_t* wstart = reinterpret_cast<int64_t*>(p);
+    p += (size_t)Q * 8 * ix->L;
+    int32_t* qsub = reinterpret_cast<int32_t*>(p);
+    const QueryIndexView v = view_of(ix);
+    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, st));
+    SFC_TRY(launch_query_search(v, qsub, qkeys, Q, wstart, st));
+    return launch_query_rescore(v, ix->vol, t, rm, qpad, qsub, wstart, Q, best_id, best_cost, cand,
+                                ncand, st);
+}
+
+sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int32_t* subset,
+                        double* coords) {
+    const size_t need = (size_t)Q * 8 * ix->L * ix->W64 + 256;
+    SFC_TRY(ix->qtmp.reserve(need, "query scratch"));
+    uint64_t* qkeys = static_cast<uint64_t*>(ix->qtmp.ptr);
+    const QueryIndexView v = view_of(ix);
+    return launch_query_prologue(v, t, m, Q, subset, coords, qkeys, ix->st);
+}
+
+sfc_status query_brute_reduced(sfc_index*, const float*, const uint8_t*, int64_t, sfc_mode,
+                               int64_t*, float*) {
+    return fail(SFC_EUNSUPPORTED, "reduced-precision scan not built yet");
+}
+
+}  // namespace sfc
+
+using namespace sfc;
+
+extern "C" {
+
+sfc_status sfc_index_quantized(const sfc_index* ix, uint8_t* xq) {
+    clear_error();
+    if (!ix || !xq) return fail(SFC_EINVAL, "null pointer");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "no SFC index on this handle");
+    SFC_HIP(hipMemcpyAsync(xq, ix->xq, (size_t)ix->g.nvox * ix->g.C, hipMemcpyDeviceToDevice, ix->st));
+    return SFC_OK;
+}
+
+sfc_status sfc_index_get_basis(const sfc_index* ix, int32_t subset, int8_t* out, int32_t* rows) {
+    clear_error();
+    if (!ix || !out || !rows) return fail(SFC_EINVAL, "null pointer");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "no SFC index on this handle");
+    if (subset < 0 || subset >= ix->S) return fail(SFC_EINVAL, "subset out of range");
+    const int m = ix->h_npix[subset] * ix->g.C;
+    std::memcpy(out, &ix->h_basis[(size_t)subset * ix->mmax * ix->D], (size_t)m * ix->D);
+    *rows = m;
+    return SFC_OK;
+}
+
+sfc_status sfc_index_get_params(const sfc_index* ix, int32_t subset, int64_t* lo, int64_t* span) {
+    clear_error();
+    if (!ix || !lo || !span) return fail(SFC_EINVAL, "null pointer");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "no SFC index on this handle");
+    if (subset < 0 || subset >= ix->S) return fail(SFC_EINVAL, "subset out of range");
+    std::memcpy(lo, &ix->h_lo[(size_t)subset * ix->D], (size_t)ix->D * 8);
+    *span = ix->h_span[subset];
+    return SFC_OK;
+}
+
+sfc_status sfc_index_projection(const sfc_index* ix, int32_t subset, int64_t* y) {
+    clear_error();
+    if (!ix || !y) return fail(SFC_EINVAL, "null pointer");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "no SFC index on this handle");
+    if (subset < 0 || subset >= ix->S) return fail(SFC_EINVAL, "subset out of range");
+    const int ncols = ix->S * ix->D;
+    const int64_t chunk = std::min<int64_t>(ix->n, int64_t(1) << 22);
+    int32_t* buf = nullptr;
+    SFC_TRY(dev_alloc((void**)&buf, (size_t)chunk * ncols * 4, "projection export"));
+    ProjArgs pa{};
+    pa.xq = ix->xq;
+    pa.dict = ix->dict;
+    pa.elem_off = ix->elem_off;
+    pa.P = ix->g.Kd * ix->g.C;
+    pa.Pp = ix->Pp;
+    pa.C = ix->g.C;
+    pa.Wt = static_cast<const uint16_t*>(ix->proj_w);
+    pa.ncols = ncols;
+    pa.ystride = ncols;
+    pa.y = buf;
+    sfc_status s = SFC_OK;
+    for (int64_t r0 = 0; r0 < ix->n && s == SFC_OK; r0 += chunk) {
+        pa.r0 = r0;
+        pa.cnt = std::min(chunk, ix->n - r0);
+        s = launch_projection(pa, ix->st);
+        if (s == SFC_OK) {
+            cols_i32_to_i64_kernel<<<(unsigned)((pa.cnt * ix->D + 255) / 256), 256, 0, ix->st>>>(
+                buf, pa.cnt, ncols, subset * ix->D, ix->D, y + r0 * ix->D);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) s = check_hip(e, "cols_i32_to_i64_kernel");
+        }
+    }
+    hipError_t e = hipStreamSynchronize(ix->st);
+    dev_free(buf);
+    if (s == SFC_OK && e != hipSuccess) s = check_hip(e, "projection export");
+    return s;
+}
+
+sfc_status sfc_index_export(const sfc_index* ix, int32_t subset, int32_t curve, uint64_t* keys,
+                            int64_t* ids) {
+    clear_error();
+    if (!ix || !keys || !ids) return fail(SFC_EINVAL, "null pointer");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "no SFC index on this handle");
+    if (subset < 0 || subset >= ix->S || curve < 0 || curve >= ix->L)
+        return fail(SFC_EINVAL, "subset or curve out of range");
+    const int64_t a = (int64_t)subset * ix->L + curve;
+    export_kernel<<<(unsigned)((ix->n + 255) / 256), 256, 0, ix->st>>>(
+        ix->keys + a * ix->W64 * ix->n, ix->ids + a * ix->n, ix->n, ix->W64, keys, ids);
+    SFC_HIP(hipGetLastError());
+    return SFC_OK;
+}
+
+}  // extern "C"

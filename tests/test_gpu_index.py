@@ -1,0 +1,81 @@
+"""GPU parity of the SFC multi-index against the oracle, stage by stage:
+byte codes, bases, grid parameters, projections, sorted (key, id) arrays,
+query subsets and coordinates, candidate sets and answers (all bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_06326_amd import synth
+
+from gpu_util import dev, host, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(vol, mask, K, D, L, b, curve, W, queries=None, with_basis=False):
+    nat = need_gpu()
+    say(f"index {mask.shape}x{vol.shape[-1]} K={K} D={D} L={L} b={b} {curve} W={W}")
+    ox = oracle.Index(vol, mask, K, D, L, key_bits=b, curve=curve, window=W, keep_y=True)
+    vd, md = dev(vol), dev(mask)
+    kw = dict(reduced_dim=D, n_curves=L, key_bits=b, window=W, curve=curve)
+    ix = nat.Index(vd, md, K, bases=ox.bases if with_basis else None, **kw)
+    info = ix.info
+    assert info.n == ox.n and info.n_sub == ox.nsub and info.n_subsets == ox.S
+    assert np.array_equal(host(ix.quantized()), ox.xq)
+    assert np.float32(info.vmin) == ox.vmin and np.float32(info.qscale) == ox.qscale
+    for s in range(ox.S):
+        assert np.array_equal(ix.basis(s), ox.bases[s]), f"basis of subset {s}"
+    for s in range(ox.S):
+        lo, span = ix.params(s)
+        assert np.array_equal(lo, ox.lo[s]) and span == ox.span[s], f"grid of subset {s}"
+        assert np.array_equal(host(ix.projection(s)), ox.y[s]), f"projection of subset {s}"
+    for s in range(ox.S):
+        for j in range(L):
+            k, i = ix.export(s, j)
+            assert np.array_equal(host(k).view(np.uint64), ox.keys[s, j]), f"keys ({s},{j})"
+            assert np.array_equal(host(i), ox.ids[s, j]), f"ids ({s},{j})"
+    f = oracle.front(mask) if queries is None else queries
+    t, m = oracle.extract(vol, mask, K, f)
+    td, mdq = dev(t), dev(m)
+    sub, y = ix.coords(td, mdq)
+    so, yo = ox.query_point(t, m)
+    assert np.array_equal(host(sub), so)
+    assert np.array_equal(host(y).view(np.uint64), yo.view(np.uint64))
+    cand, nc = ix.candidates(td, mdq)
+    bo, co, cando, nco, _ = ox.query(vol, t, m)
+    assert np.array_equal(host(nc), nco) and np.array_equal(host(cand), cando)
+    bi, bc = ix.query(td, mdq, "index")
+    assert np.array_equal(host(bi), bo) and np.array_equal(host(bc).view(np.uint32), co.view(np.uint32))
+    return ix, ox
+
+
+@pytest.mark.parametrize("h,w,c,K,D,L,b,curve,W,seed", [
+    (40, 44, 1, 5, 4, 2, 8, "morton", 8, 1),
+    (48, 64, 3, 5, 6, 3, 12, "morton", 16, 2),
+    (50, 70, 3, 9, 8, 4, 21, "morton", 32, 3),
+    (45, 52, 2, 7, 6, 4, 10, "hilbert", 16, 4),
+    (64, 80, 1, 9, 10, 6, 8, "hilbert", 32, 5),
+])
+def test_index_small_images(h, w, c, K, D, L, b, curve, W, seed):
+    d = synth.small_image(h, w, c, seed)
+    _check(d["volume"], d["mask"], K, D, L, b, curve, W)
+
+
+@pytest.mark.parametrize("n,c,K,D,L,b,curve,W,seed", [
+    (14, 1, 3, 4, 2, 8, "morton", 8, 1),
+    (16, 1, 5, 8, 4, 8, "morton", 16, 2),
+    (18, 1, 7, 10, 6, 8, "hilbert", 32, 3),
+])
+def test_index_small_volumes(n, c, K, D, L, b, curve, W, seed):
+    d = synth.small_volume(n, seed, c=c)
+    _check(d["volume"], d["mask"], K, D, L, b, curve, W)
+
+
+def test_index_config1():
+    d = synth.config1()
+    _check(d["volume"], d["mask"], 9, 8, 4, 8, "morton", 32)
+
+
+def test_index_with_given_basis():
+    d = synth.small_image(40, 50, 2, 8)
+    _check(d["volume"], d["mask"], 5, 5, 3, 12, "hilbert", 16, with_basis=True)
