@@ -1,0 +1,210 @@
+"""Throughput of the masked-L2 patch search on one MI355X.
+
+One step runs the whole hot path over one synthetic workload: fill front and
+target extraction, the SFC multi-index build (byte codes, covariance, Jacobi,
+int8 basis, MFMA projection, keys, radix sort), the index query of every
+front target, and the full float32 scan of every front target (plus the
+reduced-precision scan when it is available). `value` is front queries
+answered per second by that whole step; the per-form rates are reported
+beside it.
+
+  python bench.py [--steps K] [--warmup W] [--workload config2] [--no-cpu-baseline]
+
+Prints one JSON line. Only N=1 is supported: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 78.6   # TFLOP/s: 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s dense
+PEAK_HBM = 8000.0        # GB/s
+
+WORKLOADS = {
+    "config2": dict(gen="config2", K=9, D=8, L=4, key_bits=21, window=32, curve="morton",
+                    label="config2_1024sq_rgb_blobs10_K9 (n~0.9e6)"),
+    "config1": dict(gen="config1", K=9, D=8, L=4, key_bits=8, window=32, curve="morton",
+                    label="config1_256sq_gray_hole32_K9"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1712_06326_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key, workload, src_hash):
+    p = os.path.join(ROOT, "profiles", f"{kernel_key}_{workload}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != src_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="oracle full-scan queries timed")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 512 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1712_06326_amd import native, synth
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.time()
+    data = getattr(synth, wl["gen"])()
+    log(f"generated {wl['label']} in {time.time() - t0:.1f}s")
+    vol_h, mask_h = data["volume"], data["mask"]
+    dev = torch.device("cuda:0")
+    vol = torch.from_numpy(vol_h).to(dev)
+    mask = torch.from_numpy(mask_h).to(dev)
+    K = wl["K"]
+    opts = dict(key_bits=wl["key_bits"], window=wl["window"], curve=wl["curve"])
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def step(record):
+        e0 = ev()
+        f = native.fill_front(mask)
+        t, m = native.extract_targets(vol, mask, K, f)
+        e1 = ev()
+        ix = native.Index(vol, mask, K, reduced_dim=wl["D"], n_curves=wl["L"], **opts)
+        e2 = ev()
+        bi_x, bc_x = ix.query(t, m, "index")
+        e3 = ev()
+        bi_s, bc_s = ix.query(t, m, "fp32")
+        e4 = ev()
+        out = dict(Q=f.numel(), n=ix.info.n, t=t, m=m, f=f, bi_x=bi_x, bc_x=bc_x, bi_s=bi_s,
+                   bc_s=bc_s)
+        if record is not None:
+            record.append((e0, e1, e2, e3, e4))
+        ix.close()
+        return out
+
+    # autotune the float32 scan's tile shape once on this workload (the
+    # choice is remembered for every later handle of the same shape)
+    f0 = native.fill_front(mask)
+    t0_, m0_ = native.extract_targets(vol, mask, K, f0)
+    ix0 = native.Index(vol, mask, K)
+    chosen = ix0.autotune(t0_, m0_)
+    ix0.close()
+    log(f"autotuned float32-scan shape: {chosen}")
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    marks = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        res = step(marks)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = 1e3 * wall / args.steps
+    phases = np.array([[a.elapsed_time(b) for a, b in zip(mk[:-1], mk[1:])] for mk in marks])
+    ph = phases.mean(axis=0)
+    Q, n = res["Q"], res["n"]
+    m_h = res["m"].cpu().numpy()
+    known_elems = float(m_h.sum()) * vol_h.shape[-1]
+
+    # agreement of the index with the full scan (recall@1, acceleration error)
+    bi_x, bc_x = res["bi_x"].cpu().numpy(), res["bc_x"].cpu().numpy()
+    bi_s, bc_s = res["bi_s"].cpu().numpy(), res["bc_s"].cpu().numpy()
+    recall = float(np.mean(bi_x == bi_s))
+    ok = bc_s > 0
+    ae = float(np.mean(np.sqrt(bc_x[ok].astype(np.float64)) / np.sqrt(bc_s[ok]) - 1.0)) * 100
+
+    scan_ms = ph[3]
+    scan_flops = 3.0 * known_elems * n
+    scan_tflops = scan_flops / (scan_ms * 1e-3) / 1e12
+    traffic = load_traffic("scan_fp32", args.workload, source_hash(["k_scan.hip"]))
+
+    line = {
+        "metric": "queries/s at n=1e6 (SFC index vs GPU brute force), argmin agreement %",
+        "value": round(Q / (ms_step * 1e-3), 2),
+        "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["label"], "n": n, "queries": Q, "K": K,
+                   "reduced_dim": wl["D"], "n_curves": wl["L"], "key_bits": wl["key_bits"],
+                   "window": wl["window"], "curve": wl["curve"]},
+        "forms": {
+            "index_qps": round(Q / (ph[2] * 1e-3), 1),
+            "index_qps_with_build": round(Q / ((ph[1] + ph[2]) * 1e-3), 1),
+            "fp32_scan_qps": round(Q / (scan_ms * 1e-3), 1),
+            "phase_ms": {"front_extract": round(ph[0], 3), "index_build": round(ph[1], 3),
+                         "index_query": round(ph[2], 3), "fp32_scan": round(ph[3], 3)},
+            "fp32_scan_shape": chosen,
+            "index_recall_at_1_pct": round(100 * recall, 3),
+            "index_acceleration_error_pct": round(ae, 4),
+        },
+        "roofline": {"bound": "alu", "kernel": "scan_fp32_kernel",
+                     "achieved": round(scan_tflops, 3), "peak": PEAK_FP32_VALU,
+                     "unit": "TFLOP/s", "frac": round(scan_tflops / PEAK_FP32_VALU, 4),
+                     "traffic": traffic},
+    }
+
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 536870912 bytes read, 536870912 bytes written")
+
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(7)
+        k = min(args.cpu_sample, Q)
+        sel = np.sort(rng.choice(Q, k, replace=False))
+        f_h = res["f"].cpu().numpy()[sel]
+        t_h = res["t"].cpu().numpy()[sel]
+        d_h = oracle.dictionary(mask_h, K)
+        tc = time.perf_counter()
+        ob, oc = oracle.brute(vol_h, mask_h.shape, K, d_h, t_h, m_h[sel])
+        cpu_s = time.perf_counter() - tc
+        agree = float(np.mean((ob == bi_s[sel]) & (oc.view(np.uint32) == bc_s[sel].view(np.uint32))))
+        line["cpu_baseline"] = {
+            "value": round(k / cpu_s, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} seeded front queries of the same workload through the oracle's "
+                      f"float32 full scan (n={n}), single thread, {cpu_s:.1f}s; index build "
+                      f"and index queries excluded (under 0.1% of the oracle's per-query time)"}
+        line["forms"]["fp32_vs_oracle_agreement_pct"] = round(100 * agree, 2)
+        line["forms"]["oracle_sample_centres"] = [int(x) for x in f_h]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

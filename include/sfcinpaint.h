@@ -76,8 +76,9 @@ typedef struct {
                               reduced-precision scans, default 16 */
     int32_t certify;       /* 1 (default): a reduced-precision answer whose
                               certificate fails is recomputed by the float32 scan */
-    int32_t query_block;   /* queries per float32-scan pass, 0 = library choice */
-    int32_t reserved;
+    int32_t query_block;   /* queries per float32-scan workgroup, 0 = library choice */
+    int32_t scan_variant;  /* float32-scan tile shape: 0 = default or the one
+                              sfc_autotune chose, k >= 1 = the k-th shape */
     void *stream;          /* hipStream_t; NULL = default stream */
 } sfc_options;
 
@@ -179,6 +180,15 @@ sfc_status sfc_query_candidates(sfc_index *idx, const float *targets,
 sfc_status sfc_query_coords(sfc_index *idx, const float *targets,
                             const uint8_t *target_masks, int64_t Q, int32_t *subset,
                             double *coords);
+
+/* Autotuner: times every float32-scan tile shape available for the handle's
+ * (ndim, K, channels) on these targets (one warm-up and one timed run each,
+ * HIP events on the handle's stream) and keeps the fastest for later
+ * SFC_MODE_BRUTE_FP32 queries of this handle (unless options.scan_variant
+ * forces one) and for handles of the same shape created later in the
+ * process. *chosen_host receives the chosen shape (>= 1). Synchronises. */
+sfc_status sfc_autotune(sfc_index *idx, const float *targets, const uint8_t *target_masks,
+                        int64_t Q, int32_t *chosen_host);
 
 /* Statistics of the last sfc_query call on this handle (host values):
  * n_fallback = queries a reduced-precision scan could not certify. */

@@ -4,7 +4,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -115,6 +118,21 @@ sfc_status validate_options(const sfc_options& o) {
     return SFC_OK;
 }
 
+// Process-wide memory of the autotuner's choices, per (ndim, K, C).
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tuned;
+
+void remember_variant(int nd, int K, int C, int v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(nd, K, C)] = v;
+}
+
+int recalled_variant(int nd, int K, int C) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(nd, K, C));
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
 // Dictionary of a handle: validity map + ascending id list.
 sfc_status build_dictionary(sfc_index* ix, const uint8_t* mask) {
     const Grid& g = ix->g;
@@ -153,11 +171,20 @@ namespace sfc {
 sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                             uint64_t* best_dev) {
     const Grid& g = ix->g;
-    SFC_TRY(ix->rowmask.reserve((size_t)scan_qpad(Q) * g.rows * sizeof(uint32_t), "row masks"));
+    const int64_t qpad = scan_qpad(Q);
+    SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
     uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
     SFC_TRY(launch_pack_rowmask(m, g, Q, rm, ix->st));
+    // targets padded with zero rows up to the scan's query block
+    const size_t tbytes = (size_t)Q * g.Kd * g.C * sizeof(float);
+    const size_t pbytes = (size_t)qpad * g.Kd * g.C * sizeof(float);
+    SFC_TRY(ix->tpad.reserve(pbytes, "padded targets"));
+    float* tp = static_cast<float*>(ix->tpad.ptr);
+    SFC_HIP(hipMemcpyAsync(tp, t, tbytes, hipMemcpyDeviceToDevice, ix->st));
+    SFC_TRY(launch_zero_f32(tp + (size_t)Q * g.Kd * g.C, (int64_t)(qpad - Q) * g.Kd * g.C, ix->st));
     SFC_TRY(launch_fill_u64(best_dev, Q, ~0ull, ix->st));
-    ScanArgs a{ix->vol, ix->valid, t, rm, Q, best_dev, ix->opt.query_block};
+    ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best_dev, ix->opt.query_block,
+               ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant};
     return launch_scan_fp32(g, a, ix->st);
 }
 
@@ -231,6 +258,7 @@ static sfc_status new_handle(const float* volume, const uint8_t* mask, const sfc
     SFC_TRY(validate_options(o));
     sfc_index* ix = new sfc_index();
     ix->g = make_grid(g, K);
+    ix->tuned_variant = recalled_variant(g->ndim, K, g->channels);
     ix->opt = o;
     ix->st = static_cast<hipStream_t>(o.stream);
     ix->vol = volume;
@@ -360,6 +388,53 @@ sfc_status sfc_query_coords(sfc_index* ix, const float* targets, const uint8_t* 
     if (!targets || !target_masks || !subset || !coords)
         return fail(SFC_EINVAL, "sfc_query_coords: null pointer");
     return query_coords(ix, targets, target_masks, Q, subset, coords);
+}
+
+sfc_status sfc_autotune(sfc_index* ix, const float* targets, const uint8_t* target_masks,
+                        int64_t Q, int32_t* chosen) {
+    clear_error();
+    if (!ix || !targets || !target_masks || !chosen) return fail(SFC_EINVAL, "null pointer");
+    if (Q < 1) return fail(SFC_EINVAL, "autotuning needs Q >= 1");
+    const Grid& g = ix->g;
+    const int nv = scan_variants(g.nd, g.K, g.C);
+    if (nv == 0) return fail(SFC_EUNSUPPORTED, "no float32 scan for this shape");
+    SFC_TRY(ix->best.reserve((size_t)Q * sizeof(uint64_t), "query results"));
+    uint64_t* best = static_cast<uint64_t*>(ix->best.ptr);
+    hipEvent_t e0, e1;
+    SFC_HIP(hipEventCreate(&e0));
+    SFC_HIP(hipEventCreate(&e1));
+    const int saved = ix->tuned_variant, saved_opt = ix->opt.scan_variant;
+    ix->opt.scan_variant = 0;
+    int bestv = 0;
+    float bestms = 0.0f;
+    sfc_status st = SFC_OK;
+    for (int v = 0; v < nv && st == SFC_OK; v++) {
+        ix->tuned_variant = v;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && st == SFC_OK; rep++) {   // first run warms up
+            hipError_t he = hipEventRecord(e0, ix->st);
+            if (he == hipSuccess) st = query_brute_fp32(ix, targets, target_masks, Q, best);
+            if (st == SFC_OK && he == hipSuccess) he = hipEventRecord(e1, ix->st);
+            if (st == SFC_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+            if (st == SFC_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (st == SFC_OK && he != hipSuccess) st = check_hip(he, "autotune timing");
+        }
+        if (st == SFC_OK && (v == 0 || ms < bestms)) {
+            bestms = ms;
+            bestv = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ix->opt.scan_variant = saved_opt;
+    if (st != SFC_OK) {
+        ix->tuned_variant = saved;
+        return st;
+    }
+    ix->tuned_variant = bestv;
+    remember_variant(g.nd, g.K, g.C, bestv);
+    *chosen = bestv + 1;
+    return SFC_OK;
 }
 
 sfc_status sfc_query_stats(const sfc_index* ix, int64_t* n_fallback) {

@@ -72,22 +72,25 @@ sfc_status launch_extract(const float* vol, const uint8_t* mask, const Grid& g,
 sfc_status launch_valid_centres(const uint8_t* mask, const Grid& g, uint8_t* valid,
                                 uint8_t* tmp, hipStream_t st);
 sfc_status launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
+sfc_status launch_zero_f32(float* p, int64_t n, hipStream_t st);
 sfc_status launch_u32_to_i64(const uint32_t* in, int64_t* out, int64_t n, hipStream_t st);
 
 // float32 full scan: best[q] = min over valid centres of (cost bits << 32 | id)
 struct ScanArgs {
     const float* vol;
     const uint8_t* valid;
-    const float* t;
+    const float* t;            // [scan_qpad(Q), K^nd, C], rows beyond Q zero
     const uint32_t* rowmask;   // [rows, scan_qpad(Q)] bit dx set when (row, dx) is known
     int64_t Q;
     uint64_t* best;            // [Q], pre-filled with ~0
     int query_block;           // 0 = default
+    int variant;               // scan shape variant (0 = default)
 };
 sfc_status launch_pack_rowmask(const uint8_t* m, const Grid& g, int64_t Q, uint32_t* rowmask,
                                hipStream_t st);
 sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st);
 int64_t scan_qpad(int64_t Q);  // row-mask query stride
+int scan_variants(int nd, int K, int C);
 sfc_status launch_unpack_best(const uint64_t* best, int64_t Q, int64_t* id, float* cost,
                               hipStream_t st);
 

@@ -20,6 +20,8 @@ struct Scratch {
 };
 
 sfc_options resolve_options(const sfc_options* in);
+void remember_variant(int nd, int K, int C, int v);
+int recalled_variant(int nd, int K, int C);
 
 }  // namespace sfc
 
@@ -59,8 +61,9 @@ struct sfc_index {
     int Pp = 0;                      // element count padded to 16
 
     // ---- per-call scratch
-    sfc::Scratch rowmask, best, qtmp, cand, rp_a, rp_b;
+    sfc::Scratch rowmask, best, qtmp, tpad;
     int64_t last_fallback = 0;
+    int tuned_variant = 0;           // float32-scan shape chosen by sfc_autotune
 
     ~sfc_index();
 };

@@ -159,6 +159,11 @@ __global__ void fill_u64_kernel(uint64_t* p, int64_t n, uint64_t v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void zero_f32_kernel(float* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
 __global__ void u32_to_i64_kernel(const uint32_t* __restrict__ in, int64_t* __restrict__ out,
                                   int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,6 +255,12 @@ sfc_status launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st) {
     if (n == 0) return SFC_OK;
     fill_u64_kernel<<<blocks_for(n), kBlock, 0, st>>>(p, n, v);
     return launched("fill_u64_kernel");
+}
+
+sfc_status launch_zero_f32(float* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return SFC_OK;
+    zero_f32_kernel<<<blocks_for(n), kBlock, 0, st>>>(p, n);
+    return launched("zero_f32_kernel");
 }
 
 sfc_status launch_u32_to_i64(const uint32_t* in, int64_t* out, int64_t n, hipStream_t st) {

@@ -187,9 +187,9 @@ __global__ void cov_matrix_kernel(const uint64_t* __restrict__ sum,
 
 // ------------------------------------------------------------ Jacobi
 // One workgroup per subset. Rotations of one round act on disjoint index
-// pairs (round-robin pairing), so each phase is data parallel:
-//   decide (c, s) per pair from the round's starting matrix,
-//   rows B = J^T A, columns A = B J, zero the pair entries, V = V J.
+// pairs (round-robin pairing), so each round is two data-parallel phases:
+//   decide (c, s) per pair from the round's starting matrix;
+//   A <- J^T A J (rows then columns, pair entries zeroed) and V <- V J.
 // The operation sequence per element matches the documented algorithm
 // exactly (no fused multiply-add: the file is compiled with contraction off).
 constexpr int kJacThreads = 1024;
@@ -268,49 +268,102 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_kernel(double* __restrict_
                 sact[k] = act;
             }
             __syncthreads();
-            // rows: B = J^T A (inactive rows copied)
-            for (int64_t i = tid; i < (int64_t)np * m; i += kJacThreads) {
-                const int k = (int)(i / m), j = (int)(i % m);
-                const int p = sp[k], q = sq[k];
-                if (sact[k]) {
-                    const double c = scs[k], sn = ssn[k];
-                    const double x = A[(int64_t)p * m + j], y = A[(int64_t)q * m + j];
-                    B[(int64_t)p * m + j] = c * x - sn * y;
-                    B[(int64_t)q * m + j] = sn * x + c * y;
-                } else {
-                    if (p < m) B[(int64_t)p * m + j] = A[(int64_t)p * m + j];
-                    if (q < m) B[(int64_t)q * m + j] = A[(int64_t)q * m + j];
+            // A <- J^T A J block by block: the 2x2 block at (rows of pair k1,
+            // columns of pair k2) depends only on itself. Rows are rotated
+            // first (when pair k1 rotates), then columns (when pair k2
+            // rotates), exactly the operations of the row pass followed by
+            // the column pass; blocks are disjoint, so the update is in place.
+            // V <- V J runs alongside on its own data.
+            // blocks: item i = k1*np + k2 with i = tid + it*kJacThreads, the
+            // pair indices advanced by constant steps (no division per item)
+            {
+                const int d1 = kJacThreads / np, d2 = kJacThreads % np;
+                int k1 = tid / np, k2 = tid % np;
+                constexpr int kBatch = 4;
+                while (k1 < np) {
+                    int bk1[kBatch], bk2[kBatch];
+                    double x[kBatch][4];
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        bk1[u] = k1;
+                        bk2[u] = k2;
+                        if (k1 < np) {
+                            const int r0 = sp[k1], r1 = sq[k1], c0 = sp[k2], c1 = sq[k2];
+                            const bool vr1 = r1 < m, vc1 = c1 < m;
+                            x[u][0] = A[r0 * m + c0];
+                            x[u][1] = vc1 ? A[r0 * m + c1] : 0.0;
+                            x[u][2] = vr1 ? A[r1 * m + c0] : 0.0;
+                            x[u][3] = (vr1 && vc1) ? A[r1 * m + c1] : 0.0;
+                        }
+                        k1 += d1;
+                        k2 += d2;
+                        if (k2 >= np) {
+                            k2 -= np;
+                            k1++;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBatch; u++) {
+                        const int a1 = bk1[u], a2 = bk2[u];
+                        if (a1 >= np) continue;
+                        double x00 = x[u][0], x01 = x[u][1], x10 = x[u][2], x11 = x[u][3];
+                        if (sact[a1]) {
+                            const double c = scs[a1], sn = ssn[a1];
+                            const double y00 = c * x00 - sn * x10, y10 = sn * x00 + c * x10;
+                            const double y01 = c * x01 - sn * x11, y11 = sn * x01 + c * x11;
+                            x00 = y00; x10 = y10; x01 = y01; x11 = y11;
+                        }
+                        if (sact[a2]) {
+                            const double c = scs[a2], sn = ssn[a2];
+                            const double y00 = c * x00 - sn * x01, y01 = sn * x00 + c * x01;
+                            const double y10 = c * x10 - sn * x11, y11 = sn * x10 + c * x11;
+                            x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+                        }
+                        if (a1 == a2 && sact[a1]) {
+                            x01 = 0.0;
+                            x10 = 0.0;
+                        }
+                        const int r0 = sp[a1], r1 = sq[a1], c0 = sp[a2], c1 = sq[a2];
+                        const bool vr1 = r1 < m, vc1 = c1 < m;
+                        A[r0 * m + c0] = x00;
+                        if (vc1) A[r0 * m + c1] = x01;
+                        if (vr1) A[r1 * m + c0] = x10;
+                        if (vr1 && vc1) A[r1 * m + c1] = x11;
+                    }
                 }
             }
-            __syncthreads();
-            // columns: A = B J (inactive columns copied)
-            for (int64_t i = tid; i < (int64_t)np * m; i += kJacThreads) {
-                const int k = (int)(i / m), j = (int)(i % m);
-                const int p = sp[k], q = sq[k];
-                if (sact[k]) {
-                    const double c = scs[k], sn = ssn[k];
-                    const double x = B[(int64_t)j * m + p], y = B[(int64_t)j * m + q];
-                    A[(int64_t)j * m + p] = c * x - sn * y;
-                    A[(int64_t)j * m + q] = sn * x + c * y;
-                } else {
-                    if (p < m) A[(int64_t)j * m + p] = B[(int64_t)j * m + p];
-                    if (q < m) A[(int64_t)j * m + q] = B[(int64_t)j * m + q];
+            // eigenvectors: item i = k*m + j, same stepping, loads batched
+            {
+                const int d1 = kJacThreads / m, d2 = kJacThreads % m;
+                int k = tid / m, j = tid % m;
+                constexpr int kVB = 8;
+                while (k < np) {
+                    int bk[kVB], bj[kVB];
+                    double xv[kVB], yv[kVB];
+#pragma unroll
+                    for (int u = 0; u < kVB; u++) {
+                        bk[u] = k;
+                        bj[u] = j;
+                        if (k < np && sact[k]) {
+                            xv[u] = V[j * m + sp[k]];
+                            yv[u] = V[j * m + sq[k]];
+                        }
+                        k += d1;
+                        j += d2;
+                        if (j >= m) {
+                            j -= m;
+                            k++;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kVB; u++) {
+                        const int kk = bk[u];
+                        if (kk >= np || !sact[kk]) continue;
+                        const double c = scs[kk], sn = ssn[kk];
+                        V[bj[u] * m + sp[kk]] = c * xv[u] - sn * yv[u];
+                        V[bj[u] * m + sq[kk]] = sn * xv[u] + c * yv[u];
+                    }
                 }
-            }
-            __syncthreads();
-            // annihilated entries and eigenvectors
-            for (int64_t i = tid; i < (int64_t)np * m; i += kJacThreads) {
-                const int k = (int)(i / m), j = (int)(i % m);
-                if (!sact[k]) continue;
-                const int p = sp[k], q = sq[k];
-                if (j == 0) {
-                    A[(int64_t)p * m + q] = 0.0;
-                    A[(int64_t)q * m + p] = 0.0;
-                }
-                const double c = scs[k], sn = ssn[k];
-                const double x = V[(int64_t)j * m + p], y = V[(int64_t)j * m + q];
-                V[(int64_t)j * m + p] = c * x - sn * y;
-                V[(int64_t)j * m + q] = sn * x + c * y;
             }
             __syncthreads();
         }

@@ -20,7 +20,7 @@ namespace sfc {
 namespace {
 
 constexpr int kLanes = 256;
-constexpr int kScanQB = 16;
+constexpr int kScanQB = 48;   // row-mask padding: a multiple of every variant's QB
 
 typedef const __attribute__((address_space(4))) float cfloat_as4;
 typedef const __attribute__((address_space(4))) uint32_t cu32_as4;
@@ -46,18 +46,20 @@ struct ScanParams {
     int64_t qpad;            // row-mask stride (queries padded to the block size)
 };
 
-// Lane-level running best over the tiles of a workgroup: candidates of later
-// tiles have larger ids, so a strict comparison keeps the lowest id on ties.
-template <int ND, int K, int C, int QB>
+// Each lane owns NX adjacent candidates of a 64*NX-wide line tile; their
+// patch rows are read straight from memory (L1/L2 resident), so waves run
+// without barriers. The workgroup's four waves share the query batches and
+// split its tiles; per batch, each wave keeps a per-lane running best
+// (strict comparison in ascending id order keeps the lowest id), reduces it
+// over the wave, and the workgroup merges the four results in LDS before one
+// global atomic per query.
+template <int ND, int K, int C, int QB, int NX>
 __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     constexpr int H = (K - 1) / 2;
     constexpr int ROWS = (ND == 2) ? K : K * K;
-    constexpr int TW = kLanes + K - 1;
     constexpr int RW = K * C;
-    constexpr int TILE = ROWS * TW * C;
-    extern __shared__ float smem[];
-    float* tile = smem;
-    uint32_t* sred = reinterpret_cast<uint32_t*>(smem + TILE);  // [4 waves][QB][2]
+    constexpr int SEG = (K + NX - 1) * C;     // floats of one patch row for NX candidates
+    __shared__ uint64_t sred[kLanes / 64][QB];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -75,9 +77,9 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
             bcost[qi] = 0xffffffffu;
             bid[qi] = 0xffffffffu;
         }
-        for (int64_t tl = tl0; tl < tl1; tl++) {
+        for (int64_t tl = tl0 + wave; tl < tl1; tl += kLanes / 64) {
             const int64_t line = tl / p.tiles_per_line;
-            const int64_t x0 = (tl - line * p.tiles_per_line) * kLanes;
+            const int64_t x0 = (tl - line * p.tiles_per_line) * (64 * NX) + (int64_t)lane * NX;
             int64_t base;
             if (ND == 2) {
                 base = (line + H) * p.stride[0];
@@ -86,103 +88,96 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
                 const int64_t z = line / iy, y = line - z * iy;
                 base = (z + H) * p.stride[0] + (y + H) * p.stride[1];
             }
-            __syncthreads();
-            for (int i = tid; i < TILE; i += kLanes) {
-                const int r = i / (TW * C);
-                const int rem = i - r * TW * C;
-                const int j = rem / C;
-                const int ch = rem - j * C;
-                const int64_t xv = x0 + j;
-                float val = 0.0f;
-                if (xv < p.shape[ND - 1]) {
-                    int64_t roff;
-                    if (ND == 2) roff = (int64_t)(r - H) * p.stride[0];
-                    else roff = (int64_t)(r / K - H) * p.stride[0] + (int64_t)(r % K - H) * p.stride[1];
-                    val = p.vol[(base + roff + xv) * C + ch];
-                }
-                tile[i] = val;
-            }
-            __syncthreads();
-            const int64_t xi = x0 + tid;
-            const bool cvalid = (xi < p.line_len) && p.valid[base + xi + H];
-            const uint32_t cid = (uint32_t)(base + xi + H);
-
-            float acc[QB];
+            const bool whole = x0 + NX <= p.line_len;   // all NX candidates inside the line
+            float acc[QB][NX];
 #pragma unroll
-            for (int qi = 0; qi < QB; qi++) acc[qi] = 0.0f;
+            for (int qi = 0; qi < QB; qi++)
+#pragma unroll
+                for (int j = 0; j < NX; j++) acc[qi][j] = 0.0f;
             for (int r = 0; r < ROWS; r++) {
-                // masks of the QB queries for row r are contiguous (row-major [rows][Qpad])
                 const uint32_t* mrb = p.rowmask + (int64_t)r * p.qpad + qb;
-                uint32_t mrow[QB];
-                uint32_t orm = 0;
+                int64_t roff;
+                if (ND == 2) roff = (int64_t)(r - H) * p.stride[0];
+                else roff = (int64_t)(r / K - H) * p.stride[0] + (int64_t)(r % K - H) * p.stride[1];
+                const float* vp = p.vol + (base + roff + x0) * C;
+                float v[SEG];
+                if (whole) {
 #pragma unroll
-                for (int qi = 0; qi < QB; qi++) {
-                    mrow[qi] = ldu(mrb + qi);
-                    orm |= mrow[qi];
+                    for (int i = 0; i < SEG; i++) v[i] = vp[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < SEG; i++)
+                        v[i] = (x0 + i / C < p.shape[ND - 1]) ? vp[i] : 0.0f;
                 }
-                if (orm == 0) continue;
-                float v[RW];
-                const float* trow = tile + (r * TW + tid) * C;
-#pragma unroll
-                for (int i = 0; i < RW; i++) v[i] = trow[i];
                 const float* tb = p.t + (qb * ROWS + r) * RW;
 #pragma unroll
                 for (int qi = 0; qi < QB; qi++) {
-                    const uint32_t mr = mrow[qi];
-                    if (mr == 0) continue;
+                    // targets are padded to the query block: both loads are in
+                    // bounds and issue together before one wait
                     float tr[RW];
 #pragma unroll
                     for (int i = 0; i < RW; i++) tr[i] = ldu(tb + qi * ROWS * RW + i);
+                    const uint32_t mr = ldu(mrb + qi);
+                    if (mr == 0) continue;
+                    if (mr == (1u << K) - 1u) {
 #pragma unroll
-                    for (int dx = 0; dx < K; dx++) {
-                        if (mr & (1u << dx)) {
+                        for (int j = 0; j < NX; j++)
 #pragma unroll
-                            for (int ch = 0; ch < C; ch++) {
-                                const float d = tr[dx * C + ch] - v[dx * C + ch];
-                                acc[qi] = __builtin_fmaf(d, d, acc[qi]);
+                            for (int i = 0; i < RW; i++) {
+                                const float d = tr[i] - v[j * C + i];
+                                acc[qi][j] = __builtin_fmaf(d, d, acc[qi][j]);
+                            }
+                    } else {
+#pragma unroll
+                        for (int dx = 0; dx < K; dx++) {
+                            if (mr & (1u << dx)) {
+#pragma unroll
+                                for (int j = 0; j < NX; j++)
+#pragma unroll
+                                    for (int ch = 0; ch < C; ch++) {
+                                        const float d = tr[dx * C + ch] - v[(j + dx) * C + ch];
+                                        acc[qi][j] = __builtin_fmaf(d, d, acc[qi][j]);
+                                    }
                             }
                         }
                     }
                 }
             }
-            if (cvalid) {
 #pragma unroll
-                for (int qi = 0; qi < QB; qi++) {
-                    const uint32_t cb = __float_as_uint(acc[qi]);
-                    if (cb < bcost[qi]) {
-                        bcost[qi] = cb;
-                        bid[qi] = cid;
+            for (int j = 0; j < NX; j++) {
+                const int64_t xi = x0 + j;
+                const uint32_t cid = (uint32_t)(base + xi + H);
+                if (xi < p.line_len && p.valid[cid]) {
+#pragma unroll
+                    for (int qi = 0; qi < QB; qi++) {
+                        const uint32_t cb = __float_as_uint(acc[qi][j]);
+                        if (cb < bcost[qi]) {
+                            bcost[qi] = cb;
+                            bid[qi] = cid;
+                        }
                     }
                 }
             }
         }
-        // (cost, id) minimum over the workgroup, then one global atomic per query
 #pragma unroll
         for (int qi = 0; qi < QB; qi++) {
-            uint32_t c = bcost[qi];
+            uint64_t pk = ((uint64_t)bcost[qi] << 32) | bid[qi];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) c = min(c, (uint32_t)__shfl_xor((int)c, off, 64));
-            const uint64_t bal = __ballot(bcost[qi] == c);
-            const int first = __ffsll((unsigned long long)bal) - 1;
-            const uint32_t id = (uint32_t)__shfl((int)bid[qi], first, 64);
-            if (lane == 0) {
-                sred[(wave * QB + qi) * 2] = c;
-                sred[(wave * QB + qi) * 2 + 1] = id;
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint64_t o = (uint64_t)__shfl_xor((long long)pk, off, 64);
+                pk = o < pk ? o : pk;
             }
+            if (lane == 0) sred[wave][qi] = pk;
         }
         __syncthreads();
         if (tid < QB && qb + tid < q1) {
-            uint64_t best = ~0ull;
-            for (int w = 0; w < kLanes / 64; w++) {
-                const uint32_t c = sred[(w * QB + tid) * 2], id = sred[(w * QB + tid) * 2 + 1];
-                if (c != 0xffffffffu) {
-                    const uint64_t pk = ((uint64_t)c << 32) | id;
-                    if (pk < best) best = pk;
-                }
-            }
-            if (best != ~0ull)
+            uint64_t best = sred[0][tid];
+#pragma unroll
+            for (int w = 1; w < kLanes / 64; w++) best = sred[w][tid] < best ? sred[w][tid] : best;
+            if ((best >> 32) != 0xffffffffull)
                 atomicMin((unsigned long long*)&p.best[qb + tid], (unsigned long long)best);
         }
+        __syncthreads();
     }
 }
 
@@ -217,47 +212,56 @@ __global__ void unpack_best_kernel(const uint64_t* __restrict__ best, int64_t Q,
 
 using ScanFn = void (*)(ScanParams);
 
-template <int ND, int K, int C>
-constexpr int scan_qb() {
-    return kScanQB;
-}
-
-template <int ND, int K, int C>
-ScanFn pick() {
-    return scan_fp32_kernel<ND, K, C, scan_qb<ND, K, C>()>;
-}
-
 struct ScanEntry {
     int nd, K, C;
+    int qb, nx;
     ScanFn fn;
-    int qb;
 };
 
-#define SFC_SCAN_ENTRY(ND, K, C) {ND, K, C, pick<ND, K, C>(), scan_qb<ND, K, C>()}
-
+// (QB queries per pass, NX candidates per lane) shapes per (ndim, K, C); the
+// first entry of a shape is its default, the others are candidates for the
+// autotuner.
+#define SFC_SCAN(ND, K, C, QB, NX) {ND, K, C, QB, NX, scan_fp32_kernel<ND, K, C, QB, NX>}
 const ScanEntry kScanTable[] = {
-    SFC_SCAN_ENTRY(2, 3, 1), SFC_SCAN_ENTRY(2, 3, 2), SFC_SCAN_ENTRY(2, 3, 3),
-    SFC_SCAN_ENTRY(2, 5, 1), SFC_SCAN_ENTRY(2, 5, 2), SFC_SCAN_ENTRY(2, 5, 3),
-    SFC_SCAN_ENTRY(2, 7, 1), SFC_SCAN_ENTRY(2, 7, 2), SFC_SCAN_ENTRY(2, 7, 3),
-    SFC_SCAN_ENTRY(2, 9, 1), SFC_SCAN_ENTRY(2, 9, 2), SFC_SCAN_ENTRY(2, 9, 3),
-    SFC_SCAN_ENTRY(2, 11, 1), SFC_SCAN_ENTRY(2, 11, 3),
-    SFC_SCAN_ENTRY(2, 13, 1), SFC_SCAN_ENTRY(2, 13, 3),
-    SFC_SCAN_ENTRY(3, 3, 1), SFC_SCAN_ENTRY(3, 3, 2),
-    SFC_SCAN_ENTRY(3, 5, 1), SFC_SCAN_ENTRY(3, 5, 2),
-    SFC_SCAN_ENTRY(3, 7, 1),
+    SFC_SCAN(2, 3, 1, 16, 8), SFC_SCAN(2, 3, 2, 16, 8), SFC_SCAN(2, 3, 3, 16, 8),
+    SFC_SCAN(2, 5, 1, 16, 8), SFC_SCAN(2, 5, 2, 16, 4), SFC_SCAN(2, 5, 3, 16, 4),
+    SFC_SCAN(2, 7, 1, 16, 8), SFC_SCAN(2, 7, 2, 16, 4), SFC_SCAN(2, 7, 3, 16, 4),
+    SFC_SCAN(2, 9, 1, 16, 8), SFC_SCAN(2, 9, 1, 16, 4), SFC_SCAN(2, 9, 1, 8, 8),
+    SFC_SCAN(2, 9, 2, 16, 4),
+    SFC_SCAN(2, 9, 3, 16, 4), SFC_SCAN(2, 9, 3, 8, 4), SFC_SCAN(2, 9, 3, 16, 2),
+    SFC_SCAN(2, 9, 3, 8, 8), SFC_SCAN(2, 9, 3, 12, 4),
+    SFC_SCAN(2, 11, 1, 16, 4), SFC_SCAN(2, 11, 3, 16, 2),
+    SFC_SCAN(2, 13, 1, 16, 4), SFC_SCAN(2, 13, 3, 8, 2),
+    SFC_SCAN(3, 3, 1, 16, 8), SFC_SCAN(3, 3, 2, 16, 8),
+    SFC_SCAN(3, 5, 1, 16, 8), SFC_SCAN(3, 5, 1, 16, 4), SFC_SCAN(3, 5, 1, 8, 8),
+    SFC_SCAN(3, 5, 2, 16, 4),
+    SFC_SCAN(3, 7, 1, 16, 4), SFC_SCAN(3, 7, 1, 16, 8), SFC_SCAN(3, 7, 1, 8, 8),
 };
+
+// variant v (0 = default) of a shape, or null
+const ScanEntry* scan_entry(int nd, int K, int C, int v) {
+    int k = 0;
+    for (const auto& e : kScanTable)
+        if (e.nd == nd && e.K == K && e.C == C) {
+            if (k == v) return &e;
+            k++;
+        }
+    return nullptr;
+}
 
 inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-bool scan_supported(int nd, int K, int C) {
-    for (const auto& e : kScanTable)
-        if (e.nd == nd && e.K == K && e.C == C) return true;
-    return false;
+bool scan_supported(int nd, int K, int C) { return scan_entry(nd, K, C, 0) != nullptr; }
+
+int scan_variants(int nd, int K, int C) {
+    int k = 0;
+    while (scan_entry(nd, K, C, k)) k++;
+    return k;
 }
 
-int64_t scan_qpad(int64_t Q) { return ((Q + kScanQB - 1) / kScanQB) * kScanQB; }
+int64_t scan_qpad(int64_t Q) { return ((Q + kScanQB - 1) / kScanQB) * kScanQB; }  // multiple of every QB
 
 sfc_status launch_pack_rowmask(const uint8_t* m, const Grid& g, int64_t Q, uint32_t* rowmask,
                                hipStream_t st) {
@@ -279,9 +283,8 @@ sfc_status launch_unpack_best(const uint64_t* best, int64_t Q, int64_t* id, floa
 
 sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     if (a.Q == 0) return SFC_OK;
-    const ScanEntry* ent = nullptr;
-    for (const auto& e : kScanTable)
-        if (e.nd == g.nd && e.K == g.K && e.C == g.C) ent = &e;
+    const ScanEntry* ent = scan_entry(g.nd, g.K, g.C, a.variant);
+    if (!ent) ent = scan_entry(g.nd, g.K, g.C, 0);
     if (!ent)
         return fail(SFC_EUNSUPPORTED, "float32 scan: no kernel for this (ndim, K, channels)");
     ScanParams p{};
@@ -299,32 +302,25 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     for (int i = 0; i < g.nd - 1; i++) n_lines *= (g.shape[i] - 2 * g.h);
     p.line_len = g.shape[g.nd - 1] - 2 * g.h;
     if (n_lines <= 0 || p.line_len <= 0) return SFC_OK;
-    p.tiles_per_line = (p.line_len + kLanes - 1) / kLanes;
+    const int64_t tw = 64 * ent->nx;   // candidates per wave tile
+    p.tiles_per_line = (p.line_len + tw - 1) / tw;
     p.n_tiles = n_lines * p.tiles_per_line;
-    // queries per workgroup (LDS holds one 8-byte best per query)
-    int64_t qpw = a.query_block > 0 ? a.query_block : 1024;
+    // queries per workgroup, then tiles per workgroup so that the grid holds
+    // about 4096 workgroups (16 per CU)
+    int64_t qpw = a.query_block > 0 ? a.query_block : 512;
     qpw = ((qpw + ent->qb - 1) / ent->qb) * ent->qb;
     if (qpw > a.Q) qpw = ((a.Q + ent->qb - 1) / ent->qb) * ent->qb;
     p.q_per_wg = qpw;
     p.qpad = scan_qpad(a.Q);
     const int64_t qsplit = (a.Q + qpw - 1) / qpw;
-    int64_t tpw = (p.n_tiles * qsplit + 2047) / 2048;
-    if (tpw < 1) tpw = 1;
+    int64_t tpw = (p.n_tiles * qsplit + 4095) / 4096;
+    tpw = ((tpw + 3) / 4) * 4;
+    if (tpw < 4) tpw = 4;
     p.tiles_per_wg = tpw;
     const int64_t chunks = (p.n_tiles + tpw - 1) / tpw;
-    const int rows = g.rows;
-    const size_t tile_floats = (size_t)rows * (kLanes + g.K - 1) * g.C;
-    const size_t lds = tile_floats * sizeof(float) + (size_t)(kLanes / 64) * ent->qb * 8;
-    if (lds > 160 * 1024)
-        return fail(SFC_EUNSUPPORTED, "float32 scan: LDS tile too large");
     if (qsplit > 65535) return fail(SFC_EUNSUPPORTED, "float32 scan: too many queries");
     dim3 grid((unsigned)chunks, (unsigned)qsplit);
-    if (lds > 64 * 1024) {
-        hipError_t ea = hipFuncSetAttribute((const void*)ent->fn,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (ea != hipSuccess) return check_hip(ea, "scan_fp32_kernel LDS attribute");
-    }
-    hipLaunchKernelGGL(ent->fn, grid, dim3(kLanes), lds, st, p);
+    hipLaunchKernelGGL(ent->fn, grid, dim3(kLanes), 0, st, p);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFC_OK : check_hip(e, "scan_fp32_kernel");
 }

@@ -8,6 +8,9 @@
 // scatter in which each tile ranks its items stably with wave-level
 // multi-split (8 ballots give each lane its peers with the same digit) and a
 // per-round prefix over the four waves held in LDS.
+#include <algorithm>
+#include <utility>
+
 #include "proj.hpp"
 
 namespace sfc {
@@ -30,9 +33,11 @@ __device__ inline uint32_t digit_of(const uint64_t* keys, int64_t n, int64_t i, 
     return (uint32_t)((keys[(int64_t)w * n + i] >> (pb & 63)) & 0xffu);
 }
 
-__global__ __launch_bounds__(kThreads) void hist_kernel(const uint64_t* __restrict__ keys, int64_t n,
+__global__ __launch_bounds__(kThreads) void hist_kernel(const uint64_t* __restrict__ keys_all, int64_t n,
                                                         int W64, int pb, int64_t nb,
-                                                        uint32_t* __restrict__ counts) {
+                                                        uint32_t* __restrict__ counts_all) {
+    const uint64_t* keys = keys_all + (int64_t)blockIdx.y * W64 * n;
+    uint32_t* counts = counts_all + (int64_t)blockIdx.y * 256 * nb;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -47,11 +52,12 @@ __global__ __launch_bounds__(kThreads) void hist_kernel(const uint64_t* __restri
 
 // Exclusive scan of counts[d][0..nb) in place (one block per digit);
 // totals[d] = the digit's count.
-__global__ __launch_bounds__(kThreads) void scan_digit_kernel(uint32_t* __restrict__ counts,
+__global__ __launch_bounds__(kThreads) void scan_digit_kernel(uint32_t* __restrict__ counts_all,
                                                               int64_t nb,
-                                                              uint32_t* __restrict__ totals) {
+                                                              uint32_t* __restrict__ totals_all) {
     const int d = blockIdx.x;
-    uint32_t* row = counts + (int64_t)d * nb;
+    uint32_t* row = counts_all + (int64_t)blockIdx.y * 256 * nb + (int64_t)d * nb;
+    uint32_t* totals = totals_all + blockIdx.y * 256;
     __shared__ uint32_t wsum[kThreads / 64];
     __shared__ uint32_t carry;
     if (threadIdx.x == 0) carry = 0;
@@ -81,7 +87,10 @@ __global__ __launch_bounds__(kThreads) void scan_digit_kernel(uint32_t* __restri
     if (threadIdx.x == 0) totals[d] = carry;
 }
 
-__global__ void digit_base_kernel(const uint32_t* __restrict__ totals, uint32_t* __restrict__ dbase) {
+__global__ void digit_base_kernel(const uint32_t* __restrict__ totals_all,
+                                  uint32_t* __restrict__ dbase_all) {
+    const uint32_t* totals = totals_all + blockIdx.x * 256;
+    uint32_t* dbase = dbase_all + blockIdx.x * 256;
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
         for (int d = 0; d < 256; d++) {
@@ -91,36 +100,75 @@ __global__ void digit_base_kernel(const uint32_t* __restrict__ totals, uint32_t*
     }
 }
 
+// Scatter of one tile: local stable ranks by wave multi-split, then each
+// key word (and the ids) is reordered by digit in LDS and written out in
+// digit runs, so global writes are contiguous within each run.
 __global__ __launch_bounds__(kThreads) void scatter_kernel(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ iin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ iout, int64_t n, int W64, int pb, int64_t nb,
-    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ dbase) {
+    const uint64_t* __restrict__ kin_all, const uint32_t* __restrict__ iin_all,
+    uint64_t* __restrict__ kout_all, uint32_t* __restrict__ iout_all, int64_t n, int W64, int pb,
+    int64_t nb, const uint32_t* __restrict__ counts_all, const uint32_t* __restrict__ dbase_all) {
+    const int64_t arr = blockIdx.y;
+    const uint64_t* kin = kin_all + arr * W64 * n;
+    uint64_t* kout = kout_all + arr * W64 * n;
+    const uint32_t* iin = iin_all + arr * n;
+    uint32_t* iout = iout_all + arr * n;
+    const uint32_t* counts = counts_all + arr * 256 * nb;
+    const uint32_t* dbase = dbase_all + arr * 256;
     __shared__ uint32_t cnt[kThreads / 64][256];
     __shared__ uint32_t run[256];
+    __shared__ uint32_t tstart[256];
     __shared__ uint32_t tbase[256];
+    __shared__ uint32_t wsum[kThreads / 64];
+    __shared__ uint8_t sdig[kTileItems];
+    __shared__ uint64_t sval[kTileItems];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    run[tid] = 0;
-    tbase[tid] = dbase[tid] + counts[(int64_t)tid * nb + blockIdx.x];
     const int64_t t0 = (int64_t)blockIdx.x * kTileItems;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    uint32_t dg[kRounds];
+    run[tid] = 0;
+    tstart[tid] = 0;
+    tbase[tid] = dbase[tid] + counts[(int64_t)tid * nb + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRounds; k++) {
+        const int64_t i = t0 + (int64_t)k * kThreads + tid;
+        dg[k] = (i < n) ? digit_of(kin, n, i, W64, pb) : 0xffffffffu;
+        if (i < n) atomicAdd(&tstart[dg[k]], 1u);
+    }
+    __syncthreads();
+    {
+        // exclusive scan of the tile's digit counts (thread tid owns digit tid)
+        const uint32_t x = tstart[tid];
+        uint32_t inc = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)inc, off, 64);
+            if (lane >= off) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (int k = 0; k < w; k++) pre += wsum[k];
+        tstart[tid] = pre + inc - x;
+    }
+    uint32_t lp[kRounds];
+#pragma unroll
     for (int k = 0; k < kRounds; k++) {
         for (int ww = 0; ww < kThreads / 64; ww++) cnt[ww][tid] = 0;
         __syncthreads();
-        const int64_t i = t0 + (int64_t)k * kThreads + tid;
-        const bool valid = i < n;
-        const uint32_t dg = valid ? digit_of(kin, n, i, W64, pb) : 0u;
+        const bool valid = dg[k] != 0xffffffffu;
+        const uint32_t d = valid ? dg[k] : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; bit++) {
-            const bool on = (dg >> bit) & 1u;
+            const bool on = (d >> bit) & 1u;
             const uint64_t bl = __ballot(on);
             peers &= on ? bl : ~bl;
         }
         const uint32_t rk = (uint32_t)__popcll(peers & lt);
-        if (valid && rk == 0) cnt[w][dg] = (uint32_t)__popcll(peers);
+        if (valid && rk == 0) cnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         {
-            // thread tid owns digit tid: exclusive prefix over waves + running total
             uint32_t acc = run[tid];
             for (int ww = 0; ww < kThreads / 64; ww++) {
                 const uint32_t c = cnt[ww][tid];
@@ -130,10 +178,25 @@ __global__ __launch_bounds__(kThreads) void scatter_kernel(
             run[tid] = acc;
         }
         __syncthreads();
-        if (valid) {
-            const int64_t pos = (int64_t)tbase[dg] + cnt[w][dg] + rk;
-            for (int x = 0; x < W64; x++) kout[(int64_t)x * n + pos] = kin[(int64_t)x * n + i];
-            iout[pos] = iin[i];
+        lp[k] = valid ? tstart[d] + cnt[w][d] + rk : 0xffffffffu;
+        if (valid) sdig[lp[k]] = (uint8_t)d;
+        __syncthreads();   // cnt is cleared by the next round
+    }
+    __syncthreads();
+    const int64_t tn = min((int64_t)kTileItems, n - t0);
+    for (int x = 0; x <= W64; x++) {
+#pragma unroll
+        for (int k = 0; k < kRounds; k++) {
+            if (lp[k] == 0xffffffffu) continue;
+            const int64_t i = t0 + (int64_t)k * kThreads + tid;
+            sval[lp[k]] = (x < W64) ? kin[(int64_t)x * n + i] : (uint64_t)iin[i];
+        }
+        __syncthreads();
+        for (int slot = tid; slot < tn; slot += kThreads) {
+            const uint32_t d = sdig[slot];
+            const int64_t gpos = (int64_t)tbase[d] + slot - tstart[d];
+            if (x < W64) kout[(int64_t)x * n + gpos] = sval[slot];
+            else iout[gpos] = (uint32_t)sval[slot];
         }
         __syncthreads();
     }
@@ -157,9 +220,9 @@ __global__ void varying_kernel(const uint64_t* __restrict__ keys, int64_t n, int
 
 }  // namespace
 
-size_t sort_scratch_bytes(int64_t n, int W64) {
+size_t sort_scratch_bytes(int64_t n, int W64, int arrays) {
     const int64_t nb = (n + kTileItems - 1) / kTileItems;
-    return (size_t)n * (8 * W64 + 4) + (size_t)(256 * nb + 512) * 4 + 256;
+    return (size_t)arrays * ((size_t)n * (8 * W64 + 4) + (size_t)(256 * nb + 512) * 4) + 256;
 }
 
 sfc_status launch_varying_bits(const uint64_t* keys, int64_t n, int W64, int arrays,
@@ -170,38 +233,39 @@ sfc_status launch_varying_bits(const uint64_t* keys, int64_t n, int W64, int arr
     return launched("varying_kernel");
 }
 
-sfc_status radix_sort(uint64_t* keys, uint32_t* ids, int64_t n, int W64, const SortPlan& plan,
-                      void* scratch, hipStream_t st) {
-    if (n <= 1 || plan.n_passes == 0) return SFC_OK;
+sfc_status radix_sort(uint64_t* keys, uint32_t* ids, int64_t n, int W64, int arrays,
+                      const SortPlan& plan, void* scratch, hipStream_t st) {
+    if (n <= 1 || plan.n_passes == 0 || arrays == 0) return SFC_OK;
     const int64_t nb = (n + kTileItems - 1) / kTileItems;
     char* p = static_cast<char*>(scratch);
     uint64_t* k2 = reinterpret_cast<uint64_t*>(p);
-    p += (size_t)n * 8 * W64;
+    p += (size_t)arrays * n * 8 * W64;
     uint32_t* i2 = reinterpret_cast<uint32_t*>(p);
-    p += (size_t)n * 4;
+    p += (size_t)arrays * n * 4;
     p = reinterpret_cast<char*>(((uintptr_t)p + 255) & ~uintptr_t(255));
     uint32_t* counts = reinterpret_cast<uint32_t*>(p);
-    uint32_t* totals = counts + 256 * nb;
-    uint32_t* dbase = totals + 256;
+    uint32_t* totals = counts + (size_t)arrays * 256 * nb;
+    uint32_t* dbase = totals + (size_t)arrays * 256;
     uint64_t *kin = keys, *kout = k2;
     uint32_t *iin = ids, *iout = i2;
+    if (nb > 0x7fffffff || arrays > 65535) return fail(SFC_EUNSUPPORTED, "sort grid too large");
     for (int ps = 0; ps < plan.n_passes; ps++) {
         const int pb = plan.pass_bits[ps];
-        hist_kernel<<<(unsigned)nb, kThreads, 0, st>>>(kin, n, W64, pb, nb, counts);
+        hist_kernel<<<dim3((unsigned)nb, arrays), kThreads, 0, st>>>(kin, n, W64, pb, nb, counts);
         SFC_TRY(launched("hist_kernel"));
-        scan_digit_kernel<<<256, kThreads, 0, st>>>(counts, nb, totals);
+        scan_digit_kernel<<<dim3(256, arrays), kThreads, 0, st>>>(counts, nb, totals);
         SFC_TRY(launched("scan_digit_kernel"));
-        digit_base_kernel<<<1, 64, 0, st>>>(totals, dbase);
+        digit_base_kernel<<<arrays, 64, 0, st>>>(totals, dbase);
         SFC_TRY(launched("digit_base_kernel"));
-        scatter_kernel<<<(unsigned)nb, kThreads, 0, st>>>(kin, iin, kout, iout, n, W64, pb, nb,
-                                                          counts, dbase);
+        scatter_kernel<<<dim3((unsigned)nb, arrays), kThreads, 0, st>>>(kin, iin, kout, iout, n, W64,
+                                                                        pb, nb, counts, dbase);
         SFC_TRY(launched("scatter_kernel"));
         std::swap(kin, kout);
         std::swap(iin, iout);
     }
     if (kin != keys) {
-        SFC_HIP(hipMemcpyAsync(keys, kin, (size_t)n * 8 * W64, hipMemcpyDeviceToDevice, st));
-        SFC_HIP(hipMemcpyAsync(ids, iin, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+        SFC_HIP(hipMemcpyAsync(keys, kin, (size_t)arrays * n * 8 * W64, hipMemcpyDeviceToDevice, st));
+        SFC_HIP(hipMemcpyAsync(ids, iin, (size_t)arrays * n * 4, hipMemcpyDeviceToDevice, st));
     }
     return SFC_OK;
 }

@@ -31,14 +31,16 @@ __device__ __forceinline__ void hilbert_axes_to_transpose(uint32_t* X, int D, in
 
 // Bit l of coordinate d lands at bit l*D + (D-1-d) of the D*b-bit key:
 // level by level from the top, dim 0 first. Word 0 is the most significant.
+// Each level's D bits are gathered into one group and placed at once.
 __device__ __forceinline__ void interleave_words(const uint32_t* v, int D, int b, int W64, uint64_t* w) {
     for (int i = 0; i < W64; i++) w[i] = 0;
-    for (int d = 0; d < D; d++) {
-        const uint32_t x = v[d];
-        for (int l = 0; l < b; l++) {
-            const int pos = l * D + (D - 1 - d);
-            w[W64 - 1 - (pos >> 6)] |= (uint64_t)((x >> l) & 1u) << (pos & 63);
-        }
+    for (int l = 0; l < b; l++) {
+        uint64_t grp = 0;
+        for (int d = 0; d < D; d++) grp = (grp << 1) | ((v[d] >> l) & 1u);
+        const int pos = l * D;
+        const int wi = W64 - 1 - (pos >> 6), sh = pos & 63;
+        w[wi] |= grp << sh;
+        if (sh + D > 64) w[wi - 1] |= grp >> (64 - sh);
     }
 }
 

@@ -47,12 +47,14 @@ struct SortPlan {
     int n_passes;
     int pass_bits[64];        // bit position (from the key's LSB) of each 8-bit digit
 };
-// bytes of scratch for n items, W64 words: ping-pong copy + histograms
-size_t sort_scratch_bytes(int64_t n, int W64);
+// bytes of scratch for `arrays` arrays of n items, W64 words: ping-pong copy + histograms
+size_t sort_scratch_bytes(int64_t n, int W64, int arrays);
 // OR over items of (key XOR key[0]) for `arrays` consecutive arrays -> varying[arr][W64]
 sfc_status launch_varying_bits(const uint64_t* keys, int64_t n, int W64, int arrays,
                                uint64_t* varying, hipStream_t st);
-sfc_status radix_sort(uint64_t* keys, uint32_t* ids, int64_t n, int W64, const SortPlan& plan,
-                      void* scratch, hipStream_t st);
+// Sorts `arrays` consecutive arrays (keys [arrays][W64][n], ids [arrays][n])
+// with the same digit passes.
+sfc_status radix_sort(uint64_t* keys, uint32_t* ids, int64_t n, int W64, int arrays,
+                      const SortPlan& plan, void* scratch, hipStream_t st);
 
 }  // namespace sfc

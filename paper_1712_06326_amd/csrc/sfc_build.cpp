@@ -356,18 +356,25 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
     std::vector<uint64_t> hv((size_t)S * L * ix->W64);
     SFC_HIP(hipMemcpyAsync(hv.data(), varying, hv.size() * 8, hipMemcpyDeviceToHost, st));
     SFC_HIP(hipStreamSynchronize(st));
+    // arrays are sorted in groups whose ping-pong copies fit a fixed budget,
+    // each group with the union of its arrays' varying digit positions
+    const int narr = S * L;
+    const size_t per_arr = sort_scratch_bytes(ix->n, ix->W64, 1);
+    int group = (int)std::max<size_t>(1, std::min<size_t>(narr, (size_t(8) << 30) / per_arr));
     void* sscratch = nullptr;
-    SFC_TRY(tmp.alloc(&sscratch, sort_scratch_bytes(ix->n, ix->W64), "sort scratch"));
+    SFC_TRY(tmp.alloc(&sscratch, sort_scratch_bytes(ix->n, ix->W64, group), "sort scratch"));
     const int nbits = D * ix->b;
-    for (int a = 0; a < S * L; a++) {
+    for (int a0 = 0; a0 < narr; a0 += group) {
+        const int na = std::min(group, narr - a0);
         SortPlan plan{};
         for (int pb = 0; pb < nbits; pb += 8) {
             const int w = ix->W64 - 1 - (pb >> 6);
-            const uint64_t bits = (hv[(size_t)a * ix->W64 + w] >> (pb & 63)) & 0xffull;
+            uint64_t bits = 0;
+            for (int a = a0; a < a0 + na; a++) bits |= (hv[(size_t)a * ix->W64 + w] >> (pb & 63)) & 0xffull;
             if (bits) plan.pass_bits[plan.n_passes++] = pb;
         }
-        SFC_TRY(radix_sort(ix->keys + (size_t)a * ix->W64 * ix->n, ix->ids + (size_t)a * ix->n,
-                           ix->n, ix->W64, plan, sscratch, st));
+        SFC_TRY(radix_sort(ix->keys + (size_t)a0 * ix->W64 * ix->n, ix->ids + (size_t)a0 * ix->n,
+                           ix->n, ix->W64, na, plan, sscratch, st));
     }
 
     // host copies of the small parameters

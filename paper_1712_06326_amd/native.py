@@ -35,7 +35,7 @@ class Geometry(C.Structure):
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("key_bits", C.c_int32), ("window", C.c_int32),
                 ("curve", C.c_int32), ("rescore_top", C.c_int32), ("certify", C.c_int32),
-                ("query_block", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("query_block", C.c_int32), ("scan_variant", C.c_int32), ("stream", C.c_void_p)]
 
 
 class IndexInfo(C.Structure):
@@ -71,6 +71,7 @@ _SIG = {
     "sfc_query_candidates": (ST, [P, P, P, I64, P, P]),
     "sfc_query_coords": (ST, [P, P, P, I64, P, P]),
     "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
+    "sfc_autotune": (ST, [P, P, P, I64, C.POINTER(C.c_int32)]),
     "sfc_index_info_get": (ST, [P, C.POINTER(IndexInfo)]),
     "sfc_index_dictionary": (ST, [P, P]),
     "sfc_index_quantized": (ST, [P, P]),
@@ -127,7 +128,7 @@ def geometry(mask: torch.Tensor, channels: int) -> Geometry:
 
 
 def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
-            query_block=0) -> Options:
+            query_block=0, scan_variant=0) -> Options:
     o = Options()
     _L.sfc_options_default(C.byref(o))
     o.key_bits = key_bits
@@ -136,6 +137,7 @@ def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
     o.rescore_top = rescore_top
     o.certify = 1 if certify else 0
     o.query_block = query_block
+    o.scan_variant = scan_variant
     o.stream = _stream()
     return o
 
@@ -214,6 +216,12 @@ class Index:
         bc = torch.empty(Q, dtype=torch.float32, device=t.device)
         _check(_L.sfc_query(self._h, _ptr(t), _ptr(m), Q, MODES[mode], _ptr(bi), _ptr(bc)))
         return bi, bc
+
+    def autotune(self, t: torch.Tensor, m: torch.Tensor) -> int:
+        """Picks the fastest float32-scan tile shape on these targets."""
+        v = C.c_int32()
+        _check(_L.sfc_autotune(self._h, _ptr(t), _ptr(m), m.shape[0], C.byref(v)))
+        return v.value
 
     def fallbacks(self) -> int:
         n = C.c_int64()

@@ -84,20 +84,35 @@ def test_scan_degenerate_queries():
     assert host(bi)[0] == do[0] and host(bc)[0] == 0.0 and host(bc)[2] == 0.0
 
 
-def test_scan_determinism_and_query_blocks():
+@pytest.mark.parametrize("h,w,c,K", [(64, 300, 3, 9), (40, 530, 1, 9), (50, 260, 2, 5)])
+def test_scan_determinism_over_tile_shapes(h, w, c, K):
+    """Every float32-scan tile shape and workgroup split gives the same bits,
+    and the autotuner's choice is one of them."""
     nat = need_gpu()
-    d = synth.small_image(64, 300, 3, 10)
+    d = synth.small_image(h, w, c, 10 + K)
     vol, mask = d["volume"], d["mask"]
     vd, md = dev(vol), dev(mask)
     f = nat.fill_front(md)
-    t, m = nat.extract_targets(vd, md, 9, f)
+    t, m = nat.extract_targets(vd, md, K, f)
     outs = []
-    for qb in (0, 16, 48, 4096):
-        ix = nat.Index(vd, md, 9, query_block=qb)
-        bi, bc = ix.query(t, m)
-        outs.append((host(bi), host(bc)))
-    for o in outs[1:]:
-        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    for v in range(1, 6):
+        for qb in (0, 48, 4096):
+            try:
+                ix = nat.Index(vd, md, K, query_block=qb, scan_variant=v)
+                bi, bc = ix.query(t, m)
+            except nat.SfcError:
+                continue
+            outs.append((host(bi), host(bc)))
+    ix = nat.Index(vd, md, K)
+    chosen = ix.autotune(t, m)
+    assert chosen >= 1
+    bi, bc = ix.query(t, m)
+    outs.append((host(bi), host(bc)))
+    to, mo = oracle.extract(vol, mask, K, host(f))
+    boi, boc = oracle.brute(vol, mask.shape, K, oracle.dictionary(mask, K), to, mo)
+    assert len(outs) >= 4
+    for o in outs:
+        assert np.array_equal(o[0], boi) and np.array_equal(o[1].view(np.uint32), boc.view(np.uint32))
 
 
 def test_scan_config2_sampled():
