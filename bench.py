@@ -26,7 +26,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU = 78.6   # TFLOP/s: 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
+PEAK_FP32_VALU = 157.3  # TFLOP/s: 256 CU x 128 FP32 lanes x 2 flop x 2.4 GHz (published vector peak)
 PEAK_BF16_MFMA = 2500.0  # TFLOP/s dense
 PEAK_HBM = 8000.0        # GB/s
 
@@ -107,10 +107,12 @@ def main():
         e3 = ev()
         bi_s, bc_s = ix.query(t, m, "fp32")
         e4 = ev()
+        bi_r, bc_r = ix.query(t, m, "bf16")
+        e5 = ev()
         out = dict(Q=f.numel(), n=ix.info.n, t=t, m=m, f=f, bi_x=bi_x, bc_x=bc_x, bi_s=bi_s,
-                   bc_s=bc_s)
+                   bc_s=bc_s, bi_r=bi_r, bc_r=bc_r, fallback=ix.fallbacks())
         if record is not None:
-            record.append((e0, e1, e2, e3, e4))
+            record.append((e0, e1, e2, e3, e4, e5))
         ix.close()
         return out
 
@@ -145,6 +147,8 @@ def main():
     ok = bc_s > 0
     ae = float(np.mean(np.sqrt(bc_x[ok].astype(np.float64)) / np.sqrt(bc_s[ok]) - 1.0)) * 100
 
+    bi_r, bc_r = res["bi_r"].cpu().numpy(), res["bc_r"].cpu().numpy()
+    red_agree = float(np.mean((bi_r == bi_s) & (bc_r.view(np.uint32) == bc_s.view(np.uint32))))
     scan_ms = ph[3]
     scan_flops = 3.0 * known_elems * n
     scan_tflops = scan_flops / (scan_ms * 1e-3) / 1e12
@@ -165,8 +169,12 @@ def main():
             "index_qps": round(Q / (ph[2] * 1e-3), 1),
             "index_qps_with_build": round(Q / ((ph[1] + ph[2]) * 1e-3), 1),
             "fp32_scan_qps": round(Q / (scan_ms * 1e-3), 1),
+            "bf16_scan_qps": round(Q / (ph[4] * 1e-3), 1),
+            "bf16_vs_fp32_agreement_pct": round(100 * red_agree, 3),
+            "bf16_fallback_queries": int(res["fallback"]),
             "phase_ms": {"front_extract": round(ph[0], 3), "index_build": round(ph[1], 3),
-                         "index_query": round(ph[2], 3), "fp32_scan": round(ph[3], 3)},
+                         "index_query": round(ph[2], 3), "fp32_scan": round(ph[3], 3),
+                         "bf16_scan": round(ph[4], 3)},
             "fp32_scan_shape": chosen,
             "index_recall_at_1_pct": round(100 * recall, 3),
             "index_acceleration_error_pct": round(ae, 4),

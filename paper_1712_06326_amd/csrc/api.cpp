@@ -262,7 +262,13 @@ static sfc_status new_handle(const float* volume, const uint8_t* mask, const sfc
     ix->opt = o;
     ix->st = static_cast<hipStream_t>(o.stream);
     ix->vol = volume;
-    sfc_status s = build_dictionary(ix, mask);
+    sfc_status s = dev_alloc((void**)&ix->mask_copy, (size_t)ix->g.nvox, "mask copy");
+    if (s == SFC_OK) {
+        hipError_t e = hipMemcpyAsync(ix->mask_copy, mask, (size_t)ix->g.nvox,
+                                      hipMemcpyDeviceToDevice, ix->st);
+        if (e != hipSuccess) s = check_hip(e, "mask copy");
+    }
+    if (s == SFC_OK) s = build_dictionary(ix, mask);
     if (s != SFC_OK) {
         delete ix;
         return s;

@@ -7,7 +7,7 @@
 namespace sfc {
 
 // ---- byte quantisation (vmin/vmax over known voxels, FP32 scale)
-// params: float[2] = {vmin, scale} on the device
+// params: float[3] = {vmin, scale, vmax} on the device
 sfc_status launch_quantize(const float* vol, const uint8_t* mask, const Grid& g, uint8_t* xq,
                            float* params, uint32_t* tmp2, hipStream_t st);
 

@@ -58,10 +58,12 @@ struct sfc_index {
     std::vector<int8_t> h_basis;
     std::vector<int64_t> h_lo, h_span;
     void* proj_w = nullptr;          // bf16 projection weights [tiles*32][Pp]
+    uint8_t* mask_copy = nullptr;    // [nvox] the mask at build time
+    uint16_t* mfma_B = nullptr;      // reduced-precision scan operand [npad][Kp] bf16
     int Pp = 0;                      // element count padded to 16
 
     // ---- per-call scratch
-    sfc::Scratch rowmask, best, qtmp, tpad;
+    sfc::Scratch rowmask, best, qtmp, tpad, red;
     int64_t last_fallback = 0;
     int tuned_variant = 0;           // float32-scan shape chosen by sfc_autotune
 
@@ -70,6 +72,8 @@ struct sfc_index {
 
 namespace sfc {
 
+sfc_status ensure_quantized(sfc_index* ix, const uint8_t* mask);
+sfc_status ensure_elem_offsets(sfc_index* ix);
 sfc_status check_sfc_args(const sfc_geometry* g, int K, int D, int L, const sfc_options& o);
 sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int8_t* bases_host);
 void release_sfc(sfc_index* ix);

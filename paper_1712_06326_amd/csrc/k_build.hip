@@ -52,11 +52,13 @@ __global__ void minmax_kernel(const float* __restrict__ vol, const uint8_t* __re
     }
 }
 
-// scale = 255 / (vmax - vmin) in float32 (0 when the range is empty)
+// params = {vmin, scale = 255 / (vmax - vmin) in float32 (0 when the range is
+// empty), vmax}
 __global__ void scale_kernel(const uint32_t* __restrict__ mm, float* __restrict__ params) {
     const float lo = fdec(mm[0]), hi = fdec(mm[1]);
     params[0] = lo;
     params[1] = (hi > lo) ? 255.0f / (hi - lo) : 0.0f;
+    params[2] = hi;
 }
 
 __global__ void quantize_kernel(const float* __restrict__ vol, int64_t n,

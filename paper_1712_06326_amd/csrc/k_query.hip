@@ -4,6 +4,7 @@
 // of entries around it per curve, and rescore the union of the windows with
 // the exact masked cost (a full scan in image space over the candidates).
 #include "keys.hpp"
+#include "mfma_scan.hpp"
 #include "query.hpp"
 
 namespace sfc {
@@ -316,6 +317,43 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
     }
 }
 
+// One wave per query: exact cost of every listed candidate, (cost, id) min.
+template <int ND, int K, int C>
+__global__ __launch_bounds__(256) void list_rescore_kernel(QueryIndexView v, const float* __restrict__ vol,
+                                                           const float* __restrict__ t,
+                                                           const uint32_t* __restrict__ rowmask,
+                                                           int64_t qpad, const uint32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ cnt,
+                                                           const int32_t* __restrict__ thr, int cap,
+                                                           int64_t Q, int64_t* __restrict__ best_id,
+                                                           float* __restrict__ best_cost,
+                                                           uint8_t* __restrict__ fb) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (q >= Q) return;
+    const int nc = cnt[q];
+    const bool fallback = thr[q] < 0 || nc > cap || nc == 0;
+    if (lane == 0) fb[q] = fallback ? 1 : 0;
+    if (fallback) return;
+    const float* tq = t + q * (int64_t)v.Kd * C;
+    const uint32_t* rm = rowmask + q;
+    uint64_t best = ~0ull;
+    for (int i = lane; i < nc; i += 64) {
+        const uint32_t c = list[q * cap + i];
+        const float cost = cand_cost<ND, K, C>(v, vol, tq, rm, qpad, c);
+        const uint64_t pk = ((uint64_t)__float_as_uint(cost) << 32) | c;
+        if (pk < best) best = pk;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = (uint64_t)__shfl_xor((long long)best, off, 64);
+        if (o < best) best = o;
+    }
+    if (lane == 0) {
+        best_id[q] = (int64_t)(best & 0xffffffffull);
+        best_cost[q] = __uint_as_float((uint32_t)(best >> 32));
+    }
+}
+
 using PrologueFn = void (*)(QueryIndexView, const float*, const uint8_t*, int64_t, int32_t*,
                             double*, uint64_t*);
 using RescoreFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
@@ -325,11 +363,16 @@ using RescoreFn = void (*)(QueryIndexView, const float*, const float*, const uin
 template <int D>
 PrologueFn prologue_fn() { return prologue_kernel<D>; }
 
+using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
+                       const uint32_t*, const int32_t*, const int32_t*, int, int64_t, int64_t*,
+                       float*, uint8_t*);
+
 struct RescoreEntry {
     int nd, K, C;
     RescoreFn fn;
+    ListFn lfn;
 };
-#define SFC_RESCORE(ND, K, C) {ND, K, C, rescore_kernel<ND, K, C>}
+#define SFC_RESCORE(ND, K, C) {ND, K, C, rescore_kernel<ND, K, C>, list_rescore_kernel<ND, K, C>}
 const RescoreEntry kRescore[] = {
     SFC_RESCORE(2, 3, 1), SFC_RESCORE(2, 3, 2), SFC_RESCORE(2, 3, 3),
     SFC_RESCORE(2, 5, 1), SFC_RESCORE(2, 5, 2), SFC_RESCORE(2, 5, 3),
@@ -375,6 +418,29 @@ sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub, con
     if (Q == 0) return SFC_OK;
     search_kernel<<<blocks_for(Q * v.L * 64), 256, 0, st>>>(v, qsub, qkeys, Q, wstart);
     return launched("search_kernel");
+}
+
+sfc_status launch_list_rescore(const Grid& g, const float* vol, const float* t,
+                               const uint32_t* rowmask, int64_t qpad, const uint32_t* list,
+                               const int32_t* cnt, const int32_t* thr, int cap, int64_t Q,
+                               int64_t* best_id, float* best_cost, uint8_t* fb, hipStream_t st) {
+    if (Q == 0) return SFC_OK;
+    const RescoreEntry* ent = nullptr;
+    for (const auto& e : kRescore)
+        if (e.nd == g.nd && e.K == g.K && e.C == g.C) ent = &e;
+    if (!ent) return fail(SFC_EUNSUPPORTED, "list rescoring: no kernel for this (ndim, K, C)");
+    QueryIndexView v{};
+    v.nd = g.nd;
+    v.K = g.K;
+    v.C = g.C;
+    v.Kd = g.Kd;
+    for (int i = 0; i < kMaxDims; i++) {
+        v.shape[i] = g.shape[i];
+        v.stride[i] = g.stride[i];
+    }
+    hipLaunchKernelGGL(ent->lfn, dim3(blocks_for(Q * 64)), dim3(256), 0, st, v, vol, t, rowmask,
+                       qpad, list, cnt, thr, cap, Q, best_id, best_cost, fb);
+    return launched("list_rescore_kernel");
 }
 
 bool rescore_supported(int nd, int K, int C) {

@@ -20,6 +20,7 @@ namespace sfc {
 namespace {
 
 constexpr int kLanes = 256;
+constexpr int kXcds = 8;
 constexpr int kScanQB = 48;   // row-mask padding: a multiple of every variant's QB
 
 typedef const __attribute__((address_space(4))) float cfloat_as4;
@@ -44,6 +45,7 @@ struct ScanParams {
     int64_t tiles_per_wg;
     int64_t q_per_wg;
     int64_t qpad;            // row-mask stride (queries padded to the block size)
+    int64_t n_chunks, chunks_per_xcd, q_splits;
 };
 
 // Each lane owns NX adjacent candidates of a 64*NX-wide line tile; their
@@ -64,10 +66,19 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t q0 = (int64_t)blockIdx.y * p.q_per_wg;
+    // XCD-aware mapping: workgroups are dispatched to the 8 XCDs round-robin,
+    // so block b runs on XCD b % 8. Each XCD gets a contiguous band of tile
+    // chunks (all query splits of it), keeping its band of the volume in
+    // that XCD's L2.
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b % kXcds, slot = b / kXcds;
+    const int64_t chunk = xcd * p.chunks_per_xcd + slot % p.chunks_per_xcd;
+    const int64_t qs = slot / p.chunks_per_xcd;
+    if (chunk >= p.n_chunks || qs >= p.q_splits) return;
+    const int64_t q0 = qs * p.q_per_wg;
     const int64_t q1 = min(p.Q, q0 + p.q_per_wg);
     if (q0 >= q1) return;
-    const int64_t tl0 = (int64_t)blockIdx.x * p.tiles_per_wg;
+    const int64_t tl0 = chunk * p.tiles_per_wg;
     const int64_t tl1 = min(p.n_tiles, tl0 + p.tiles_per_wg);
 
     for (int64_t qb = q0; qb < q1; qb += QB) {
@@ -318,9 +329,12 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     if (tpw < 4) tpw = 4;
     p.tiles_per_wg = tpw;
     const int64_t chunks = (p.n_tiles + tpw - 1) / tpw;
-    if (qsplit > 65535) return fail(SFC_EUNSUPPORTED, "float32 scan: too many queries");
-    dim3 grid((unsigned)chunks, (unsigned)qsplit);
-    hipLaunchKernelGGL(ent->fn, grid, dim3(kLanes), 0, st, p);
+    p.n_chunks = chunks;
+    p.chunks_per_xcd = (chunks + kXcds - 1) / kXcds;
+    p.q_splits = qsplit;
+    const int64_t nblocks = kXcds * p.chunks_per_xcd * qsplit;
+    if (nblocks > 0x7fffffffLL) return fail(SFC_EUNSUPPORTED, "float32 scan: grid too large");
+    hipLaunchKernelGGL(ent->fn, dim3((unsigned)nblocks), dim3(kLanes), 0, st, p);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFC_OK : check_hip(e, "scan_fp32_kernel");
 }

