@@ -1,0 +1,258 @@
+// Fill loop kernels (Section I: repeatedly pick a target on the fill front,
+// find its best dictionary patch, insert it). The fill order follows
+// Criminisi et al.'s priority, which the paper cites without formulas; the
+// formulas below are the documented reading: P = C_p * D_p with
+//   C_p = (sum of confidence over the known in-bounds voxels of the box, rho
+//         ascending) / K^nd,
+//   D_p = |grad I^perp . n| (2D) or |grad I x n| (3D), I = channel mean,
+//         grad I by central differences where both neighbours are known,
+//         one-sided where one is, else 0; n = the difference of the known
+//         indicator across p (out of bounds counts as known), normalised.
+// All arithmetic is float64 without fused operations, in the same order as
+// the reference implementation, so the chosen targets agree bit for bit.
+#include "inpaint.hpp"
+
+namespace sfc {
+
+namespace {
+
+inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+sfc_status launched(const char* what) {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFC_OK : check_hip(e, what);
+}
+
+__device__ inline void coords_of(const Grid& g, int64_t v, int64_t* c) {
+    for (int i = 0; i < g.nd; i++) {
+        c[i] = v / g.stride[i];
+        v -= c[i] * g.stride[i];
+    }
+}
+
+__device__ inline double mean_intensity(const float* vol, int64_t v, int C) {
+    double s = 0.0;
+    for (int ch = 0; ch < C; ch++) s += (double)vol[v * C + ch];
+    return s / (double)C;
+}
+
+struct Cand {
+    double p, c;
+    int64_t id;
+};
+
+// a better than b: larger priority, then larger confidence, then lower id
+__device__ inline bool better(const Cand& a, const Cand& b) {
+    if (a.p != b.p) return a.p > b.p;
+    if (a.c != b.c) return a.c > b.c;
+    return a.id < b.id;
+}
+
+__device__ inline Cand shfl_cand(const Cand& x, int off) {
+    Cand y;
+    y.p = __shfl_xor(x.p, off, 64);
+    y.c = __shfl_xor(x.c, off, 64);
+    y.id = __shfl_xor(x.id, off, 64);
+    return y;
+}
+
+// Per block: the best front voxel by (P, C, -id) (order 0) or the lowest
+// front id (order 1, with P and C of that voxel), and the unknown count.
+__global__ __launch_bounds__(256) void priority_kernel(const float* __restrict__ vol,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const double* __restrict__ conf, Grid g,
+                                                       int order, Cand* __restrict__ part,
+                                                       unsigned long long* __restrict__ unknown) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Cand best{-1.0, -1.0, INT64_MAX};
+    int unk = 0;
+    if (v < g.nvox) {
+        if (!mask[v]) {
+            unk = 1;
+        } else {
+            int64_t c[kMaxDims];
+            coords_of(g, v, c);
+            bool front = false;
+            for (int i = 0; i < g.nd; i++) {
+                if (c[i] > 0 && !mask[v - g.stride[i]]) front = true;
+                if (c[i] + 1 < g.shape[i] && !mask[v + g.stride[i]]) front = true;
+            }
+            if (front) {
+                double cs = 0.0;
+                for (int rho = 0; rho < g.Kd; rho++) {
+                    int64_t u = 0;
+                    bool inb = true;
+                    int r = rho;
+                    for (int a = g.nd - 1; a >= 0; a--) {
+                        const int64_t x = c[a] + (r % g.K) - g.h;
+                        r /= g.K;
+                        if (x < 0 || x >= g.shape[a]) inb = false;
+                        u += x * g.stride[a];
+                    }
+                    if (inb && mask[u]) cs += conf[u];
+                }
+                const double Cp = cs / (double)g.Kd;
+                double Pp = 0.0;
+                if (order == 0) {
+                    double gr[kMaxDims], nr[kMaxDims], nn = 0.0;
+                    const double I0 = mean_intensity(vol, v, g.C);
+                    for (int i = 0; i < g.nd; i++) {
+                        const bool hasp = c[i] + 1 < g.shape[i], hasm = c[i] > 0;
+                        const int64_t vp = v + g.stride[i], vm = v - g.stride[i];
+                        const bool kp = hasp && mask[vp], km = hasm && mask[vm];
+                        if (kp && km)
+                            gr[i] = (mean_intensity(vol, vp, g.C) - mean_intensity(vol, vm, g.C)) / 2.0;
+                        else if (kp)
+                            gr[i] = mean_intensity(vol, vp, g.C) - I0;
+                        else if (km)
+                            gr[i] = I0 - mean_intensity(vol, vm, g.C);
+                        else
+                            gr[i] = 0.0;
+                        const int ip = hasp ? mask[vp] : 1, im = hasm ? mask[vm] : 1;
+                        nr[i] = (double)(ip - im);
+                        nn += nr[i] * nr[i];
+                    }
+                    double Dp = 0.0;
+                    if (nn > 0.0) {
+                        const double len = sqrt(nn);
+                        for (int i = 0; i < g.nd; i++) nr[i] = nr[i] / len;
+                        if (g.nd == 2) {
+                            Dp = fabs(gr[0] * nr[1] - gr[1] * nr[0]);
+                        } else {
+                            const double c0 = gr[1] * nr[2] - gr[2] * nr[1];
+                            const double c1 = gr[2] * nr[0] - gr[0] * nr[2];
+                            const double c2 = gr[0] * nr[1] - gr[1] * nr[0];
+                            Dp = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+                        }
+                    }
+                    Pp = Cp * Dp;
+                    best = Cand{Pp, Cp, v};
+                } else {
+                    // raster: only the id ranks; keep Cp for the confidence update
+                    best = Cand{0.0, 0.0, v};
+                    best.p = -Cp;   // carried, not compared (see reduce with order 1)
+                }
+            }
+        }
+    }
+    // block reduction
+    for (int off = 32; off > 0; off >>= 1) {
+        const Cand o = shfl_cand(best, off);
+        if (order == 0 ? better(o, best) : (o.id < best.id)) best = o;
+        unk += __shfl_xor(unk, off, 64);
+    }
+    __shared__ Cand sb[4];
+    __shared__ int su[4];
+    if ((threadIdx.x & 63) == 0) {
+        sb[threadIdx.x >> 6] = best;
+        su[threadIdx.x >> 6] = unk;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Cand b = sb[0];
+        int u = su[0];
+        for (int w = 1; w < 4; w++) {
+            if (order == 0 ? better(sb[w], b) : (sb[w].id < b.id)) b = sb[w];
+            u += su[w];
+        }
+        part[blockIdx.x] = b;
+        if (u) atomicAdd(unknown, (unsigned long long)u);
+    }
+}
+
+__global__ __launch_bounds__(256) void pick_kernel(const Cand* __restrict__ part, int64_t nb, int order,
+                                                   int64_t* __restrict__ centre, double* __restrict__ cpick) {
+    Cand best{-1.0, -1.0, INT64_MAX};
+    for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) {
+        const Cand o = part[i];
+        if (order == 0 ? better(o, best) : (o.id < best.id)) best = o;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const Cand o = shfl_cand(best, off);
+        if (order == 0 ? better(o, best) : (o.id < best.id)) best = o;
+    }
+    __shared__ Cand sb[4];
+    if ((threadIdx.x & 63) == 0) sb[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Cand b = sb[0];
+        for (int w = 1; w < 4; w++)
+            if (order == 0 ? better(sb[w], b) : (sb[w].id < b.id)) b = sb[w];
+        *centre = b.id == INT64_MAX ? -1 : b.id;
+        *cpick = order == 0 ? b.c : -b.p;
+    }
+}
+
+// Copy the chosen patch into the unknown in-bounds voxels of the target box,
+// mark them known and give them the target's confidence; log the iteration.
+__global__ void fill_kernel(float* __restrict__ vol, uint8_t* __restrict__ mask,
+                            double* __restrict__ conf, Grid g, const int64_t* __restrict__ centre,
+                            const int64_t* __restrict__ source, const float* __restrict__ cost,
+                            const double* __restrict__ cpick, int64_t it, int64_t cap,
+                            int64_t* __restrict__ lc, int64_t* __restrict__ ls,
+                            float* __restrict__ lcost) {
+    const int rho = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = *centre, s = *source;
+    if (rho == 0 && it < cap) {
+        lc[it] = p;
+        ls[it] = s;
+        lcost[it] = *cost;
+    }
+    if (rho >= g.Kd || p < 0 || s < 0) return;
+    int64_t cp[kMaxDims], cs[kMaxDims];
+    coords_of(g, p, cp);
+    coords_of(g, s, cs);
+    int64_t up = 0, us = 0;
+    bool inb = true;
+    int r = rho;
+    for (int a = g.nd - 1; a >= 0; a--) {
+        const int64_t o = (r % g.K) - g.h;
+        r /= g.K;
+        const int64_t x = cp[a] + o;
+        if (x < 0 || x >= g.shape[a]) inb = false;
+        up += x * g.stride[a];
+        us += (cs[a] + o) * g.stride[a];
+    }
+    if (!inb || mask[up]) return;
+    for (int ch = 0; ch < g.C; ch++) vol[up * g.C + ch] = vol[us * g.C + ch];
+    mask[up] = 1;
+    conf[up] = *cpick;
+}
+
+__global__ void conf_init_kernel(const uint8_t* __restrict__ mask, int64_t n, double* __restrict__ conf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) conf[i] = mask[i] ? 1.0 : 0.0;
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+}  // namespace
+
+size_t inpaint_part_bytes(const Grid& g) { return (size_t)blocks_for(g.nvox) * sizeof(Cand); }
+
+sfc_status launch_conf_init(const uint8_t* mask, const Grid& g, double* conf, hipStream_t st) {
+    conf_init_kernel<<<blocks_for(g.nvox), 256, 0, st>>>(mask, g.nvox, conf);
+    return launched("conf_init_kernel");
+}
+
+sfc_status launch_pick(const float* vol, const uint8_t* mask, const double* conf, const Grid& g,
+                       int order, void* part, unsigned long long* unknown, int64_t* centre,
+                       double* cpick, hipStream_t st) {
+    zero_u64_kernel<<<1, 1, 0, st>>>(unknown);
+    SFC_TRY(launched("zero_u64_kernel"));
+    const unsigned nb = blocks_for(g.nvox);
+    priority_kernel<<<nb, 256, 0, st>>>(vol, mask, conf, g, order, static_cast<Cand*>(part), unknown);
+    SFC_TRY(launched("priority_kernel"));
+    pick_kernel<<<1, 256, 0, st>>>(static_cast<const Cand*>(part), nb, order, centre, cpick);
+    return launched("pick_kernel");
+}
+
+sfc_status launch_fill(float* vol, uint8_t* mask, double* conf, const Grid& g, const int64_t* centre,
+                       const int64_t* source, const float* cost, const double* cpick, int64_t it,
+                       int64_t cap, int64_t* lc, int64_t* ls, float* lcost, hipStream_t st) {
+    fill_kernel<<<blocks_for(g.Kd), 256, 0, st>>>(vol, mask, conf, g, centre, source, cost, cpick, it,
+                                                  cap, lc, ls, lcost);
+    return launched("fill_kernel");
+}
+
+}  // namespace sfc
