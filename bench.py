@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="oracle full-scan queries timed")
+    ap.add_argument("--cpu-sample", type=int, default=48, help="oracle full-scan queries timed")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()

@@ -130,7 +130,7 @@ sfc_status sfc_extract_targets(const float *volume, const uint8_t *mask,
 /* Dictionary only (Section I: every fully known K^ndim patch lying inside the
  * volume), for the full-scan modes. The handle BORROWS `volume`: it must stay
  * alive and its dictionary patches unchanged until sfc_index_free. The mask
- * is read once. Returns SFC_EEMPTY if no patch is fully known. */
+ * is copied into the handle. Returns SFC_EEMPTY if no patch is fully known. */
 sfc_status sfc_dictionary_build(const float *volume, const uint8_t *mask,
                                 const sfc_geometry *g, int32_t K, const sfc_options *opt,
                                 sfc_index **out);
