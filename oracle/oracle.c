@@ -397,7 +397,11 @@ void orc_cov_matrix(const int64_t *sum, const int64_t *sumsq, int64_t nsub, int6
  * Then the rotations are applied as A <- J^T A J in two passes (all rows of
  * the rotating pairs: B_p = c A_p - s A_q, B_q = s A_p + c A_q; then all their
  * columns the same way), the pair's a_pq and a_qp are set to exactly 0, and
- * V <- V J by columns. tiny = 2^-100 * max_i |a_ii| of the input.
+ * V <- V J by columns. The two passes round the entries above and below the
+ * diagonal differently, so each round ends by copying the upper triangle onto
+ * the lower one: A stays exactly symmetric, and entry (i, j), i < j, is the
+ * row rotation of i's pair followed by the column rotation of j's pair.
+ * tiny = 2^-100 * max_i |a_ii| of the input.
  * Stops after a sweep with no rotation, or 60 sweeps. Returns the sweep count.
  * A (m*m, row-major) is overwritten; eigenvalues are its diagonal on return;
  * V (m*m, row-major) receives eigenvectors as columns. */
@@ -485,6 +489,8 @@ int orc_jacobi(double *A, int m, double *V)
                     V[(size_t)i * m + q] = s * x + c * y;
                 }
             }
+            for (int i = 0; i < m; i++)
+                for (int j = i + 1; j < m; j++) A[(size_t)j * m + i] = A[(size_t)i * m + j];
         }
         sweep++;
         if (rotations == 0) break;

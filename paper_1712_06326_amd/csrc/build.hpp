@@ -26,8 +26,10 @@ sfc_status launch_gram(const uint32_t* Xt, int P, int64_t nsp4, uint64_t* sum, u
 sfc_status launch_cov_matrix(const uint64_t* sum, const uint64_t* gram, int64_t nsub, int P,
                              const int32_t* elems, const int32_t* m, int S, int mmax, double* A,
                              hipStream_t st);
-// Eigenvectors into V, eigenvalues on A's diagonal; sweeps[S] (int32)
-sfc_status launch_jacobi(double* A, double* V, double* B, const int32_t* m, int S, int mmax,
+// Eigenvectors into V, eigenvalues on A's diagonal; sweeps[S] (int32).
+// scratch: jacobi_scratch_bytes(S, mmax) bytes of device memory.
+size_t jacobi_scratch_bytes(int S, int mmax);
+sfc_status launch_jacobi(double* A, double* V, void* scratch, const int32_t* m, int S, int mmax,
                          int32_t* sweeps, hipStream_t st);
 // int8 basis [S][mmax][D] (row-major per subset) from A/V
 sfc_status launch_basis(const double* A, const double* V, const int32_t* m, int S, int mmax,

@@ -188,193 +188,314 @@ __global__ void cov_matrix_kernel(const uint64_t* __restrict__ sum,
 }
 
 // ------------------------------------------------------------ Jacobi
-// One workgroup per subset. Rotations of one round act on disjoint index
-// pairs (round-robin pairing), so each round is two data-parallel phases:
-//   decide (c, s) per pair from the round's starting matrix;
-//   A <- J^T A J (rows then columns, pair entries zeroed) and V <- V J.
-// The operation sequence per element matches the documented algorithm
-// exactly (no fused multiply-add: the file is compiled with contraction off).
+// Round-robin Jacobi (disjoint pairs per round) on the packed upper triangle
+// of each subset's symmetric matrix. Per round:
+//   decide (c, s) per pair from the round's starting matrix, log it;
+//   rotate every 2x2 block (rows of pair a, columns of pair b), a <= b, in
+//   place: entry (x, y) above the diagonal is the row rotation of x's pair
+//   followed by the column rotation of y's pair, the value the full-matrix
+//   two-pass update gives above the diagonal (and mirrors below it).
+// The triangle lives in LDS; when it is larger, its first rows stay in global
+// memory. Eigenvectors are rebuilt afterwards by replaying the logged
+// rotations on the rows of V, which are independent of each other.
+// Arithmetic per entry matches the documented algorithm operation for
+// operation (the file is compiled with contraction off).
 constexpr int kJacThreads = 1024;
 constexpr int kJacMaxPairs = (kMaxSubsetElems + 1) / 2 + 1;
+constexpr int kJacTriLds = 19500;    // doubles of the triangle kept in LDS
+constexpr int kJacChunk = 4;         // sweeps per launch (rotation-log depth)
+constexpr int kJacMaxSweeps = 60;
 
-__global__ __launch_bounds__(kJacThreads) void jacobi_kernel(double* __restrict__ Aall,
-                                                              double* __restrict__ Vall,
-                                                              double* __restrict__ Ball,
-                                                              const int32_t* __restrict__ msz,
-                                                              int mmax, int32_t* __restrict__ sweeps) {
-    const int s = blockIdx.x;
+// state per subset: [0] sweeps done, [1] converged, [2] sweeps in this chunk
+struct JacState {
+    int32_t done, conv, nsw, pad;
+    double tiny;
+};
+
+__device__ inline int tri_index(int x, int y, int m) {   // x <= y
+    return x * (2 * m - x + 1) / 2 + (y - x);
+}
+
+// Entries [G, total) of the triangle in LDS, [0, G) in global memory
+// (kSplit = false: G = 0, everything in LDS).
+template <bool kSplit>
+struct TriStore {
+    double* lds;
+    double* glob;
+    int G, m;
+    __device__ double get(int x, int y) const {
+        const int t = x <= y ? tri_index(x, y, m) : tri_index(y, x, m);
+        if (!kSplit) return lds[t];
+        if (t >= G) return lds[t - G];
+        return glob[t];
+    }
+    __device__ void set(int x, int y, double v) const {
+        const int t = x <= y ? tri_index(x, y, m) : tri_index(y, x, m);
+        if (!kSplit) lds[t] = v;
+        else if (t >= G) lds[t - G] = v;
+        else glob[t] = v;
+    }
+};
+
+// pair k of round r (M even): (r, M-1) for k = 0, else ((r+k), (r-k)) mod M-1
+__device__ inline void round_pair(int r, int k, int M, int* p, int* q) {
+    int a, b;
+    if (k == 0) {
+        a = r;
+        b = M - 1;
+    } else {
+        a = r + k;
+        if (a >= M - 1) a -= M - 1;
+        b = r - k;
+        if (b < 0) b += M - 1;
+    }
+    *p = a < b ? a : b;
+    *q = a < b ? b : a;
+}
+
+// block u of the np x np upper triangle (row-major, diagonal included)
+__device__ inline void block_of(int u, int np, int* a, int* b) {
+    const float n2 = 2.0f * np + 1.0f;   // n2^2 - 8u is exact in float32
+    int r = (int)((n2 - sqrtf(n2 * n2 - 8.0f * u)) * 0.5f);
+    if (r < 0) r = 0;
+    if (r > np - 1) r = np - 1;
+    while (r > 0 && r * np - r * (r - 1) / 2 > u) r--;
+    while (r < np - 1 && (r + 1) * np - (r + 1) * r / 2 <= u) r++;
+    *a = r;
+    *b = r + (u - (r * np - r * (r - 1) / 2));
+}
+
+// One 2x2 block (rows of pair a, columns of pair b, a <= b) of a round.
+template <bool kSplit>
+__device__ inline void rotate_block(const TriStore<kSplit>& T, int a, int b, int m, const int* sp,
+                                const int* sq, const int* sact, const double* scs,
+                                const double* ssn) {
+    const int acta = sact[a], actb = sact[b];
+    if (!acta && !actb) return;
+    const int pa = sp[a], qa = sq[a], pb = sp[b], qb = sq[b];
+    const double ca = scs[a], sa = ssn[a], cb = scs[b], sb = ssn[b];
+    if (a == b) {
+        // both passes on the pair's own 2x2 block; a_pq -> 0
+        const double app = T.get(pa, pa), apq = T.get(pa, qa), aqq = T.get(qa, qa);
+        const double y00 = ca * app - sa * apq, y01 = ca * apq - sa * aqq;
+        const double y10 = sa * app + ca * apq, y11 = sa * apq + ca * aqq;
+        T.set(pa, pa, ca * y00 - sa * y01);
+        T.set(qa, qa, sa * y10 + ca * y11);
+        T.set(pa, qa, 0.0);
+        return;
+    }
+    const bool va = qa < m, vb = qb < m;
+    // X[i][j] = A(row i of pair a, column j of pair b)
+    double x00 = T.get(pa, pb);
+    double x01 = vb ? T.get(pa, qb) : 0.0;
+    double x10 = va ? T.get(qa, pb) : 0.0;
+    double x11 = (va && vb) ? T.get(qa, qb) : 0.0;
+    // rows by a, then columns by b: Z
+    double z00 = x00, z01 = x01, z10 = x10, z11 = x11;
+    if (acta) {
+        const double y00 = ca * z00 - sa * z10, y10 = sa * z00 + ca * z10;
+        const double y01 = ca * z01 - sa * z11, y11 = sa * z01 + ca * z11;
+        z00 = y00; z10 = y10; z01 = y01; z11 = y11;
+    }
+    if (actb) {
+        const double y00 = cb * z00 - sb * z01, y01 = sb * z00 + cb * z01;
+        const double y10 = cb * z10 - sb * z11, y11 = sb * z10 + cb * z11;
+        z00 = y00; z01 = y01; z10 = y10; z11 = y11;
+    }
+    // rows by b, then columns by a, on the transposed block: W,
+    // W[j][i] = new A(row j of pair b, column i of pair a)
+    double w00 = x00, w01 = x10, w10 = x01, w11 = x11;
+    if (actb) {
+        const double y00 = cb * w00 - sb * w10, y10 = sb * w00 + cb * w10;
+        const double y01 = cb * w01 - sb * w11, y11 = sb * w01 + cb * w11;
+        w00 = y00; w10 = y10; w01 = y01; w11 = y11;
+    }
+    if (acta) {
+        const double y00 = ca * w00 - sa * w01, y01 = sa * w00 + ca * w01;
+        const double y10 = ca * w10 - sa * w11, y11 = sa * w10 + ca * w11;
+        w00 = y00; w01 = y01; w10 = y10; w11 = y11;
+    }
+    T.set(pa, pb, pa < pb ? z00 : w00);
+    if (vb) T.set(pa, qb, pa < qb ? z01 : w10);
+    if (va) T.set(qa, pb, qa < pb ? z10 : w01);
+    if (va && vb) T.set(qa, qb, qa < qb ? z11 : w11);
+}
+
+__global__ __launch_bounds__(256) void jacobi_init_kernel(const double* __restrict__ Aall,
+                                                          double* __restrict__ Vall,
+                                                          double* __restrict__ Tall,
+                                                          const int32_t* __restrict__ msz, int mmax,
+                                                          int64_t tri_stride,
+                                                          JacState* __restrict__ state) {
+    const int s = blockIdx.y;
     const int m = msz[s];
-    double* A = Aall + (int64_t)s * mmax * mmax;
+    const double* A = Aall + (int64_t)s * mmax * mmax;
     double* V = Vall + (int64_t)s * mmax * mmax;
-    double* B = Ball + (int64_t)s * mmax * mmax;
-    const int M = m + (m & 1);
-    const int np = M / 2;
-    __shared__ int sp[kJacMaxPairs], sq[kJacMaxPairs], sact[kJacMaxPairs];
-    __shared__ double scs[kJacMaxPairs], ssn[kJacMaxPairs];
-    __shared__ double s_tiny;
-    __shared__ int s_rot;
-    const int tid = threadIdx.x;
-
-    for (int64_t i = tid; i < (int64_t)m * m; i += kJacThreads) {
+    double* T = Tall + (int64_t)s * tri_stride;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)m * m;
+         i += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(i / m), c = (int)(i % m);
         V[i] = (r == c) ? 1.0 : 0.0;
+        if (r <= c) T[tri_index(r, c, m)] = A[i];
     }
-    if (tid == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         double t = 0.0;
         for (int i = 0; i < m; i++) {
             const double a = fabs(A[(int64_t)i * m + i]);
             if (a > t) t = a;
         }
-        s_tiny = ldexp(t, -100);
+        state[s] = JacState{0, 0, 0, 0, ldexp(t, -100)};
     }
-    __syncthreads();
-    const double tiny = s_tiny;
+}
 
-    int sweep = 0;
-    while (sweep < 60) {
+template <bool kSplit>
+__global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
+    double* __restrict__ Tall, int64_t tri_stride, const int32_t* __restrict__ msz,
+    JacState* __restrict__ state, double2* __restrict__ logall, int64_t log_stride) {
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (state[s].conv) {
+        if (tid == 0) state[s].nsw = 0;
+        return;
+    }
+    const int m = msz[s];
+    const int M = m + (m & 1);
+    const int np = M / 2;
+    const int total = m * (m + 1) / 2;
+    const int G = total > kJacTriLds ? total - kJacTriLds : 0;
+    __shared__ double lds[kJacTriLds];
+    __shared__ int sp[kJacMaxPairs], sq[kJacMaxPairs], sact[kJacMaxPairs];
+    __shared__ double scs[kJacMaxPairs], ssn[kJacMaxPairs];
+    __shared__ int s_rot;
+    double* Tg = Tall + (int64_t)s * tri_stride;
+    double2* log = logall + (int64_t)s * log_stride;
+    for (int t = G + tid; t < total; t += kJacThreads) lds[t - G] = Tg[t];
+    const TriStore<kSplit> T{lds, Tg, G, m};
+    const double tiny = state[s].tiny;
+    const int done0 = state[s].done;
+    const int nblk = np * (np + 1) / 2;
+    __syncthreads();
+
+    int sw = 0;
+    bool conv = false;
+    while (sw < kJacChunk && done0 + sw < kJacMaxSweeps) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
         for (int r = 0; r < M - 1; r++) {
             if (tid < np) {
                 const int k = tid;
-                int a, b;
-                if (k == 0) {
-                    a = r;
-                    b = M - 1;
-                } else {
-                    a = (r + k) % (M - 1);
-                    b = (r - k + (M - 1)) % (M - 1);
-                }
-                const int p = a < b ? a : b, q = a < b ? b : a;
+                int p, q;
+                round_pair(r, k, M, &p, &q);
                 sp[k] = p;
                 sq[k] = q;
                 int act = 0;
+                double c = -1.0, sn = 0.0;
                 if (q < m) {
-                    const double apq = A[(int64_t)p * m + q];
-                    const double app = A[(int64_t)p * m + p], aqq = A[(int64_t)q * m + q];
+                    const double apq = T.get(p, q);
+                    const double app = T.get(p, p), aqq = T.get(q, q);
                     const double g = 100.0 * fabs(apq);
                     if (fabs(apq) <= tiny || (fabs(app) + g == fabs(app) && fabs(aqq) + g == fabs(aqq))) {
-                        A[(int64_t)p * m + q] = 0.0;
-                        A[(int64_t)q * m + p] = 0.0;
+                        T.set(p, q, 0.0);
                     } else {
                         const double theta = (aqq - app) / (2.0 * apq);
                         double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
                         if (theta < 0.0) t = -t;
-                        const double c = 1.0 / sqrt(1.0 + t * t);
-                        scs[k] = c;
-                        ssn[k] = t * c;
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
                         act = 1;
                         atomicAdd(&s_rot, 1);
                     }
                 }
+                scs[k] = c;
+                ssn[k] = sn;
                 sact[k] = act;
+                log[((int64_t)sw * (M - 1) + r) * np + k] = make_double2(c, sn);
             }
             __syncthreads();
-            // A <- J^T A J block by block: the 2x2 block at (rows of pair k1,
-            // columns of pair k2) depends only on itself. Rows are rotated
-            // first (when pair k1 rotates), then columns (when pair k2
-            // rotates), exactly the operations of the row pass followed by
-            // the column pass; blocks are disjoint, so the update is in place.
-            // V <- V J runs alongside on its own data.
-            // blocks: item i = k1*np + k2 with i = tid + it*kJacThreads, the
-            // pair indices advanced by constant steps (no division per item)
-            {
-                const int d1 = kJacThreads / np, d2 = kJacThreads % np;
-                int k1 = tid / np, k2 = tid % np;
-                constexpr int kBatch = 4;
-                while (k1 < np) {
-                    int bk1[kBatch], bk2[kBatch];
-                    double x[kBatch][4];
-#pragma unroll
-                    for (int u = 0; u < kBatch; u++) {
-                        bk1[u] = k1;
-                        bk2[u] = k2;
-                        if (k1 < np) {
-                            const int r0 = sp[k1], r1 = sq[k1], c0 = sp[k2], c1 = sq[k2];
-                            const bool vr1 = r1 < m, vc1 = c1 < m;
-                            x[u][0] = A[r0 * m + c0];
-                            x[u][1] = vc1 ? A[r0 * m + c1] : 0.0;
-                            x[u][2] = vr1 ? A[r1 * m + c0] : 0.0;
-                            x[u][3] = (vr1 && vc1) ? A[r1 * m + c1] : 0.0;
-                        }
-                        k1 += d1;
-                        k2 += d2;
-                        if (k2 >= np) {
-                            k2 -= np;
-                            k1++;
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < kBatch; u++) {
-                        const int a1 = bk1[u], a2 = bk2[u];
-                        if (a1 >= np) continue;
-                        double x00 = x[u][0], x01 = x[u][1], x10 = x[u][2], x11 = x[u][3];
-                        if (sact[a1]) {
-                            const double c = scs[a1], sn = ssn[a1];
-                            const double y00 = c * x00 - sn * x10, y10 = sn * x00 + c * x10;
-                            const double y01 = c * x01 - sn * x11, y11 = sn * x01 + c * x11;
-                            x00 = y00; x10 = y10; x01 = y01; x11 = y11;
-                        }
-                        if (sact[a2]) {
-                            const double c = scs[a2], sn = ssn[a2];
-                            const double y00 = c * x00 - sn * x01, y01 = sn * x00 + c * x01;
-                            const double y10 = c * x10 - sn * x11, y11 = sn * x10 + c * x11;
-                            x00 = y00; x01 = y01; x10 = y10; x11 = y11;
-                        }
-                        if (a1 == a2 && sact[a1]) {
-                            x01 = 0.0;
-                            x10 = 0.0;
-                        }
-                        const int r0 = sp[a1], r1 = sq[a1], c0 = sp[a2], c1 = sq[a2];
-                        const bool vr1 = r1 < m, vc1 = c1 < m;
-                        A[r0 * m + c0] = x00;
-                        if (vc1) A[r0 * m + c1] = x01;
-                        if (vr1) A[r1 * m + c0] = x10;
-                        if (vr1 && vc1) A[r1 * m + c1] = x11;
-                    }
-                }
-            }
-            // eigenvectors: item i = k*m + j, same stepping, loads batched
-            {
-                const int d1 = kJacThreads / m, d2 = kJacThreads % m;
-                int k = tid / m, j = tid % m;
-                constexpr int kVB = 8;
-                while (k < np) {
-                    int bk[kVB], bj[kVB];
-                    double xv[kVB], yv[kVB];
-#pragma unroll
-                    for (int u = 0; u < kVB; u++) {
-                        bk[u] = k;
-                        bj[u] = j;
-                        if (k < np && sact[k]) {
-                            xv[u] = V[j * m + sp[k]];
-                            yv[u] = V[j * m + sq[k]];
-                        }
-                        k += d1;
-                        j += d2;
-                        if (j >= m) {
-                            j -= m;
-                            k++;
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < kVB; u++) {
-                        const int kk = bk[u];
-                        if (kk >= np || !sact[kk]) continue;
-                        const double c = scs[kk], sn = ssn[kk];
-                        V[bj[u] * m + sp[kk]] = c * xv[u] - sn * yv[u];
-                        V[bj[u] * m + sq[kk]] = sn * xv[u] + c * yv[u];
-                    }
-                }
+            for (int u = tid; u < nblk; u += kJacThreads) {
+                int a, b;
+                block_of(u, np, &a, &b);
+                rotate_block(T, a, b, m, sp, sq, sact, scs, ssn);
             }
             __syncthreads();
         }
-        sweep++;
-        const int rot = s_rot;
+        sw++;
+        if (s_rot == 0) {
+            conv = true;
+            break;
+        }
         __syncthreads();
-        if (rot == 0) break;
     }
-    if (tid == 0) sweeps[s] = sweep;
+    __syncthreads();
+    for (int t = G + tid; t < total; t += kJacThreads) Tg[t] = lds[t - G];
+    if (tid == 0) {
+        state[s].done = done0 + sw;
+        state[s].nsw = sw;
+        state[s].conv = (conv || done0 + sw >= kJacMaxSweeps) ? 1 : 0;
+    }
+}
+
+// V <- V J for the logged rounds: one wave per row of V, the row in LDS; the
+// workgroup stages a batch of rounds' (c, s) in LDS for all its rows.
+constexpr int kRepRows = 16;
+constexpr int kRepStage = 4096;   // (c, s) entries staged per batch
+
+__global__ __launch_bounds__(kRepRows * 64) void jacobi_replay_kernel(
+    double* __restrict__ Vall, const int32_t* __restrict__ msz, int mmax,
+    const JacState* __restrict__ state, const double2* __restrict__ logall, int64_t log_stride) {
+    const int s = blockIdx.y;
+    const int nsw = state[s].nsw;
+    const int m = msz[s];
+    const int row0 = blockIdx.x * kRepRows;
+    if (nsw == 0 || row0 >= m) return;
+    const int M = m + (m & 1);
+    const int np = M / 2;
+    __shared__ double rows[kRepRows][kMaxSubsetElems];
+    __shared__ double2 stage[kRepStage];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = row0 + wave;
+    double* V = Vall + (int64_t)s * mmax * mmax;
+    const double2* log = logall + (int64_t)s * log_stride;
+    if (row < m)
+        for (int j = lane; j < m; j += 64) rows[wave][j] = V[(int64_t)row * m + j];
+    const int rounds = nsw * (M - 1);
+    const int per = kRepStage / np;   // rounds per batch (np <= 260)
+    for (int base = 0; base < rounds; base += per) {
+        const int nr = min(per, rounds - base);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nr * np; i += blockDim.x)
+            stage[i] = log[(int64_t)base * np + i];
+        __syncthreads();
+        if (row < m) {
+            for (int rr = 0; rr < nr; rr++) {
+                const int r = (base + rr) % (M - 1);
+                for (int k = lane; k < np; k += 64) {
+                    const double2 cs = stage[rr * np + k];
+                    if (cs.x < 0.0) continue;
+                    int p, q;
+                    round_pair(r, k, M, &p, &q);
+                    const double x = rows[wave][p], y = rows[wave][q];
+                    rows[wave][p] = cs.x * x - cs.y * y;
+                    rows[wave][q] = cs.y * x + cs.x * y;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    if (row < m)
+        for (int j = lane; j < m; j += 64) V[(int64_t)row * m + j] = rows[wave][j];
+}
+
+__global__ void jacobi_finish_kernel(double* __restrict__ Aall, const double* __restrict__ Tall,
+                                     int64_t tri_stride, const int32_t* __restrict__ msz, int mmax,
+                                     const JacState* __restrict__ state,
+                                     int32_t* __restrict__ sweeps) {
+    const int s = blockIdx.x;
+    const int m = msz[s];
+    double* A = Aall + (int64_t)s * mmax * mmax;
+    const double* T = Tall + (int64_t)s * tri_stride;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) A[(int64_t)i * m + i] = T[tri_index(i, i, m)];
+    if (threadIdx.x == 0) sweeps[s] = state[s].done;
 }
 
 // First D components by eigenvalue (descending, ties to the lower column),
@@ -470,11 +591,44 @@ sfc_status launch_cov_matrix(const uint64_t* sum, const uint64_t* gram, int64_t 
     return launched("cov_matrix_kernel");
 }
 
-sfc_status launch_jacobi(double* A, double* V, double* B, const int32_t* m, int S, int mmax,
+size_t jacobi_scratch_bytes(int S, int mmax) {
+    const int64_t Mx = mmax + (mmax & 1);
+    const size_t tri = (size_t)S * ((size_t)mmax * (mmax + 1) / 2) * sizeof(double);
+    const size_t log = (size_t)S * kJacChunk * (Mx - 1) * (Mx / 2) * sizeof(double2);
+    return ((tri + 255) & ~size_t(255)) + ((log + 255) & ~size_t(255)) + (size_t)S * sizeof(JacState);
+}
+
+sfc_status launch_jacobi(double* A, double* V, void* scratch, const int32_t* m, int S, int mmax,
                          int32_t* sweeps, hipStream_t st) {
     if (mmax > kMaxSubsetElems) return fail(SFC_EUNSUPPORTED, "subset larger than 518 elements");
-    jacobi_kernel<<<S, kJacThreads, 0, st>>>(A, V, B, m, mmax, sweeps);
-    return launched("jacobi_kernel");
+    const int64_t Mx = mmax + (mmax & 1);
+    const int64_t tri_stride = (int64_t)mmax * (mmax + 1) / 2;
+    const int64_t log_stride = (int64_t)kJacChunk * (Mx - 1) * (Mx / 2);
+    const size_t tri = (size_t)S * tri_stride * sizeof(double);
+    const size_t log = (size_t)S * log_stride * sizeof(double2);
+    char* base = static_cast<char*>(scratch);
+    double* T = reinterpret_cast<double*>(base);
+    double2* lg = reinterpret_cast<double2*>(base + ((tri + 255) & ~size_t(255)));
+    JacState* state =
+        reinterpret_cast<JacState*>(base + ((tri + 255) & ~size_t(255)) + ((log + 255) & ~size_t(255)));
+    jacobi_init_kernel<<<dim3(blocks_for((int64_t)mmax * mmax), S), 256, 0, st>>>(A, V, T, m, mmax,
+                                                                                 tri_stride, state);
+    SFC_TRY(launched("jacobi_init_kernel"));
+    const unsigned rblocks = (unsigned)((mmax + kRepRows - 1) / kRepRows);
+    for (int c = 0; c < (kJacMaxSweeps + kJacChunk - 1) / kJacChunk; c++) {
+        if (tri_stride > kJacTriLds)
+            jacobi_sweeps_kernel<true><<<S, kJacThreads, 0, st>>>(T, tri_stride, m, state, lg,
+                                                                  log_stride);
+        else
+            jacobi_sweeps_kernel<false><<<S, kJacThreads, 0, st>>>(T, tri_stride, m, state, lg,
+                                                                   log_stride);
+        SFC_TRY(launched("jacobi_sweeps_kernel"));
+        jacobi_replay_kernel<<<dim3(rblocks, S), kRepRows * 64, 0, st>>>(V, m, mmax, state, lg,
+                                                                        log_stride);
+        SFC_TRY(launched("jacobi_replay_kernel"));
+    }
+    jacobi_finish_kernel<<<S, 256, 0, st>>>(A, T, tri_stride, m, mmax, state, sweeps);
+    return launched("jacobi_finish_kernel");
 }
 
 sfc_status launch_basis(const double* A, const double* V, const int32_t* m, int S, int mmax,

@@ -283,12 +283,13 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
     // basis per subset
     SFC_TRY(dev_alloc((void**)&ix->basis, (size_t)S * mmax * D, "bases"));
     if (!bases_host) {
-        double *A = nullptr, *V = nullptr, *B = nullptr;
+        double *A = nullptr, *V = nullptr;
+        void* B = nullptr;
         int32_t* sweeps = nullptr;
         const size_t mat = (size_t)S * mmax * mmax * sizeof(double);
         SFC_TRY(tmp.alloc((void**)&A, mat, "covariance matrices"));
         SFC_TRY(tmp.alloc((void**)&V, mat, "eigenvectors"));
-        SFC_TRY(tmp.alloc((void**)&B, mat, "rotation buffer"));
+        SFC_TRY(tmp.alloc(&B, jacobi_scratch_bytes(S, mmax), "eigensolver scratch"));
         SFC_TRY(tmp.alloc((void**)&sweeps, S * sizeof(int32_t), "sweep counts"));
         SFC_TRY(launch_cov_matrix(reinterpret_cast<uint64_t*>(ix->sum), gram, ix->nsub, P,
                                   ix->elems, ix->msz, S, mmax, A, st));
