@@ -3,12 +3,17 @@
 One step runs the whole hot path over one synthetic workload: fill front and
 target extraction, the SFC multi-index build (byte codes, covariance, Jacobi,
 int8 basis, MFMA projection, keys, radix sort), the index query of every
-front target, and the full float32 scan of every front target (plus the
-reduced-precision scan when it is available). `value` is front queries
-answered per second by that whole step; the per-form rates are reported
-beside it.
+front target, and the full float32 scan plus the reduced-precision (bf16
+MFMA) scan of every front target. `value` is front queries answered per
+second by that whole step; the per-form rates are reported beside it.
+
+The default workload is the 1024x1024 RGB image (n ~ 0.9e6). After its timed
+steps, one pass over the 512^3 volume (n ~ 1.25e8) reports the index query
+rate over its whole front and the float32 scan rate on a seeded sample of
+4096 front targets (`n1e8`).
 
   python bench.py [--steps K] [--warmup W] [--workload config2] [--no-cpu-baseline]
+                  [--no-n1e8] [--calib-copy]
 
 Prints one JSON line. Only N=1 is supported: this build runs on one GPU.
 """
@@ -26,15 +31,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU = 157.3  # TFLOP/s: 256 CU x 128 FP32 lanes x 2 flop x 2.4 GHz (published vector peak)
-PEAK_BF16_MFMA = 2500.0  # TFLOP/s dense
+# Published MI355X peaks. FP32 vector: 256 CU x 128 lanes x 2 flop x 2.4 GHz.
+PEAK_FP32_VALU = 157.3   # TFLOP/s
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s, dense
 PEAK_HBM = 8000.0        # GB/s
 
 WORKLOADS = {
-    "config2": dict(gen="config2", K=9, D=8, L=4, key_bits=21, window=32, curve="morton",
-                    label="config2_1024sq_rgb_blobs10_K9 (n~0.9e6)"),
     "config1": dict(gen="config1", K=9, D=8, L=4, key_bits=8, window=32, curve="morton",
-                    label="config1_256sq_gray_hole32_K9"),
+                    scan_sample=0, bf16=True, label="config1_256sq_gray_hole32_K9 (n~6e4)"),
+    "config2": dict(gen="config2", K=9, D=8, L=4, key_bits=21, window=32, curve="morton",
+                    scan_sample=0, bf16=True, label="config2_1024sq_rgb_blobs10_K9 (n~0.9e6)"),
+    "config3": dict(gen="config3", K=7, D=10, L=6, key_bits=8, window=32, curve="hilbert",
+                    scan_sample=4096, bf16=True, label="config3_256cube_tomo_voids5_K7 (n~1.4e7)"),
+    "config4": dict(gen="config4", K=5, D=8, L=4, key_bits=8, window=32, curve="morton",
+                    scan_sample=4096, bf16=False,
+                    label="config4_512cube_phantom_u16_K5 (n~1.25e8)"),
 }
 
 
@@ -51,6 +62,8 @@ def source_hash(names):
 
 
 def load_traffic(kernel_key, workload, src_hash):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current source of the kernel."""
     p = os.path.join(ROOT, "profiles", f"{kernel_key}_{workload}_traffic.json")
     if not os.path.exists(p):
         return None
@@ -60,6 +73,31 @@ def load_traffic(kernel_key, workload, src_hash):
     return d.get("bytes_per_launch")
 
 
+class Workload:
+    """Synthetic volume on the device plus its front targets."""
+
+    def __init__(self, name, torch, native, synth):
+        self.name, self.cfg = name, WORKLOADS[name]
+        t0 = time.time()
+        data = getattr(synth, self.cfg["gen"])()
+        log(f"generated {self.cfg['label']} in {time.time() - t0:.1f}s")
+        self.vol_h, self.mask_h = data["volume"], data["mask"]
+        dev = torch.device("cuda:0")
+        self.vol = torch.from_numpy(self.vol_h).to(dev)
+        self.mask = torch.from_numpy(self.mask_h).to(dev)
+        self.K = self.cfg["K"]
+        self.opts = dict(key_bits=self.cfg["key_bits"], window=self.cfg["window"],
+                         curve=self.cfg["curve"])
+        f = native.fill_front(self.mask)
+        self.Q = int(f.numel())
+        k = self.cfg["scan_sample"]
+        if k and k < self.Q:
+            sel = np.sort(np.random.default_rng(5).choice(self.Q, k, replace=False))
+            self.sel = torch.from_numpy(sel).to(dev)
+        else:
+            self.sel = None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +105,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-n1e8", action="store_true", help="skip the n~1.25e8 pass")
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle full-scan queries timed")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (HBM counter calibration)")
@@ -79,16 +118,6 @@ def main():
     import torch
     from paper_1712_06326_amd import native, synth
 
-    wl = WORKLOADS[args.workload]
-    t0 = time.time()
-    data = getattr(synth, wl["gen"])()
-    log(f"generated {wl['label']} in {time.time() - t0:.1f}s")
-    vol_h, mask_h = data["volume"], data["mask"]
-    dev = torch.device("cuda:0")
-    vol = torch.from_numpy(vol_h).to(dev)
-    mask = torch.from_numpy(mask_h).to(dev)
-    K = wl["K"]
-    opts = dict(key_bits=wl["key_bits"], window=wl["window"], curve=wl["curve"])
     stream = torch.cuda.current_stream()
 
     def ev():
@@ -96,97 +125,141 @@ def main():
         e.record(stream)
         return e
 
-    def step(record):
-        e0 = ev()
-        f = native.fill_front(mask)
-        t, m = native.extract_targets(vol, mask, K, f)
-        e1 = ev()
-        ix = native.Index(vol, mask, K, reduced_dim=wl["D"], n_curves=wl["L"], **opts)
-        e2 = ev()
+    w = Workload(args.workload, torch, native, synth)
+    cfg, K = w.cfg, w.K
+
+    def step(record, ktimes):
+        e = [ev()]
+        f = native.fill_front(w.mask)
+        t, m = native.extract_targets(w.vol, w.mask, K, f)
+        e.append(ev())
+        ix = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], timing=True,
+                          **w.opts)
+        e.append(ev())
         bi_x, bc_x = ix.query(t, m, "index")
-        e3 = ev()
-        bi_s, bc_s = ix.query(t, m, "fp32")
-        e4 = ev()
-        bi_r, bc_r = ix.query(t, m, "bf16")
-        e5 = ev()
-        out = dict(Q=f.numel(), n=ix.info.n, t=t, m=m, f=f, bi_x=bi_x, bc_x=bc_x, bi_s=bi_s,
-                   bc_s=bc_s, bi_r=bi_r, bc_r=bc_r, fallback=ix.fallbacks())
+        kt = dict(ix.kernel_times())
+        e.append(ev())
+        ts, ms = (t, m) if w.sel is None else (t[w.sel].contiguous(), m[w.sel].contiguous())
+        bi_s, bc_s = ix.query(ts, ms, "fp32")
+        kt.update(ix.kernel_times())
+        e.append(ev())
+        out = dict(n=ix.info.n, t=ts, m=ms, bi_x=bi_x, bc_x=bc_x, bi_s=bi_s, bc_s=bc_s)
+        if cfg["bf16"]:
+            bi_r, bc_r = ix.query(ts, ms, "bf16")
+            kr = ix.kernel_times()
+            kt.update({k: v for k, v in kr.items() if k != "scan_fp32_kernel"})
+            e.append(ev())
+            out.update(bi_r=bi_r, bc_r=bc_r, fallback=ix.fallbacks())
         if record is not None:
-            record.append((e0, e1, e2, e3, e4, e5))
+            record.append(e)
+            ktimes.append(kt)
         ix.close()
         return out
 
     # autotune the float32 scan's tile shape once on this workload (the
     # choice is remembered for every later handle of the same shape)
-    f0 = native.fill_front(mask)
-    t0_, m0_ = native.extract_targets(vol, mask, K, f0)
-    ix0 = native.Index(vol, mask, K)
+    f0 = native.fill_front(w.mask)
+    t0_, m0_ = native.extract_targets(w.vol, w.mask, K, f0)
+    if w.sel is not None:
+        t0_, m0_ = t0_[w.sel].contiguous(), m0_[w.sel].contiguous()
+    ix0 = native.Index(w.vol, w.mask, K)
     chosen = ix0.autotune(t0_, m0_)
     ix0.close()
+    del f0, t0_, m0_
     log(f"autotuned float32-scan shape: {chosen}")
     for _ in range(args.warmup):
-        step(None)
+        step(None, None)
     torch.cuda.synchronize()
-    marks = []
+    marks, ktimes = [], []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        res = step(marks)
+        res = step(marks, ktimes)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms_step = 1e3 * wall / args.steps
-    phases = np.array([[a.elapsed_time(b) for a, b in zip(mk[:-1], mk[1:])] for mk in marks])
-    ph = phases.mean(axis=0)
-    Q, n = res["Q"], res["n"]
+    ph = np.array([[a.elapsed_time(b) for a, b in zip(mk[:-1], mk[1:])] for mk in marks]).mean(0)
+    kavg = {k: float(np.mean([kt[k][1] / kt[k][0] for kt in ktimes])) for k in ktimes[0]}
+    Q, n = w.Q, res["n"]
+    Qs = int(res["m"].shape[0])
     m_h = res["m"].cpu().numpy()
-    known_elems = float(m_h.sum()) * vol_h.shape[-1]
+    C = w.vol_h.shape[-1]
+    P = K ** (w.mask_h.ndim) * C
+    known_elems = float(m_h.sum()) * C
 
-    # agreement of the index with the full scan (recall@1, acceleration error)
-    bi_x, bc_x = res["bi_x"].cpu().numpy(), res["bc_x"].cpu().numpy()
+    # index vs float32 scan on the scanned queries: recall@1, acceleration error
+    bi_x, bc_x = res["bi_x"], res["bc_x"]
+    if w.sel is not None:
+        bi_x, bc_x = bi_x[w.sel], bc_x[w.sel]
+    bi_x, bc_x = bi_x.cpu().numpy(), bc_x.cpu().numpy()
     bi_s, bc_s = res["bi_s"].cpu().numpy(), res["bc_s"].cpu().numpy()
     recall = float(np.mean(bi_x == bi_s))
     ok = bc_s > 0
     ae = float(np.mean(np.sqrt(bc_x[ok].astype(np.float64)) / np.sqrt(bc_s[ok]) - 1.0)) * 100
 
-    bi_r, bc_r = res["bi_r"].cpu().numpy(), res["bc_r"].cpu().numpy()
-    red_agree = float(np.mean((bi_r == bi_s) & (bc_r.view(np.uint32) == bc_s.view(np.uint32))))
-    scan_ms = ph[3]
+    # rooflines of the dominant kernels, from their own launch durations
     scan_flops = 3.0 * known_elems * n
-    scan_tflops = scan_flops / (scan_ms * 1e-3) / 1e12
-    traffic = load_traffic("scan_fp32", args.workload, source_hash(["k_scan.hip"]))
+    roofs = {"scan_fp32_kernel": {
+        "bound": "alu", "kernel": "scan_fp32_kernel",
+        "achieved": scan_flops / (kavg["scan_fp32_kernel"] * 1e-3) / 1e12,
+        "peak": PEAK_FP32_VALU, "unit": "TFLOP/s",
+        "traffic": load_traffic("scan_fp32", args.workload, source_hash(["k_scan.hip"])),
+        "work_per_launch": f"{scan_flops:.4g} flop = 3 x {known_elems:.0f} known elements x n"}}
+    if cfg["bf16"]:
+        gemm_flops = 2.0 * 3 * P * n * Qs
+        for k in ("filter_kernel<1>", "filter_kernel<2>"):
+            if k in kavg:
+                roofs[k] = {
+                    "bound": "mfma", "kernel": k,
+                    "achieved": gemm_flops / (kavg[k] * 1e-3) / 1e12,
+                    "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
+                    "traffic": load_traffic("filter_bf16_pass" + k[-2], args.workload,
+                                            source_hash(["k_mfma_scan.hip"])),
+                    "work_per_launch": f"{gemm_flops:.4g} flop = 2 x 3P x n x Q"}
+    dom = max(roofs, key=lambda k: kavg.get(k, 0.0))
+    for r in roofs.values():
+        r["achieved"] = round(r["achieved"], 3)
+        r["frac"] = round(r["achieved"] / r["peak"], 4)
+        r["avg_ms"] = round(kavg[r["kernel"]], 3)
+
+    phase_names = ["front_extract", "index_build", "index_query", "fp32_scan"]
+    if cfg["bf16"]:
+        phase_names.append("bf16_scan")
+    forms = {
+        "index_qps": round(Q / (ph[2] * 1e-3), 1),
+        "index_qps_with_build": round(Q / ((ph[1] + ph[2]) * 1e-3), 1),
+        "fp32_scan_qps": round(Qs / (ph[3] * 1e-3), 1),
+        "phase_ms": {k: round(float(v), 3) for k, v in zip(phase_names, ph)},
+        "kernel_avg_ms": {k: round(v, 3) for k, v in kavg.items()},
+        "fp32_scan_shape": chosen,
+        "scan_queries": Qs,
+        "index_recall_at_1_pct": round(100 * recall, 3),
+        "index_acceleration_error_pct": round(ae, 4),
+        "rooflines": {k: v for k, v in roofs.items() if k != dom},
+    }
+    if cfg["bf16"]:
+        bi_r, bc_r = res["bi_r"].cpu().numpy(), res["bc_r"].cpu().numpy()
+        forms["bf16_scan_qps"] = round(Qs / (ph[4] * 1e-3), 1)
+        forms["bf16_vs_fp32_agreement_pct"] = round(
+            100 * float(np.mean((bi_r == bi_s) & (bc_r.view(np.uint32) == bc_s.view(np.uint32)))), 3)
+        forms["bf16_fallback_queries"] = int(res["fallback"])
 
     line = {
-        "metric": "queries/s at n=1e6 (SFC index vs GPU brute force), argmin agreement %",
+        "metric": "queries/s at n=1e6,1e8 (SFC index vs GPU brute force), argmin agreement %",
         "value": round(Q / (ms_step * 1e-3), 2),
         "unit": "queries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl["label"], "n": n, "queries": Q, "K": K,
-                   "reduced_dim": wl["D"], "n_curves": wl["L"], "key_bits": wl["key_bits"],
-                   "window": wl["window"], "curve": wl["curve"]},
-        "forms": {
-            "index_qps": round(Q / (ph[2] * 1e-3), 1),
-            "index_qps_with_build": round(Q / ((ph[1] + ph[2]) * 1e-3), 1),
-            "fp32_scan_qps": round(Q / (scan_ms * 1e-3), 1),
-            "bf16_scan_qps": round(Q / (ph[4] * 1e-3), 1),
-            "bf16_vs_fp32_agreement_pct": round(100 * red_agree, 3),
-            "bf16_fallback_queries": int(res["fallback"]),
-            "phase_ms": {"front_extract": round(ph[0], 3), "index_build": round(ph[1], 3),
-                         "index_query": round(ph[2], 3), "fp32_scan": round(ph[3], 3),
-                         "bf16_scan": round(ph[4], 3)},
-            "fp32_scan_shape": chosen,
-            "index_recall_at_1_pct": round(100 * recall, 3),
-            "index_acceleration_error_pct": round(ae, 4),
-        },
-        "roofline": {"bound": "alu", "kernel": "scan_fp32_kernel",
-                     "achieved": round(scan_tflops, 3), "peak": PEAK_FP32_VALU,
-                     "unit": "TFLOP/s", "frac": round(scan_tflops / PEAK_FP32_VALU, 4),
-                     "traffic": traffic},
+        "config": {"workload": cfg["label"], "n": n, "queries": Q, "K": K,
+                   "reduced_dim": cfg["D"], "n_curves": cfg["L"], "key_bits": cfg["key_bits"],
+                   "window": cfg["window"], "curve": cfg["curve"]},
+        "forms": forms,
+        "roofline": roofs[dom],
     }
 
     if args.calib_copy:
-        src = torch.ones(1 << 27, dtype=torch.float32, device=dev)
+        src = torch.ones(1 << 27, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
@@ -195,13 +268,12 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(7)
-        k = min(args.cpu_sample, Q)
-        sel = np.sort(rng.choice(Q, k, replace=False))
-        f_h = res["f"].cpu().numpy()[sel]
+        k = min(args.cpu_sample, Qs)
+        sel = np.sort(rng.choice(Qs, k, replace=False))
         t_h = res["t"].cpu().numpy()[sel]
-        d_h = oracle.dictionary(mask_h, K)
+        d_h = oracle.dictionary(w.mask_h, K)
         tc = time.perf_counter()
-        ob, oc = oracle.brute(vol_h, mask_h.shape, K, d_h, t_h, m_h[sel])
+        ob, oc = oracle.brute(w.vol_h, w.mask_h.shape, K, d_h, t_h, m_h[sel])
         cpu_s = time.perf_counter() - tc
         agree = float(np.mean((ob == bi_s[sel]) & (oc.view(np.uint32) == bc_s[sel].view(np.uint32))))
         line["cpu_baseline"] = {
@@ -209,9 +281,64 @@ def main():
             "sample": f"{k} seeded front queries of the same workload through the oracle's "
                       f"float32 full scan (n={n}), single thread, {cpu_s:.1f}s; index build "
                       f"and index queries excluded (under 0.1% of the oracle's per-query time)"}
-        line["forms"]["fp32_vs_oracle_agreement_pct"] = round(100 * agree, 2)
-        line["forms"]["oracle_sample_centres"] = [int(x) for x in f_h]
+        forms["fp32_vs_oracle_agreement_pct"] = round(100 * agree, 2)
+
+    if args.workload == "config2" and not args.no_n1e8:
+        del w, res
+        torch.cuda.empty_cache()
+        line["n1e8"] = large_pass(torch, native, synth, ev)
     print(json.dumps(line), flush=True)
+
+
+def large_pass(torch, native, synth, ev):
+    """One pass over the 512^3 volume: build, index query of the whole front,
+    float32 scan of a seeded 4096-target sample (each query form timed on its
+    second run)."""
+    w = Workload("config4", torch, native, synth)
+    cfg, K = w.cfg, w.K
+    f = native.fill_front(w.mask)
+    t, m = native.extract_targets(w.vol, w.mask, K, f)
+    e0 = ev()
+    ix = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], timing=True,
+                      **w.opts)
+    e1 = ev()
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    log(f"n~1.25e8: index built in {build_ms:.0f} ms")
+    for _ in range(2):
+        a = ev()
+        bi_x, bc_x = ix.query(t, m, "index")
+        b = ev()
+        torch.cuda.synchronize()
+    idx_ms = a.elapsed_time(b)
+    ts, ms = t[w.sel].contiguous(), m[w.sel].contiguous()
+    for _ in range(2):
+        a = ev()
+        bi_s, bc_s = ix.query(ts, ms, "fp32")
+        b = ev()
+        torch.cuda.synchronize()
+    scan_ms = a.elapsed_time(b)
+    kt = ix.kernel_times()
+    n = ix.info.n
+    ix.close()
+    bx, cx = bi_x[w.sel].cpu().numpy(), bc_x[w.sel].cpu().numpy()
+    bs, cs = bi_s.cpu().numpy(), bc_s.cpu().numpy()
+    ok = cs > 0
+    known = float(ms.sum().item())
+    scan_tf = 3.0 * known * n / (kt["scan_fp32_kernel"][1] * 1e-3) / 1e12
+    out = {"workload": cfg["label"], "n": n, "queries": w.Q, "scan_queries": int(ms.shape[0]),
+           "index_build_ms": round(build_ms, 1),
+           "index_qps": round(w.Q / (idx_ms * 1e-3), 1),
+           "fp32_scan_qps": round(ms.shape[0] / (scan_ms * 1e-3), 2),
+           "fp32_scan_tflops": round(scan_tf, 2),
+           "fp32_scan_frac_of_fp32_peak": round(scan_tf / PEAK_FP32_VALU, 4),
+           "index_recall_at_1_pct": round(100 * float(np.mean(bx == bs)), 3),
+           "index_acceleration_error_pct": round(
+               float(np.mean(np.sqrt(cx[ok].astype(np.float64)) / np.sqrt(cs[ok]) - 1)) * 100, 4),
+           "index_cost_never_below_scan": bool(np.all(cx >= cs))}
+    del w, t, m, ts, ms
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

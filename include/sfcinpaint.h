@@ -80,6 +80,9 @@ typedef struct {
     int32_t scan_variant;  /* float32-scan tile shape: 0 = default or the one
                               sfc_autotune chose, k >= 1 = the k-th shape */
     void *stream;          /* hipStream_t; NULL = default stream */
+    int32_t timing;        /* 1: record HIP events around the main kernels of
+                              each sfc_query call (sfc_query_kernel_times);
+                              default 0 */
 } sfc_options;
 
 typedef struct sfc_index sfc_index;  /* opaque */
@@ -193,6 +196,24 @@ sfc_status sfc_autotune(sfc_index *idx, const float *targets, const uint8_t *tar
 /* Statistics of the last sfc_query call on this handle (host values):
  * n_fallback = queries a reduced-precision scan could not certify. */
 sfc_status sfc_query_stats(const sfc_index *idx, int64_t *n_fallback_host);
+
+/* Duration of one kernel of the last sfc_query call. */
+typedef struct {
+    const char *kernel;    /* kernel name (static string owned by the library) */
+    int32_t launches;      /* launches timed */
+    float ms;              /* their total duration (HIP events on the handle's stream) */
+} sfc_kernel_time;
+
+/* Kernel durations of the last sfc_query call on this handle, one entry per
+ * kernel, recorded only when the handle's options.timing was 1 (else
+ * *count_host = 0). The float32 scan records "scan_fp32_kernel", the bf16
+ * scan "filter_kernel<1>", "filter_kernel<2>" and "list_rescore_kernel" (plus
+ * the float32 scan of its fallback queries), the index query
+ * "prologue_kernel", "search_kernel" and "rescore_kernel". Writes
+ * min(count, capacity) entries to times_host and the number of kernels to
+ * *count_host. Synchronises the handle's stream. */
+sfc_status sfc_query_kernel_times(const sfc_index *idx, sfc_kernel_time *times_host,
+                                  int32_t capacity, int32_t *count_host);
 
 /* Handle description. */
 sfc_status sfc_index_info_get(const sfc_index *idx, sfc_index_info *info_host);

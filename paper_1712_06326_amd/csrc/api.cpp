@@ -96,6 +96,37 @@ static sfc_status check_geometry(const sfc_geometry* g, int K) {
     return SFC_OK;
 }
 
+sfc_status KernelTimer::begin(const char* name, hipStream_t st) {
+    if (!on) return SFC_OK;
+    if (used == (int)marks.size()) {
+        Mark mk;
+        SFC_HIP(hipEventCreate(&mk.a));
+        hipError_t e = hipEventCreate(&mk.b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(mk.a);
+            return check_hip(e, "hipEventCreate");
+        }
+        marks.push_back(mk);
+    }
+    marks[used].name = name;
+    SFC_HIP(hipEventRecord(marks[used].a, st));
+    return SFC_OK;
+}
+
+sfc_status KernelTimer::end(hipStream_t st) {
+    if (!on) return SFC_OK;
+    SFC_HIP(hipEventRecord(marks[used].b, st));
+    used++;
+    return SFC_OK;
+}
+
+KernelTimer::~KernelTimer() {
+    for (auto& mk : marks) {
+        (void)hipEventDestroy(mk.a);
+        (void)hipEventDestroy(mk.b);
+    }
+}
+
 sfc_options resolve_options(const sfc_options* in) {
     sfc_options o;
     sfc_options_default(&o);
@@ -185,7 +216,9 @@ sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int
     SFC_TRY(launch_fill_u64(best_dev, Q, ~0ull, ix->st));
     ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best_dev, ix->opt.query_block,
                ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant};
-    return launch_scan_fp32(g, a, ix->st);
+    SFC_TRY(ix->timer.begin("scan_fp32_kernel", ix->st));
+    SFC_TRY(launch_scan_fp32(g, a, ix->st));
+    return ix->timer.end(ix->st);
 }
 
 }  // namespace sfc
@@ -354,6 +387,7 @@ sfc_status sfc_query(sfc_index* ix, const float* targets, const uint8_t* target_
     if (!targets || !target_masks || !best_id || !best_cost)
         return fail(SFC_EINVAL, "sfc_query: null pointer");
     ix->last_fallback = 0;
+    ix->timer.reset(ix->opt.timing != 0);
     switch (mode) {
     case SFC_MODE_BRUTE_FP32: {
         SFC_TRY(ix->best.reserve((size_t)Q * sizeof(uint64_t), "query results"));
@@ -409,6 +443,7 @@ sfc_status sfc_autotune(sfc_index* ix, const float* targets, const uint8_t* targ
     hipEvent_t e0, e1;
     SFC_HIP(hipEventCreate(&e0));
     SFC_HIP(hipEventCreate(&e1));
+    ix->timer.reset(false);
     const int saved = ix->tuned_variant, saved_opt = ix->opt.scan_variant;
     ix->opt.scan_variant = 0;
     int bestv = 0;
@@ -447,6 +482,29 @@ sfc_status sfc_query_stats(const sfc_index* ix, int64_t* n_fallback) {
     clear_error();
     if (!ix || !n_fallback) return fail(SFC_EINVAL, "null pointer");
     *n_fallback = ix->last_fallback;
+    return SFC_OK;
+}
+
+sfc_status sfc_query_kernel_times(const sfc_index* ix, sfc_kernel_time* times, int32_t capacity,
+                                  int32_t* count) {
+    clear_error();
+    if (!ix || !count || (capacity > 0 && !times)) return fail(SFC_EINVAL, "null pointer");
+    if (capacity < 0) return fail(SFC_EINVAL, "capacity must be >= 0");
+    const KernelTimer& tm = ix->timer;
+    std::vector<sfc_kernel_time> out;
+    for (int i = 0; i < tm.used; i++) {
+        const KernelTimer::Mark& mk = tm.marks[i];
+        SFC_HIP(hipEventSynchronize(mk.b));
+        float ms = 0.0f;
+        SFC_HIP(hipEventElapsedTime(&ms, mk.a, mk.b));
+        size_t k = 0;
+        while (k < out.size() && std::strcmp(out[k].kernel, mk.name) != 0) k++;
+        if (k == out.size()) out.push_back(sfc_kernel_time{mk.name, 0, 0.0f});
+        out[k].launches++;
+        out[k].ms += ms;
+    }
+    for (size_t k = 0; k < out.size() && (int32_t)k < capacity; k++) times[k] = out[k];
+    *count = (int32_t)out.size();
     return SFC_OK;
 }
 

@@ -19,6 +19,26 @@ struct Scratch {
     ~Scratch();
 };
 
+// HIP-event timing of a handle's main query kernels (options.timing = 1):
+// begin/end bracket one launch on the handle's stream; the events are pooled
+// and reused by the next query.
+struct KernelTimer {
+    struct Mark {
+        const char* name = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
+    };
+    std::vector<Mark> marks;
+    int used = 0;
+    bool on = false;
+    void reset(bool enable) {
+        used = 0;
+        on = enable;
+    }
+    sfc_status begin(const char* name, hipStream_t st);
+    sfc_status end(hipStream_t st);
+    ~KernelTimer();
+};
+
 sfc_options resolve_options(const sfc_options* in);
 void remember_variant(int nd, int K, int C, int v);
 int recalled_variant(int nd, int K, int C);
@@ -66,6 +86,7 @@ struct sfc_index {
     sfc::Scratch rowmask, best, qtmp, tpad, red;
     int64_t last_fallback = 0;
     int tuned_variant = 0;           // float32-scan shape chosen by sfc_autotune
+    sfc::KernelTimer timer;
 
     ~sfc_index();
 };

@@ -47,19 +47,20 @@ __device__ inline uint16_t bf16_bits_of_int(int v) {
 __global__ void dict_operand_kernel(const uint8_t* __restrict__ xq, const uint32_t* __restrict__ dict,
                                     int64_t n, const int32_t* __restrict__ elem_off, int P, int C,
                                     int Kp, uint16_t* __restrict__ B) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t npad = (n + kMfmaTile - 1) / kMfmaTile * kMfmaTile;
-    if (i >= npad * Kp) return;
-    const int64_t c = i / Kp;
-    const int k = (int)(i - c * Kp);
-    const int e = k / 3, j = k - 3 * e;
-    int v = 0;
-    if (c < n && e < P) {
-        const int x = (int)xq[(int64_t)dict[c] * C + elem_off[e]] - 128;
-        const int sq = x * x;
-        v = (j == 0) ? x : (j == 1 ? (sq >> 7) : (sq & 127));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad * Kp;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / Kp;
+        const int k = (int)(i - c * Kp);
+        const int e = k / 3, j = k - 3 * e;
+        int v = 0;
+        if (c < n && e < P) {
+            const int x = (int)xq[(int64_t)dict[c] * C + elem_off[e]] - 128;
+            const int sq = x * x;
+            v = (j == 0) ? x : (j == 1 ? (sq >> 7) : (sq & 127));
+        }
+        B[i] = bf16_bits_of_int(v);
     }
-    B[i] = bf16_bits_of_int(v);
 }
 
 // A[q][3e + j], T2[q] = sum_known t'^2, kq[q] = known elements, flag[q] = 1
@@ -276,7 +277,8 @@ sfc_status launch_dict_operand(const uint8_t* xq, const uint32_t* dict, int64_t 
                                const int32_t* elem_off, int P, int C, uint16_t* B, hipStream_t st) {
     const int64_t Kp = mfma_kp(P);
     const int64_t npad = (n + kMfmaTile - 1) / kMfmaTile * kMfmaTile;
-    dict_operand_kernel<<<blocks_for(npad * Kp), 256, 0, st>>>(xq, dict, n, elem_off, P, C, (int)Kp, B);
+    const unsigned nb = (unsigned)std::min<int64_t>(1 << 20, (npad * Kp + 255) / 256);
+    dict_operand_kernel<<<nb, 256, 0, st>>>(xq, dict, n, elem_off, P, C, (int)Kp, B);
     return launched("dict_operand_kernel");
 }
 

@@ -446,10 +446,16 @@ sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t 
     p += (size_t)Q * 8 * ix->L;
     int32_t* qsub = reinterpret_cast<int32_t*>(p);
     const QueryIndexView v = view_of(ix);
+    SFC_TRY(ix->timer.begin("prologue_kernel", st));
     SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, st));
+    SFC_TRY(ix->timer.end(st));
+    SFC_TRY(ix->timer.begin("search_kernel", st));
     SFC_TRY(launch_query_search(v, qsub, qkeys, Q, wstart, st));
-    return launch_query_rescore(v, ix->vol, t, rm, qpad, qsub, wstart, Q, best_id, best_cost, cand,
-                                ncand, st);
+    SFC_TRY(ix->timer.end(st));
+    SFC_TRY(ix->timer.begin("rescore_kernel", st));
+    SFC_TRY(launch_query_rescore(v, ix->vol, t, rm, qpad, qsub, wstart, Q, best_id, best_cost, cand,
+                                 ncand, st));
+    return ix->timer.end(st);
 }
 
 sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int32_t* subset,

@@ -33,6 +33,7 @@ __global__ void scatter_results_kernel(const uint64_t* __restrict__ best, const 
 }
 
 constexpr int kCap = 2048;   // candidates kept per query
+constexpr double kMaxOperandBytes = 32.0 * (1ull << 30);   // bf16 dictionary operand
 
 }  // namespace
 
@@ -49,6 +50,9 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
     SFC_TRY(ensure_elem_offsets(ix));
     const int64_t Kp = mfma_kp(P);
     const int64_t npad = (ix->n + kMfmaTile - 1) / kMfmaTile * kMfmaTile;
+    if ((double)npad * Kp * 2 > kMaxOperandBytes)
+        return fail(SFC_EUNSUPPORTED,
+                    "reduced-precision scan: dictionary operand above 32 GiB; use SFC_MODE_BRUTE_FP32");
     if (!ix->mfma_B) {
         SFC_TRY(dev_alloc((void**)&ix->mfma_B, (size_t)npad * Kp * 2, "reduced-precision operand"));
         SFC_TRY(launch_dict_operand(ix->xq, ix->dict, ix->n, ix->elem_off, P, g.C, ix->mfma_B, st));
@@ -97,14 +101,20 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
     fa.cnt = cnt;
     fa.list = list;
     fa.cap = kCap;
+    SFC_TRY(ix->timer.begin("filter_kernel<1>", st));
     SFC_TRY(launch_filter(fa, 1, st));
+    SFC_TRY(ix->timer.end(st));
     SFC_TRY(launch_threshold(eqmin, kq, flag, ix->qparams, Q, thr, st));
+    SFC_TRY(ix->timer.begin("filter_kernel<2>", st));
     SFC_TRY(launch_filter(fa, 2, st));
+    SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->rowmask.reserve((size_t)qpad_rm * g.rows * sizeof(uint32_t), "row masks"));
     uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
     SFC_TRY(launch_pack_rowmask(m, g, Q, rm, st));
+    SFC_TRY(ix->timer.begin("list_rescore_kernel", st));
     SFC_TRY(launch_list_rescore(g, ix->vol, t, rm, qpad_rm, list, cnt, thr, kCap, Q, best_id,
                                 best_cost, fb, st));
+    SFC_TRY(ix->timer.end(st));
     // queries the filter could not settle go through the float32 scan
     SFC_TRY(launch_compact(fb, Q, fidx, nullptr, Q, nfb_dev, cscratch, st));
     int64_t nfb = 0;

@@ -35,7 +35,12 @@ class Geometry(C.Structure):
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("key_bits", C.c_int32), ("window", C.c_int32),
                 ("curve", C.c_int32), ("rescore_top", C.c_int32), ("certify", C.c_int32),
-                ("query_block", C.c_int32), ("scan_variant", C.c_int32), ("stream", C.c_void_p)]
+                ("query_block", C.c_int32), ("scan_variant", C.c_int32), ("stream", C.c_void_p),
+                ("timing", C.c_int32)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("kernel", C.c_char_p), ("launches", C.c_int32), ("ms", C.c_float)]
 
 
 class IndexInfo(C.Structure):
@@ -71,6 +76,7 @@ _SIG = {
     "sfc_query_candidates": (ST, [P, P, P, I64, P, P]),
     "sfc_query_coords": (ST, [P, P, P, I64, P, P]),
     "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
+    "sfc_query_kernel_times": (ST, [P, P, I32, C.POINTER(C.c_int32)]),
     "sfc_autotune": (ST, [P, P, P, I64, C.POINTER(C.c_int32)]),
     "sfc_index_info_get": (ST, [P, C.POINTER(IndexInfo)]),
     "sfc_index_dictionary": (ST, [P, P]),
@@ -128,7 +134,7 @@ def geometry(mask: torch.Tensor, channels: int) -> Geometry:
 
 
 def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
-            query_block=0, scan_variant=0) -> Options:
+            query_block=0, scan_variant=0, timing=False) -> Options:
     o = Options()
     _L.sfc_options_default(C.byref(o))
     o.key_bits = key_bits
@@ -139,6 +145,7 @@ def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
     o.query_block = query_block
     o.scan_variant = scan_variant
     o.stream = _stream()
+    o.timing = 1 if timing else 0
     return o
 
 
@@ -222,6 +229,15 @@ class Index:
         v = C.c_int32()
         _check(_L.sfc_autotune(self._h, _ptr(t), _ptr(m), m.shape[0], C.byref(v)))
         return v.value
+
+    def kernel_times(self) -> dict:
+        """{kernel: (launches, total ms)} of the last query (timing=True)."""
+        cap = 16
+        arr = (KernelTime * cap)()
+        n = C.c_int32()
+        _check(_L.sfc_query_kernel_times(self._h, arr, cap, C.byref(n)))
+        return {arr[i].kernel.decode(): (arr[i].launches, arr[i].ms)
+                for i in range(min(n.value, cap))}
 
     def fallbacks(self) -> int:
         n = C.c_int64()

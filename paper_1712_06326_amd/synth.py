@@ -190,10 +190,11 @@ def _gauss_blur3(vol, sigma):
 def _sphere_mask(shape, frac, r_range, rng, start=None):
     miss = np.zeros(shape, dtype=bool) if start is None else start.copy()
     total = float(np.prod(shape))
+    count = int(miss.sum())
     zz = np.arange(shape[0])
     yy = np.arange(shape[1])
     xx = np.arange(shape[2])
-    while miss.sum() / total < frac:
+    while count / total < frac:
         r = rng.uniform(*r_range)
         c = [rng.uniform(0, s) for s in shape]
         lo = [max(0, int(c[i] - r) - 1) for i in range(3)]
@@ -201,7 +202,10 @@ def _sphere_mask(shape, frac, r_range, rng, start=None):
         dz = (zz[lo[0]:hi[0]] - c[0])[:, None, None]
         dy = (yy[lo[1]:hi[1]] - c[1])[None, :, None]
         dx = (xx[lo[2]:hi[2]] - c[2])[None, None, :]
-        miss[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] |= dz * dz + dy * dy + dx * dx <= r * r
+        sub = miss[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        ball = dz * dz + dy * dy + dx * dx <= r * r
+        count += int(np.count_nonzero(ball & ~sub))
+        sub |= ball
     return miss
 
 
