@@ -10,10 +10,12 @@ second by that whole step; the per-form rates are reported beside it.
 The default workload is the 1024x1024 RGB image (n ~ 0.9e6). After its timed
 steps, one pass over the 512^3 volume (n ~ 1.25e8) reports the index query
 rate over its whole front and the float32 scan rate on a seeded sample of
-4096 front targets (`n1e8`).
+4096 front targets (`n1e8`), and 16 uneven images (sides 256-1024, 1-3
+channels) report the batched, graph-replayed float32 scan (`batch`);
+`--workload config5` times that batch over 64 images (sides 256-2048).
 
   python bench.py [--steps K] [--warmup W] [--workload config2] [--no-cpu-baseline]
-                  [--no-n1e8] [--calib-copy]
+                  [--no-n1e8] [--no-batch] [--calib-copy]
 
 Prints one JSON line. Only N=1 is supported: this build runs on one GPU.
 """
@@ -46,6 +48,8 @@ WORKLOADS = {
     "config4": dict(gen="config4", K=5, D=8, L=4, key_bits=8, window=32, curve="morton",
                     scan_sample=4096, bf16=False,
                     label="config4_512cube_phantom_u16_K5 (n~1.25e8)"),
+    "config5": dict(gen="config5", K=9, n_images=64, sides=(256, 2048),
+                    label="config5_64_images_256-2048_C1-3_K9"),
 }
 
 
@@ -106,6 +110,7 @@ def main():
     ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-n1e8", action="store_true", help="skip the n~1.25e8 pass")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-images pass")
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle full-scan queries timed")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (HBM counter calibration)")
@@ -124,6 +129,22 @@ def main():
         e = torch.cuda.Event(enable_timing=True)
         e.record(stream)
         return e
+
+    if args.workload == "config5":
+        cfg = WORKLOADS["config5"]
+        res = batch_pass(torch, native, synth, ev, cfg["n_images"], cfg["sides"], args.steps,
+                         args.warmup)
+        line = {
+            "metric": "queries/s at n=1e6,1e8 (SFC index vs GPU brute force), argmin agreement %",
+            "value": res["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["ms_per_replay"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": cfg["label"], "images": cfg["n_images"], "K": cfg["K"],
+                       "queries": res["queries"]},
+            "forms": res}
+        print(json.dumps(line), flush=True)
+        return
 
     w = Workload(args.workload, torch, native, synth)
     cfg, K = w.cfg, w.K
@@ -149,7 +170,7 @@ def main():
             kr = ix.kernel_times()
             kt.update({k: v for k, v in kr.items() if k != "scan_fp32_kernel"})
             e.append(ev())
-            out.update(bi_r=bi_r, bc_r=bc_r, fallback=ix.fallbacks())
+            out.update(bi_r=bi_r, bc_r=bc_r, fallback=ix.fallbacks(), tiles=ix.filter_tiles())
         if record is not None:
             record.append(e)
             ktimes.append(kt)
@@ -205,16 +226,18 @@ def main():
         "traffic": load_traffic("scan_fp32", args.workload, source_hash(["k_scan.hip"])),
         "work_per_launch": f"{scan_flops:.4g} flop = 3 x {known_elems:.0f} known elements x n"}}
     if cfg["bf16"]:
-        gemm_flops = 2.0 * 3 * P * n * Qs
-        for k in ("filter_kernel<1>", "filter_kernel<2>"):
+        # the filter GEMM's useful width: C codes plus 2 norm columns per pixel
+        kd = K ** w.mask_h.ndim
+        gemm_flops = 2.0 * kd * (C + 2) * n * Qs
+        for k in ("filter_kernel<list>", "filter_kernel<min>"):
             if k in kavg:
+                key = "filter_bf16_" + k[len("filter_kernel<"):-1]
                 roofs[k] = {
                     "bound": "mfma", "kernel": k,
                     "achieved": gemm_flops / (kavg[k] * 1e-3) / 1e12,
                     "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
-                    "traffic": load_traffic("filter_bf16_pass" + k[-2], args.workload,
-                                            source_hash(["k_mfma_scan.hip"])),
-                    "work_per_launch": f"{gemm_flops:.4g} flop = 2 x 3P x n x Q"}
+                    "traffic": load_traffic(key, args.workload, source_hash(["k_mfma_scan.hip"])),
+                    "work_per_launch": f"{gemm_flops:.4g} flop = 2 x K^d(C+2) x n x Q"}
     dom = max(roofs, key=lambda k: kavg.get(k, 0.0))
     for r in roofs.values():
         r["achieved"] = round(r["achieved"], 3)
@@ -242,6 +265,7 @@ def main():
         forms["bf16_vs_fp32_agreement_pct"] = round(
             100 * float(np.mean((bi_r == bi_s) & (bc_r.view(np.uint32) == bc_s.view(np.uint32)))), 3)
         forms["bf16_fallback_queries"] = int(res["fallback"])
+        forms["bf16_filter_tiles"] = list(res["tiles"])
 
     line = {
         "metric": "queries/s at n=1e6,1e8 (SFC index vs GPU brute force), argmin agreement %",
@@ -287,7 +311,66 @@ def main():
         del w, res
         torch.cuda.empty_cache()
         line["n1e8"] = large_pass(torch, native, synth, ev)
+    if args.workload == "config2" and not args.no_batch:
+        torch.cuda.empty_cache()
+        line["batch"] = batch_pass(torch, native, synth, ev, 16, (256, 1024), 3, 1)
     print(json.dumps(line), flush=True)
+
+
+def batch_pass(torch, native, synth, ev, n_images, sides, steps, warmup):
+    """Uneven images answered together: every front target of every image by
+    one persistent float32-scan launch, replayed from a HIP graph (tile-shape
+    set from the batch autotuner). Two images are checked against the
+    single-image scan."""
+    t0 = time.time()
+    imgs = synth.config5(n_images=n_images, side_range=sides)
+    log(f"generated {n_images} images in {time.time() - t0:.1f}s")
+    K = 9
+    vols = [torch.from_numpy(d["volume"]).cuda() for d in imgs]
+    masks = [torch.from_numpy(d["mask"]).cuda() for d in imgs]
+    ts, ms, counts = [], [], []
+    for v, m in zip(vols, masks):
+        f = native.fill_front(m)
+        t, mm = native.extract_targets(v, m, K, f)
+        ts.append(t.reshape(-1))
+        ms.append(mm)
+        counts.append(int(f.numel()))
+    t = torch.cat(ts).contiguous()
+    m = torch.cat(ms).contiguous()
+    Q = sum(counts)
+    b = native.Batch(vols, masks, K)
+    out = (torch.empty(Q, dtype=torch.int64, device="cuda"),
+           torch.empty(Q, dtype=torch.float32, device="cuda"))
+    shape = b.autotune(t, m, counts, out)
+    for _ in range(warmup):
+        b.query(t, m, counts, out)
+    torch.cuda.synchronize()
+    a = ev()
+    for _ in range(steps):
+        b.query(t, m, counts, out)
+    e = ev()
+    torch.cuda.synchronize()
+    ms_rep = a.elapsed_time(e) / steps
+    st = b.stats()
+    # the first two images against the single-image float32 scan
+    agree, toff, qoff = [], 0, 0
+    for i, d in enumerate(imgs[:2]):
+        C = d["volume"].shape[-1]
+        q = counts[i]
+        ix = native.Index(vols[i], masks[i], K)
+        bi, bc = ix.query(t[toff: toff + q * K * K * C].reshape(q, K * K, C).contiguous(),
+                          m[qoff: qoff + q].contiguous(), "fp32")
+        agree.append(bool(torch.equal(bi, out[0][qoff: qoff + q]) and
+                          torch.equal(bc.view(torch.int32), out[1][qoff: qoff + q].view(torch.int32))))
+        ix.close()
+        toff += q * K * K * C
+        qoff += q
+    b.close()
+    return {"images": n_images, "sides": list(sides), "queries": Q,
+            "pixels": int(sum(x.numel() for x in masks)),
+            "ms_per_replay": round(ms_rep, 3), "qps": round(Q / (ms_rep * 1e-3), 1),
+            "work_items": st["work_items"], "graph_replays": st["graph_replays"],
+            "shape_set": shape, "equals_single_image_scan": all(agree)}
 
 
 def large_pass(torch, native, synth, ev):

@@ -197,6 +197,14 @@ sfc_status sfc_autotune(sfc_index *idx, const float *targets, const uint8_t *tar
  * n_fallback = queries a reduced-precision scan could not certify. */
 sfc_status sfc_query_stats(const sfc_index *idx, int64_t *n_fallback_host);
 
+/* Work of the last SFC_MODE_BRUTE_BF16 query on this handle (host values):
+ * *pass1_host = (query tile, candidate tile) pairs of the filter's first
+ * pass (all of them), *pass2_host = pairs a second pass revisited (those
+ * whose tile minimum can reach a query's threshold). On a handle with an SFC
+ * index the index answer's exact cost seeds the threshold and there is no
+ * second pass (*pass2_host = 0). Both 0 after other modes. */
+sfc_status sfc_query_filter_tiles(const sfc_index *idx, int64_t *pass1_host, int64_t *pass2_host);
+
 /* Duration of one kernel of the last sfc_query call. */
 typedef struct {
     const char *kernel;    /* kernel name (static string owned by the library) */
@@ -207,8 +215,9 @@ typedef struct {
 /* Kernel durations of the last sfc_query call on this handle, one entry per
  * kernel, recorded only when the handle's options.timing was 1 (else
  * *count_host = 0). The float32 scan records "scan_fp32_kernel", the bf16
- * scan "filter_kernel<1>", "filter_kernel<2>" and "list_rescore_kernel" (plus
- * the float32 scan of its fallback queries), the index query
+ * scan "filter_kernel<list>" and "list_rescore_kernel", plus
+ * "filter_kernel<min>" on a dictionary-only handle (its first pass) and
+ * "scan_fp32_kernel" for the queries it could not settle, the index query
  * "prologue_kernel", "search_kernel" and "rescore_kernel". Writes
  * min(count, capacity) entries to times_host and the number of kernels to
  * *count_host. Synchronises the handle's stream. */
@@ -258,6 +267,45 @@ void sfc_index_free(sfc_index *idx);
 sfc_status sfc_inpaint(float *volume, uint8_t *mask, const sfc_geometry *g, int32_t K,
                        sfc_order order, sfc_mode mode, sfc_index *idx,
                        const sfc_options *opt, int64_t *n_iters_host, sfc_fill_log *log);
+
+/* ---- Batches of images (many independent 2D images of uneven size, each
+ * with its own dictionary: Section I's full scan per image), answered by one
+ * persistent float32-scan launch over (image, query block, tile chunk) work
+ * items. A query is captured once in a HIP graph on the batch's own stream
+ * and replayed while its layout (per-image counts and the four buffer
+ * pointers) stays the same; any change recaptures. Ordering with the
+ * caller's stream (options.stream) uses events. */
+typedef struct sfc_batch sfc_batch;  /* opaque */
+
+/* volumes/masks: host arrays of n_images device pointers (each borrowed as
+ * in sfc_dictionary_build); geoms: host array of n_images geometries, each
+ * 2D with 1 to 3 channels. K in {5, 7, 9, 11}. SFC_EEMPTY if an image has no
+ * fully known patch. */
+sfc_status sfc_batch_create(int32_t n_images, const float *const *volumes_host,
+                            const uint8_t *const *masks_host, const sfc_geometry *geoms_host,
+                            int32_t K, const sfc_options *opt, sfc_batch **out);
+
+/* Best patch of every target of every image. targets: the concatenation over
+ * images of float32 [count_i, K*K, channels_i]; target_masks: uint8
+ * [sum count_i, K*K]; best_id int64 / best_cost float32 [sum count_i], ids
+ * local to each image (its voxel ids). counts_host: n_images counts (>= 0).
+ * Same cost, order and tie rule as sfc_query in SFC_MODE_BRUTE_FP32. */
+sfc_status sfc_batch_query(sfc_batch *b, const float *targets, const uint8_t *target_masks,
+                           const int64_t *counts_host, int64_t *best_id, float *best_cost);
+
+/* Autotuner for the batched scan: times each tile-shape set (one replay
+ * after a warm-up run each) on these queries and keeps the fastest;
+ * *chosen_host receives it (0..2). The outputs hold the last run's answers. */
+sfc_status sfc_batch_autotune(sfc_batch *b, const float *targets, const uint8_t *target_masks,
+                              const int64_t *counts_host, int64_t *best_id, float *best_cost,
+                              int32_t *chosen_host);
+
+/* Graph replays so far, work items of the current graph, tile-shape set. */
+sfc_status sfc_batch_stats(const sfc_batch *b, int64_t *graph_replays_host,
+                           int64_t *work_items_host, int32_t *shape_host);
+
+/* Release the batch (NULL is a no-op). */
+void sfc_batch_free(sfc_batch *b);
 
 #ifdef __cplusplus
 }

@@ -387,6 +387,7 @@ sfc_status sfc_query(sfc_index* ix, const float* targets, const uint8_t* target_
     if (!targets || !target_masks || !best_id || !best_cost)
         return fail(SFC_EINVAL, "sfc_query: null pointer");
     ix->last_fallback = 0;
+    ix->last_pass1_tiles = ix->last_pass2_tiles = 0;
     ix->timer.reset(ix->opt.timing != 0);
     switch (mode) {
     case SFC_MODE_BRUTE_FP32: {
@@ -482,6 +483,14 @@ sfc_status sfc_query_stats(const sfc_index* ix, int64_t* n_fallback) {
     clear_error();
     if (!ix || !n_fallback) return fail(SFC_EINVAL, "null pointer");
     *n_fallback = ix->last_fallback;
+    return SFC_OK;
+}
+
+sfc_status sfc_query_filter_tiles(const sfc_index* ix, int64_t* pass1, int64_t* pass2) {
+    clear_error();
+    if (!ix || !pass1 || !pass2) return fail(SFC_EINVAL, "null pointer");
+    *pass1 = ix->last_pass1_tiles;
+    *pass2 = ix->last_pass2_tiles;
     return SFC_OK;
 }
 

@@ -85,6 +85,7 @@ struct sfc_index {
     // ---- per-call scratch
     sfc::Scratch rowmask, best, qtmp, tpad, red;
     int64_t last_fallback = 0;
+    int64_t last_pass1_tiles = 0, last_pass2_tiles = 0;   // bf16 filter tiles of the last query
     int tuned_variant = 0;           // float32-scan shape chosen by sfc_autotune
     sfc::KernelTimer timer;
 

@@ -1,19 +1,23 @@
 // Full scan of the dictionary in float32 (Section I: evaluate the masked L2
 // cost of every fully known patch and keep the global minimum).
 //
-// Mapping on gfx950: one workgroup of 256 lanes owns a "line tile" of 256
-// consecutive candidate centres along the fastest axis and stages the K^(nd-1)
-// volume rows those patches touch in LDS. Each lane is one candidate. A block
-// of QB queries is processed at a time: their targets and per-row known-masks
-// are wave-uniform and come through scalar loads, so each known element costs
-// one v_sub and one v_fma per lane per query, with the LDS row values reused
-// across the QB accumulators. The per-candidate order (rows ascending, column
-// ascending, channel ascending, fused multiply-add from +0) is exactly the
-// reference cost order, so the cost bits are those of the definition. The
-// (cost, id) minimum is reduced per wave, merged per query in LDS and then
-// once per workgroup in global memory with a 64-bit atomic min on
-// (cost bits << 32 | id), which is order independent.
-#include "common.hpp"
+// Mapping on gfx950: candidates are walked along the fastest axis in "line
+// tiles" of 64 * NX consecutive centres; each lane owns NX adjacent centres
+// and reads their patch rows straight from memory (a row of NX candidates is
+// K + NX - 1 voxels, shared through L1/L2). A block of QB queries is processed
+// at a time: their targets and per-row known-masks are wave-uniform and come
+// through scalar loads, so each known element costs one v_sub and one v_fma
+// per lane per query per candidate. The per-candidate order (rows ascending,
+// column ascending, channel ascending, fused multiply-add from +0) is exactly
+// the definition's, so the cost bits are those of the definition. The
+// (cost, id) minimum is kept per lane, reduced per wave, merged per query in
+// LDS and then once per workgroup in global memory with a 64-bit atomic min
+// on (cost bits << 32 | id), which is order independent.
+//
+// Two entry kernels share the body: one image, with an XCD-aware grid; and a
+// batch of images of uneven size (each its own dictionary), a persistent grid
+// walking (image, query block, tile chunk) work items.
+#include "batch.hpp"
 
 namespace sfc {
 
@@ -30,23 +34,6 @@ typedef const __attribute__((address_space(4))) uint32_t cu32_as4;
 __device__ inline float ldu(const float* p) { return *(cfloat_as4*)p; }
 __device__ inline uint32_t ldu(const uint32_t* p) { return *(cu32_as4*)p; }
 
-struct ScanParams {
-    const float* vol;
-    const uint8_t* valid;
-    const float* t;
-    const uint32_t* rowmask;
-    uint64_t* best;
-    int64_t Q;
-    int64_t shape[kMaxDims];
-    int64_t stride[kMaxDims];
-    int64_t line_len;        // interior extent along the fastest axis
-    int64_t tiles_per_line;
-    int64_t n_tiles;
-    int64_t tiles_per_wg;
-    int64_t q_per_wg;
-    int64_t qpad;            // row-mask stride (queries padded to the block size)
-    int64_t n_chunks, chunks_per_xcd, q_splits;
-};
 
 // Each lane owns NX adjacent candidates of a 64*NX-wide line tile; their
 // patch rows are read straight from memory (L1/L2 resident), so waves run
@@ -55,31 +42,18 @@ struct ScanParams {
 // (strict comparison in ascending id order keeps the lowest id), reduces it
 // over the wave, and the workgroup merges the four results in LDS before one
 // global atomic per query.
+// Queries [q0, q1) against line tiles [tl0, tl1) of one image; the whole
+// workgroup calls it (it synchronises). sred: LDS [4][QB].
 template <int ND, int K, int C, int QB, int NX>
-__global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
+__device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int64_t q1, int64_t tl0,
+                                           int64_t tl1, uint64_t* sred) {
     constexpr int H = (K - 1) / 2;
     constexpr int ROWS = (ND == 2) ? K : K * K;
     constexpr int RW = K * C;
     constexpr int SEG = (K + NX - 1) * C;     // floats of one patch row for NX candidates
-    __shared__ uint64_t sred[kLanes / 64][QB];
-
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    // XCD-aware mapping: workgroups are dispatched to the 8 XCDs round-robin,
-    // so block b runs on XCD b % 8. Each XCD gets a contiguous band of tile
-    // chunks (all query splits of it), keeping its band of the volume in
-    // that XCD's L2.
-    const int64_t b = blockIdx.x;
-    const int64_t xcd = b % kXcds, slot = b / kXcds;
-    const int64_t chunk = xcd * p.chunks_per_xcd + slot % p.chunks_per_xcd;
-    const int64_t qs = slot / p.chunks_per_xcd;
-    if (chunk >= p.n_chunks || qs >= p.q_splits) return;
-    const int64_t q0 = qs * p.q_per_wg;
-    const int64_t q1 = min(p.Q, q0 + p.q_per_wg);
-    if (q0 >= q1) return;
-    const int64_t tl0 = chunk * p.tiles_per_wg;
-    const int64_t tl1 = min(p.n_tiles, tl0 + p.tiles_per_wg);
 
     for (int64_t qb = q0; qb < q1; qb += QB) {
         uint32_t bcost[QB], bid[QB];
@@ -178,18 +152,104 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
                 const uint64_t o = (uint64_t)__shfl_xor((long long)pk, off, 64);
                 pk = o < pk ? o : pk;
             }
-            if (lane == 0) sred[wave][qi] = pk;
+            if (lane == 0) sred[wave * QB + qi] = pk;
         }
         __syncthreads();
         if (tid < QB && qb + tid < q1) {
-            uint64_t best = sred[0][tid];
+            uint64_t best = sred[tid];
 #pragma unroll
-            for (int w = 1; w < kLanes / 64; w++) best = sred[w][tid] < best ? sred[w][tid] : best;
+            for (int w = 1; w < kLanes / 64; w++)
+                best = sred[w * QB + tid] < best ? sred[w * QB + tid] : best;
             if ((best >> 32) != 0xffffffffull)
                 atomicMin((unsigned long long*)&p.best[qb + tid], (unsigned long long)best);
         }
         __syncthreads();
     }
+}
+
+template <int ND, int K, int C, int QB, int NX>
+__global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
+    __shared__ uint64_t sred[(kLanes / 64) * QB];
+    // XCD-aware mapping: workgroups are dispatched to the 8 XCDs round-robin,
+    // so block b runs on XCD b % 8. Each XCD gets a contiguous band of tile
+    // chunks (all query splits of it), keeping its band of the volume in
+    // that XCD's L2.
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b % kXcds, slot = b / kXcds;
+    const int64_t chunk = xcd * p.chunks_per_xcd + slot % p.chunks_per_xcd;
+    const int64_t qs = slot / p.chunks_per_xcd;
+    if (chunk >= p.n_chunks || qs >= p.q_splits) return;
+    const int64_t q0 = qs * p.q_per_wg;
+    const int64_t q1 = min(p.Q, q0 + p.q_per_wg);
+    if (q0 >= q1) return;
+    const int64_t tl0 = chunk * p.tiles_per_wg;
+    const int64_t tl1 = min(p.n_tiles, tl0 + p.tiles_per_wg);
+    scan_range<ND, K, C, QB, NX>(p, q0, q1, tl0, tl1, sred);
+}
+
+// ---- batches of 2D images
+// (QB, NX) of a batch shape set for a channel count
+constexpr int batch_qb(int shape, int C) { return shape == 1 ? 8 : 16; }
+constexpr int batch_nx(int shape, int C) {
+    return shape == 2 ? (C == 1 ? 4 : 2) : (C == 1 ? 8 : 4);
+}
+
+template <int K, int SHAPE>
+__global__ __launch_bounds__(kLanes) void scan_batch_kernel(const ScanParams* __restrict__ imgs,
+                                                            const int32_t* __restrict__ img_c,
+                                                            const BatchItem* __restrict__ items,
+                                                            int64_t n_items) {
+    __shared__ uint64_t sred[(kLanes / 64) * 16];
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const ScanParams p = imgs[w.image];
+        const int C = img_c[w.image];
+        if (C == 1)
+            scan_range<2, K, 1, batch_qb(SHAPE, 1), batch_nx(SHAPE, 1)>(p, w.q0, w.q1, w.tl0,
+                                                                         w.tl1, sred);
+        else if (C == 2)
+            scan_range<2, K, 2, batch_qb(SHAPE, 2), batch_nx(SHAPE, 2)>(p, w.q0, w.q1, w.tl0,
+                                                                         w.tl1, sred);
+        else
+            scan_range<2, K, 3, batch_qb(SHAPE, 3), batch_nx(SHAPE, 3)>(p, w.q0, w.q1, w.tl0,
+                                                                         w.tl1, sred);
+    }
+}
+
+// Padded targets, row masks and cleared results of every image of a batch:
+// one thread per (padded query, patch row). Padded query g belongs to the
+// image i with pad_start[i] <= g < pad_start[i + 1].
+__global__ void batch_prep_kernel(const float* __restrict__ targets, const uint8_t* __restrict__ masks,
+                                  const BatchMeta* __restrict__ meta, const int64_t* __restrict__ pad_start,
+                                  int n_images, int K, int64_t total_pad, float* __restrict__ tpad,
+                                  uint32_t* __restrict__ rowmask, uint64_t* __restrict__ best) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total_pad * K) return;
+    const int64_t g = e / K;
+    const int r = (int)(e - g * K);
+    int lo = 0, hi = n_images - 1;
+    while (lo < hi) {   // last image whose padded range starts at or before g
+        const int mid = (lo + hi + 1) >> 1;
+        if (pad_start[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchMeta m = meta[lo];
+    const int64_t ql = g - pad_start[lo];
+    const int C = m.C, RW = K * C;
+    float* dst = tpad + m.tpad_off + (ql * K + r) * RW;
+    uint32_t bits = 0;
+    if (ql < m.Q) {
+        const int64_t q = m.q_off + ql;
+        const float* src = targets + m.t_off + (ql * K + r) * RW;
+        for (int i = 0; i < RW; i++) dst[i] = src[i];
+        const uint8_t* mk = masks + (q * K + r) * K;
+        for (int dx = 0; dx < K; dx++)
+            if (mk[dx]) bits |= 1u << dx;
+        if (r == 0) best[q] = ~0ull;
+    } else {
+        for (int i = 0; i < RW; i++) dst[i] = 0.0f;
+    }
+    rowmask[m.rm_off + (int64_t)r * m.qpad + ql] = bits;
 }
 
 // rowmask[r][q] bit dx = target_masks[q][r*K + dx]; queries Q..qpad-1 get 0.
@@ -338,5 +398,67 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFC_OK : check_hip(e, "scan_fp32_kernel");
 }
+
+sfc_status launch_batch_prep(const float* targets, const uint8_t* masks, const BatchMeta* meta,
+                             const int64_t* pad_start, int n_images, int K, int64_t total_pad,
+                             float* tpad, uint32_t* rowmask, uint64_t* best, hipStream_t st) {
+    if (total_pad == 0) return SFC_OK;
+    batch_prep_kernel<<<blocks_for(total_pad * K), 256, 0, st>>>(targets, masks, meta, pad_start,
+                                                                n_images, K, total_pad, tpad,
+                                                                rowmask, best);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFC_OK : check_hip(e, "batch_prep_kernel");
+}
+
+bool batch_scan_supported(int K) { return K == 5 || K == 7 || K == 9 || K == 11; }
+
+sfc_status launch_batch_scan(int K, int shape, const ScanParams* imgs, const int32_t* img_c,
+                             const BatchItem* items, int64_t n_items, unsigned grid,
+                             hipStream_t st) {
+    if (n_items == 0) return SFC_OK;
+    using Fn = void (*)(const ScanParams*, const int32_t*, const BatchItem*, int64_t);
+    Fn fn = nullptr;
+#define SFC_BATCH_K(KK)                                                  \
+    if (K == KK) {                                                       \
+        fn = shape == 1   ? scan_batch_kernel<KK, 1>                      \
+             : shape == 2 ? scan_batch_kernel<KK, 2>                      \
+                          : scan_batch_kernel<KK, 0>;                     \
+    }
+    SFC_BATCH_K(5)
+    SFC_BATCH_K(7)
+    SFC_BATCH_K(9)
+    SFC_BATCH_K(11)
+#undef SFC_BATCH_K
+    if (!fn) return fail(SFC_EUNSUPPORTED, "batched scan: K must be 5, 7, 9 or 11");
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kLanes), 0, st, imgs, img_c, items, n_items);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFC_OK : check_hip(e, "scan_batch_kernel");
+}
+
+ScanParams batch_image_params(const Grid& g, const float* vol, const uint8_t* valid,
+                              const float* t, const uint32_t* rowmask, uint64_t* best, int64_t Q,
+                              int64_t qpad, int shape, int64_t* n_tiles) {
+    ScanParams p{};
+    p.vol = vol;
+    p.valid = valid;
+    p.t = t;
+    p.rowmask = rowmask;
+    p.best = best;
+    p.Q = Q;
+    for (int i = 0; i < g.nd; i++) {
+        p.shape[i] = g.shape[i];
+        p.stride[i] = g.stride[i];
+    }
+    const int nx = shape == 2 ? (g.C == 1 ? 4 : 2) : (g.C == 1 ? 8 : 4);
+    p.line_len = g.shape[g.nd - 1] - 2 * g.h;
+    const int64_t lines = g.shape[0] - 2 * g.h;
+    p.tiles_per_line = p.line_len > 0 ? (p.line_len + 64 * nx - 1) / (64 * nx) : 0;
+    p.n_tiles = lines > 0 ? lines * p.tiles_per_line : 0;
+    p.qpad = qpad;
+    *n_tiles = p.n_tiles;
+    return p;
+}
+
+int batch_query_block(int shape) { return shape == 1 ? 8 : 16; }
 
 }  // namespace sfc

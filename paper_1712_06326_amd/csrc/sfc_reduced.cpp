@@ -3,6 +3,7 @@
 // float32 scan for the queries the filter cannot settle.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "index.hpp"
@@ -32,8 +33,14 @@ __global__ void scatter_results_kernel(const uint64_t* __restrict__ best, const 
     cost[idx[q]] = b == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(b >> 32));
 }
 
-constexpr int kCap = 2048;   // candidates kept per query
 constexpr double kMaxOperandBytes = 32.0 * (1ull << 30);   // bf16 dictionary operand
+
+// candidates kept per query: 2048 .. 16384, the lists within 512 MiB
+int list_capacity(int64_t Q) {
+    int64_t cap = (int64_t(512) << 20) / 4 / (Q > 0 ? Q : 1);
+    cap = std::max<int64_t>(2048, std::min<int64_t>(16384, cap));
+    return (int)(cap & ~int64_t(63));
+}
 
 }  // namespace
 
@@ -44,21 +51,25 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
                     "fp8 scan: e4m3 cannot hold byte codes exactly; use SFC_MODE_BRUTE_BF16");
     const Grid& g = ix->g;
     hipStream_t st = ix->st;
-    const int P = g.Kd * g.C;
-    if (P > 1024) return fail(SFC_EUNSUPPORTED, "reduced-precision scan: patch above 1024 elements");
+    if ((int64_t)g.Kd * g.C > 1024)
+        return fail(SFC_EUNSUPPORTED, "reduced-precision scan: patch above 1024 elements");
     SFC_TRY(ensure_quantized(ix, ix->mask_copy));
     SFC_TRY(ensure_elem_offsets(ix));
-    const int64_t Kp = mfma_kp(P);
-    const int64_t npad = (ix->n + kMfmaTile - 1) / kMfmaTile * kMfmaTile;
+    FilterArgs fa{};
+    SFC_TRY(plan_filter(g.Kd, g.C, Q, ix->n, &fa));
+    const int64_t Kp = fa.Kp;
+    const int64_t npad = (ix->n + 255) / 256 * 256;
     if ((double)npad * Kp * 2 > kMaxOperandBytes)
         return fail(SFC_EUNSUPPORTED,
                     "reduced-precision scan: dictionary operand above 32 GiB; use SFC_MODE_BRUTE_FP32");
     if (!ix->mfma_B) {
         SFC_TRY(dev_alloc((void**)&ix->mfma_B, (size_t)npad * Kp * 2, "reduced-precision operand"));
-        SFC_TRY(launch_dict_operand(ix->xq, ix->dict, ix->n, ix->elem_off, P, g.C, ix->mfma_B, st));
+        SFC_TRY(launch_dict_operand(ix->xq, ix->dict, ix->n, npad, ix->elem_off, g.Kd, g.C, (int)Kp,
+                                    ix->mfma_B, st));
     }
-    const int64_t Qpad = (Q + kMfmaTile - 1) / kMfmaTile * kMfmaTile;
+    const int64_t Qpad = fa.qtiles * kFilterRows;
     const int64_t qpad_rm = scan_qpad(Q);
+    const int cap = list_capacity(Q);
     // scratch layout
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -68,9 +79,12 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
     };
     const size_t oA = take((size_t)Qpad * Kp * 2);
     const size_t oT2 = take((size_t)Qpad * 4), oK = take((size_t)Qpad * 4), oF = take((size_t)Qpad * 4);
-    const size_t oMin = take((size_t)Q * 4), oThr = take((size_t)Q * 4), oCnt = take((size_t)Q * 4);
-    const size_t oList = take((size_t)Q * kCap * 4);
+    const size_t oTm = take((size_t)Q * fa.ngroups * 4);
+    const size_t oThr = take((size_t)Q * 4), oCnt = take((size_t)Q * 4);
+    const size_t oList = take((size_t)Q * cap * 4);
+    const size_t oWork = take((size_t)fa.qtiles * fa.ctiles * 8), oNw = take(64);
     const size_t oFb = take((size_t)Q), oIdx = take((size_t)Q * 8), oN = take(64);
+    const size_t oSid = take((size_t)Q * 8), oSc = take((size_t)Q * 4);
     const size_t oCs = take(compact_scratch_bytes(Q));
     SFC_TRY(ix->red.reserve(off, "reduced-precision scratch"));
     char* base = static_cast<char*>(ix->red.ptr);
@@ -78,41 +92,68 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
     int32_t* T2 = reinterpret_cast<int32_t*>(base + oT2);
     int32_t* kq = reinterpret_cast<int32_t*>(base + oK);
     int32_t* flag = reinterpret_cast<int32_t*>(base + oF);
-    int32_t* eqmin = reinterpret_cast<int32_t*>(base + oMin);
+    int32_t* tilemin = reinterpret_cast<int32_t*>(base + oTm);
     int32_t* thr = reinterpret_cast<int32_t*>(base + oThr);
     int32_t* cnt = reinterpret_cast<int32_t*>(base + oCnt);
     uint32_t* list = reinterpret_cast<uint32_t*>(base + oList);
+    uint64_t* work = reinterpret_cast<uint64_t*>(base + oWork);
+    unsigned long long* nwork_dev = reinterpret_cast<unsigned long long*>(base + oNw);
     uint8_t* fb = reinterpret_cast<uint8_t*>(base + oFb);
     int64_t* fidx = reinterpret_cast<int64_t*>(base + oIdx);
     int64_t* nfb_dev = reinterpret_cast<int64_t*>(base + oN);
     void* cscratch = base + oCs;
+    int64_t* seed_id = reinterpret_cast<int64_t*>(base + oSid);
+    float* seed_cost = reinterpret_cast<float*>(base + oSc);
 
-    SFC_TRY(launch_query_operand(t, m, Q, Qpad, g.Kd, g.C, ix->qparams, A, T2, kq, flag, st));
-    FilterArgs fa{};
+    SFC_TRY(launch_query_operand(t, m, Q, Qpad, g.Kd, g.C, (int)Kp, ix->qparams, A, T2, kq, flag,
+                                 st));
     fa.A = A;
     fa.B = ix->mfma_B;
     fa.T2 = T2;
-    fa.Q = Q;
-    fa.n = ix->n;
-    fa.Kp = (int)Kp;
     fa.dict = ix->dict;
-    fa.eqmin = eqmin;
+    fa.tilemin = tilemin;
     fa.thr = thr;
     fa.cnt = cnt;
     fa.list = list;
-    fa.cap = kCap;
-    SFC_TRY(ix->timer.begin("filter_kernel<1>", st));
-    SFC_TRY(launch_filter(fa, 1, st));
-    SFC_TRY(ix->timer.end(st));
-    SFC_TRY(launch_threshold(eqmin, kq, flag, ix->qparams, Q, thr, st));
-    SFC_TRY(ix->timer.begin("filter_kernel<2>", st));
-    SFC_TRY(launch_filter(fa, 2, st));
-    SFC_TRY(ix->timer.end(st));
+    fa.work = work;
+    fa.cap = cap;
+    if (ix->has_sfc) {
+        // seeded single pass: the index answer's exact cost bounds each
+        // query's optimum from above, so one GEMM pass can list every
+        // candidate that may reach it
+        const bool timing = ix->timer.on;
+        ix->timer.on = false;
+        sfc_status qs = query_index(ix, t, m, Q, seed_id, seed_cost, nullptr, nullptr);
+        ix->timer.on = timing;
+        SFC_TRY(qs);
+        SFC_TRY(launch_seed_threshold(seed_cost, kq, flag, ix->qparams, Q, thr, st));
+        SFC_TRY(ix->timer.begin("filter_kernel<list>", st));
+        SFC_TRY(launch_filter_list(fa, -1, st));
+        SFC_TRY(ix->timer.end(st));
+        ix->last_pass1_tiles = fa.qtiles * fa.ctiles;
+        ix->last_pass2_tiles = 0;
+    } else {
+        // two passes: per-tile minima give the threshold, then the tiles
+        // that can reach it are multiplied again and listed
+        SFC_TRY(ix->timer.begin("filter_kernel<min>", st));
+        SFC_TRY(launch_filter_minima(fa, st));
+        SFC_TRY(ix->timer.end(st));
+        SFC_TRY(launch_threshold(fa, kq, flag, ix->qparams, thr, st));
+        SFC_TRY(launch_select(fa, work, nwork_dev, st));
+        unsigned long long nwork = 0;
+        SFC_HIP(hipMemcpyAsync(&nwork, nwork_dev, sizeof(nwork), hipMemcpyDeviceToHost, st));
+        SFC_HIP(hipStreamSynchronize(st));
+        ix->last_pass1_tiles = fa.qtiles * fa.ctiles;
+        ix->last_pass2_tiles = (int64_t)nwork;
+        SFC_TRY(ix->timer.begin("filter_kernel<list>", st));
+        SFC_TRY(launch_filter_list(fa, (int64_t)nwork, st));
+        SFC_TRY(ix->timer.end(st));
+    }
     SFC_TRY(ix->rowmask.reserve((size_t)qpad_rm * g.rows * sizeof(uint32_t), "row masks"));
     uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
     SFC_TRY(launch_pack_rowmask(m, g, Q, rm, st));
     SFC_TRY(ix->timer.begin("list_rescore_kernel", st));
-    SFC_TRY(launch_list_rescore(g, ix->vol, t, rm, qpad_rm, list, cnt, thr, kCap, Q, best_id,
+    SFC_TRY(launch_list_rescore(g, ix->vol, t, rm, qpad_rm, list, cnt, thr, cap, Q, best_id,
                                 best_cost, fb, st));
     SFC_TRY(ix->timer.end(st));
     // queries the filter could not settle go through the float32 scan

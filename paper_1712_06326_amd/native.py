@@ -77,6 +77,7 @@ _SIG = {
     "sfc_query_coords": (ST, [P, P, P, I64, P, P]),
     "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
     "sfc_query_kernel_times": (ST, [P, P, I32, C.POINTER(C.c_int32)]),
+    "sfc_query_filter_tiles": (ST, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sfc_autotune": (ST, [P, P, P, I64, C.POINTER(C.c_int32)]),
     "sfc_index_info_get": (ST, [P, C.POINTER(IndexInfo)]),
     "sfc_index_dictionary": (ST, [P, P]),
@@ -86,6 +87,12 @@ _SIG = {
     "sfc_index_projection": (ST, [P, I32, P]),
     "sfc_index_export": (ST, [P, I32, I32, P, P]),
     "sfc_index_free": (None, [P]),
+    "sfc_batch_create": (ST, [I32, P, P, P, I32, C.POINTER(Options), C.POINTER(P)]),
+    "sfc_batch_query": (ST, [P, P, P, P, P, P]),
+    "sfc_batch_autotune": (ST, [P, P, P, P, P, P, C.POINTER(C.c_int32)]),
+    "sfc_batch_stats": (ST, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                             C.POINTER(C.c_int32)]),
+    "sfc_batch_free": (None, [P]),
     "sfc_inpaint": (ST, [P, P, C.POINTER(Geometry), I32, C.c_int, C.c_int, P,
                          C.POINTER(Options), C.POINTER(C.c_int64), C.POINTER(FillLog)]),
 }
@@ -239,6 +246,12 @@ class Index:
         return {arr[i].kernel.decode(): (arr[i].launches, arr[i].ms)
                 for i in range(min(n.value, cap))}
 
+    def filter_tiles(self):
+        """(pass-1 tiles, pass-2 tiles) of the last bf16 query."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(_L.sfc_query_filter_tiles(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def fallbacks(self) -> int:
         n = C.c_int64()
         _check(_L.sfc_query_stats(self._h, C.byref(n)))
@@ -295,6 +308,64 @@ class Index:
         ids = torch.empty(i.n, dtype=torch.int64, device=self.volume.device)
         _check(_L.sfc_index_export(self._h, subset, curve, _ptr(keys), _ptr(ids)))
         return keys, ids
+
+
+class Batch:
+    """Owner of an sfc_batch: many 2D images, one persistent scan launch per
+    query, captured in a HIP graph and replayed."""
+
+    def __init__(self, volumes: list, masks: list, K: int, **opts):
+        import numpy as np
+        self.volumes, self.masks, self.K = list(volumes), list(masks), K
+        self._opts = options(**opts)
+        n = len(self.volumes)
+        vp = (C.c_void_p * n)(*[_ptr(v) for v in self.volumes])
+        mp = (C.c_void_p * n)(*[_ptr(m) for m in self.masks])
+        geos = (Geometry * n)(*[geometry(m, v.shape[-1]) for v, m in zip(self.volumes, self.masks)])
+        h = C.c_void_p()
+        _check(_L.sfc_batch_create(n, C.cast(vp, C.c_void_p), C.cast(mp, C.c_void_p),
+                                   C.cast(geos, C.c_void_p), K, C.byref(self._opts), C.byref(h)))
+        self._h = h
+        self._np = np
+
+    def _counts(self, counts):
+        arr = self._np.ascontiguousarray(self._np.asarray(counts, dtype=self._np.int64))
+        return arr, arr.ctypes.data_as(C.c_void_p)
+
+    def query(self, t: torch.Tensor, m: torch.Tensor, counts, out=None):
+        """t: concatenated [count_i, K*K, C_i] float32 (flat is fine); m: [sum, K*K]."""
+        arr, cp = self._counts(counts)
+        Q = int(arr.sum())
+        if out is None:
+            out = (torch.empty(Q, dtype=torch.int64, device=m.device),
+                   torch.empty(Q, dtype=torch.float32, device=m.device))
+        bi, bc = out
+        _check(_L.sfc_batch_query(self._h, _ptr(t), _ptr(m), cp, _ptr(bi), _ptr(bc)))
+        return bi, bc
+
+    def autotune(self, t: torch.Tensor, m: torch.Tensor, counts, out) -> int:
+        arr, cp = self._counts(counts)
+        v = C.c_int32()
+        bi, bc = out
+        _check(_L.sfc_batch_autotune(self._h, _ptr(t), _ptr(m), cp, _ptr(bi), _ptr(bc),
+                                     C.byref(v)))
+        return v.value
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(_L.sfc_batch_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"graph_replays": a.value, "work_items": b.value, "shape": c.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _L.sfc_batch_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def inpaint(volume: torch.Tensor, mask: torch.Tensor, K: int, order="criminisi", mode="fp32",

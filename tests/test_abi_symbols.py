@@ -45,3 +45,19 @@ def test_host_only_calls():
     assert rc == -1 and b"geometry" in lib.sfc_last_error()
     lib.sfc_query.restype = ctypes.c_int
     assert lib.sfc_query(None, None, None, 1, 0, None, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_batch_argument_errors():
+    lib = ctypes.CDLL(LIB)
+    lib.sfc_batch_create.restype = ctypes.c_int
+    lib.sfc_batch_query.restype = ctypes.c_int
+    lib.sfc_last_error.restype = ctypes.c_char_p
+    out = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.sfc_batch_create(0, arr, arr, arr, 9, None, ctypes.byref(out)) == -1
+    assert lib.sfc_batch_create(1, None, arr, arr, 9, None, ctypes.byref(out)) == -1
+    geo = (ctypes.c_int32 * 8)(2, 1, 0, 0, 32, 0, 32, 0)
+    assert lib.sfc_batch_create(1, arr, arr, geo, 4, None, ctypes.byref(out)) == -5
+    assert b"K must be" in lib.sfc_last_error()
+    assert lib.sfc_batch_query(None, None, None, None, None, None) == -1
