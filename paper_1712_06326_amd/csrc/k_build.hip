@@ -202,7 +202,7 @@ __global__ void cov_matrix_kernel(const uint64_t* __restrict__ sum,
 // operation (the file is compiled with contraction off).
 constexpr int kJacThreads = 1024;
 constexpr int kJacMaxPairs = (kMaxSubsetElems + 1) / 2 + 1;
-constexpr int kJacTriLds = 19500;    // doubles of the triangle kept in LDS
+constexpr int kJacTriLds = 19350;    // doubles of the triangle kept in LDS
 constexpr int kJacChunk = 4;         // sweeps per launch (rotation-log depth)
 constexpr int kJacMaxSweeps = 60;
 
@@ -235,61 +235,43 @@ struct TriStore {
         else if (t >= G) lds[t - G] = v;
         else glob[t] = v;
     }
+    // by packed position
+    __device__ double at(int t) const {
+        if (!kSplit) return lds[t];
+        return t >= G ? lds[t - G] : glob[t];
+    }
+    __device__ void put(int t, double v) const {
+        if (!kSplit) lds[t] = v;
+        else if (t >= G) lds[t - G] = v;
+        else glob[t] = v;
+    }
 };
 
-// pair k of round r (M even): (r, M-1) for k = 0, else ((r+k), (r-k)) mod M-1
-__device__ inline void round_pair(int r, int k, int M, int* p, int* q) {
-    int a, b;
-    if (k == 0) {
-        a = r;
-        b = M - 1;
-    } else {
-        a = r + k;
-        if (a >= M - 1) a -= M - 1;
-        b = r - k;
-        if (b < 0) b += M - 1;
-    }
-    *p = a < b ? a : b;
-    *q = a < b ? b : a;
-}
+// Pair of a round as the block phase needs it: indices and the offsets of
+// their rows in the packed triangle (entry (x, y), x <= y, is at ro(x) + y).
+struct JacPair {
+    int p, q, rp, rq;
+};
 
-// block u of the np x np upper triangle (row-major, diagonal included)
-__device__ inline void block_of(int u, int np, int* a, int* b) {
-    const float n2 = 2.0f * np + 1.0f;   // n2^2 - 8u is exact in float32
-    int r = (int)((n2 - sqrtf(n2 * n2 - 8.0f * u)) * 0.5f);
-    if (r < 0) r = 0;
-    if (r > np - 1) r = np - 1;
-    while (r > 0 && r * np - r * (r - 1) / 2 > u) r--;
-    while (r < np - 1 && (r + 1) * np - (r + 1) * r / 2 <= u) r++;
-    *a = r;
-    *b = r + (u - (r * np - r * (r - 1) / 2));
-}
+__device__ inline int tri_row_offset(int x, int m) { return x * (2 * m - x + 1) / 2 - x; }
 
-// One 2x2 block (rows of pair a, columns of pair b, a <= b) of a round.
+// Off-diagonal block (rows of pair a, columns of pair b, a < b): the entry
+// (x, y) above the diagonal takes the row rotation of x's pair, then the
+// column rotation of y's pair. Inactive pairs (c < 0) rotate nothing.
 template <bool kSplit>
-__device__ inline void rotate_block(const TriStore<kSplit>& T, int a, int b, int m, const int* sp,
-                                const int* sq, const int* sact, const double* scs,
-                                const double* ssn) {
-    const int acta = sact[a], actb = sact[b];
-    if (!acta && !actb) return;
-    const int pa = sp[a], qa = sq[a], pb = sp[b], qb = sq[b];
-    const double ca = scs[a], sa = ssn[a], cb = scs[b], sb = ssn[b];
-    if (a == b) {
-        // both passes on the pair's own 2x2 block; a_pq -> 0
-        const double app = T.get(pa, pa), apq = T.get(pa, qa), aqq = T.get(qa, qa);
-        const double y00 = ca * app - sa * apq, y01 = ca * apq - sa * aqq;
-        const double y10 = sa * app + ca * apq, y11 = sa * apq + ca * aqq;
-        T.set(pa, pa, ca * y00 - sa * y01);
-        T.set(qa, qa, sa * y10 + ca * y11);
-        T.set(pa, qa, 0.0);
-        return;
-    }
-    const bool va = qa < m, vb = qb < m;
-    // X[i][j] = A(row i of pair a, column j of pair b)
-    double x00 = T.get(pa, pb);
-    double x01 = vb ? T.get(pa, qb) : 0.0;
-    double x10 = va ? T.get(qa, pb) : 0.0;
-    double x11 = (va && vb) ? T.get(qa, qb) : 0.0;
+__device__ inline void rotate_cross(const TriStore<kSplit>& T, const JacPair& A, const JacPair& B,
+                                    double ca, double sa, double cb, double sb, int m) {
+    const bool acta = ca >= 0.0, actb = cb >= 0.0;
+    const bool va = A.q < m, vb = B.q < m;
+    // packed positions of (pa,pb), (pa,qb), (qa,pb), (qa,qb)
+    const int t00 = A.p < B.p ? A.rp + B.p : B.rp + A.p;
+    const int t01 = A.p < B.q ? A.rp + B.q : B.rq + A.p;
+    const int t10 = A.q < B.p ? A.rq + B.p : B.rp + A.q;
+    const int t11 = A.q < B.q ? A.rq + B.q : B.rq + A.q;
+    const double x00 = T.at(t00);
+    const double x01 = vb ? T.at(t01) : 0.0;
+    const double x10 = va ? T.at(t10) : 0.0;
+    const double x11 = (va && vb) ? T.at(t11) : 0.0;
     // rows by a, then columns by b: Z
     double z00 = x00, z01 = x01, z10 = x10, z11 = x11;
     if (acta) {
@@ -315,10 +297,26 @@ __device__ inline void rotate_block(const TriStore<kSplit>& T, int a, int b, int
         const double y10 = ca * w10 - sa * w11, y11 = sa * w10 + ca * w11;
         w00 = y00; w01 = y01; w10 = y10; w11 = y11;
     }
-    T.set(pa, pb, pa < pb ? z00 : w00);
-    if (vb) T.set(pa, qb, pa < qb ? z01 : w10);
-    if (va) T.set(qa, pb, qa < pb ? z10 : w01);
-    if (va && vb) T.set(qa, qb, qa < qb ? z11 : w11);
+    T.put(t00, A.p < B.p ? z00 : w00);
+    if (vb) T.put(t01, A.p < B.q ? z01 : w10);
+    if (va) T.put(t10, A.q < B.p ? z10 : w01);
+    if (va && vb) T.put(t11, A.q < B.q ? z11 : w11);
+}
+
+// pair k of round r (M even): (r, M-1) for k = 0, else ((r+k), (r-k)) mod M-1
+__device__ inline void round_pair(int r, int k, int M, int* p, int* q) {
+    int a, b;
+    if (k == 0) {
+        a = r;
+        b = M - 1;
+    } else {
+        a = r + k;
+        if (a >= M - 1) a -= M - 1;
+        b = r - k;
+        if (b < 0) b += M - 1;
+    }
+    *p = a < b ? a : b;
+    *q = a < b ? b : a;
 }
 
 __global__ __launch_bounds__(256) void jacobi_init_kernel(const double* __restrict__ Aall,
@@ -364,8 +362,8 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
     const int total = m * (m + 1) / 2;
     const int G = total > kJacTriLds ? total - kJacTriLds : 0;
     __shared__ double lds[kJacTriLds];
-    __shared__ int sp[kJacMaxPairs], sq[kJacMaxPairs], sact[kJacMaxPairs];
-    __shared__ double scs[kJacMaxPairs], ssn[kJacMaxPairs];
+    __shared__ JacPair spair[kJacMaxPairs];
+    __shared__ double2 scs[kJacMaxPairs];   // (c, s); c < 0: no rotation
     __shared__ int s_rot;
     double* Tg = Tall + (int64_t)s * tri_stride;
     double2* log = logall + (int64_t)s * log_stride;
@@ -373,7 +371,10 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
     const TriStore<kSplit> T{lds, Tg, G, m};
     const double tiny = state[s].tiny;
     const int done0 = state[s].done;
-    const int nblk = np * (np + 1) / 2;
+    // this thread's blocks: items u = tid + k * kJacThreads of the np x np
+    // grid, (a, b) = (u / np, u % np), stepped without division; a < b only
+    const int da = kJacThreads / np, db = kJacThreads % np;
+    const int a0 = tid / np, b0 = tid % np;
     __syncthreads();
 
     int sw = 0;
@@ -383,12 +384,11 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
         __syncthreads();
         for (int r = 0; r < M - 1; r++) {
             if (tid < np) {
+                // decide this pair's rotation and apply it to the pair's own
+                // 2x2 diagonal block (both passes; a_pq -> 0)
                 const int k = tid;
                 int p, q;
                 round_pair(r, k, M, &p, &q);
-                sp[k] = p;
-                sq[k] = q;
-                int act = 0;
                 double c = -1.0, sn = 0.0;
                 if (q < m) {
                     const double apq = T.get(p, q);
@@ -402,20 +402,34 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
                         if (theta < 0.0) t = -t;
                         c = 1.0 / sqrt(1.0 + t * t);
                         sn = t * c;
-                        act = 1;
+                        const double y00 = c * app - sn * apq, y01 = c * apq - sn * aqq;
+                        const double y10 = sn * app + c * apq, y11 = sn * apq + c * aqq;
+                        T.set(p, p, c * y00 - sn * y01);
+                        T.set(q, q, sn * y10 + c * y11);
+                        T.set(p, q, 0.0);
                         atomicAdd(&s_rot, 1);
                     }
                 }
-                scs[k] = c;
-                ssn[k] = sn;
-                sact[k] = act;
+                spair[k] = JacPair{p, q, tri_row_offset(p, m), q < m ? tri_row_offset(q, m) : 0};
+                scs[k] = make_double2(c, sn);
                 log[((int64_t)sw * (M - 1) + r) * np + k] = make_double2(c, sn);
             }
             __syncthreads();
-            for (int u = tid; u < nblk; u += kJacThreads) {
-                int a, b;
-                block_of(u, np, &a, &b);
-                rotate_block(T, a, b, m, sp, sq, sact, scs, ssn);
+            {
+                int a = a0, b = b0;
+                while (a < np) {
+                    if (a < b) {
+                        const double2 ea = scs[a], eb = scs[b];
+                        if (ea.x >= 0.0 || eb.x >= 0.0)
+                            rotate_cross(T, spair[a], spair[b], ea.x, ea.y, eb.x, eb.y, m);
+                    }
+                    a += da;
+                    b += db;
+                    if (b >= np) {
+                        b -= np;
+                        a++;
+                    }
+                }
             }
             __syncthreads();
         }

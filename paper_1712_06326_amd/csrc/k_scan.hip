@@ -26,6 +26,9 @@ namespace {
 constexpr int kLanes = 256;
 constexpr int kXcds = 8;
 constexpr int kScanQB = 48;   // row-mask padding: a multiple of every variant's QB
+// s_waitcnt with lgkmcnt(0) and the vector-memory and export counters at
+// their maxima: waits for LDS, scalar-memory and message results only
+constexpr int kWaitScalar = 0xC07F;
 
 typedef const __attribute__((address_space(4))) float cfloat_as4;
 typedef const __attribute__((address_space(4))) uint32_t cu32_as4;
@@ -95,24 +98,38 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
                         v[i] = (x0 + i / C < p.shape[ND - 1]) ? vp[i] : 0.0f;
                 }
                 const float* tb = p.t + (qb * ROWS + r) * RW;
+                // The query rows come through scalar loads, which return out
+                // of order, so a wait covers every one in flight. The next
+                // query's row is requested only after the current one has
+                // arrived and is consumed while that request is in flight.
+                // (Targets are padded to the query block: all in bounds.)
+                float tc[RW];
+                uint32_t mc;
+#pragma unroll
+                for (int i = 0; i < RW; i++) tc[i] = ldu(tb + i);
+                mc = ldu(mrb);
 #pragma unroll
                 for (int qi = 0; qi < QB; qi++) {
-                    // targets are padded to the query block: both loads are in
-                    // bounds and issue together before one wait
-                    float tr[RW];
+                    __builtin_amdgcn_s_waitcnt(kWaitScalar);
+                    float tn[RW];
+                    uint32_t mn = 0;
+                    if (qi + 1 < QB) {
 #pragma unroll
-                    for (int i = 0; i < RW; i++) tr[i] = ldu(tb + qi * ROWS * RW + i);
-                    const uint32_t mr = ldu(mrb + qi);
-                    if (mr == 0) continue;
+                        for (int i = 0; i < RW; i++) tn[i] = ldu(tb + (qi + 1) * ROWS * RW + i);
+                        mn = ldu(mrb + qi + 1);
+                    }
+                    const uint32_t mr = mc;
                     if (mr == (1u << K) - 1u) {
+                        // element outer, candidate inner: NX independent
+                        // accumulation chains, each in element order
 #pragma unroll
-                        for (int j = 0; j < NX; j++)
+                        for (int i = 0; i < RW; i++)
 #pragma unroll
-                            for (int i = 0; i < RW; i++) {
-                                const float d = tr[i] - v[j * C + i];
+                            for (int j = 0; j < NX; j++) {
+                                const float d = tc[i] - v[j * C + i];
                                 acc[qi][j] = __builtin_fmaf(d, d, acc[qi][j]);
                             }
-                    } else {
+                    } else if (mr != 0) {
 #pragma unroll
                         for (int dx = 0; dx < K; dx++) {
                             if (mr & (1u << dx)) {
@@ -120,11 +137,16 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
                                 for (int j = 0; j < NX; j++)
 #pragma unroll
                                     for (int ch = 0; ch < C; ch++) {
-                                        const float d = tr[dx * C + ch] - v[(j + dx) * C + ch];
+                                        const float d = tc[dx * C + ch] - v[(j + dx) * C + ch];
                                         acc[qi][j] = __builtin_fmaf(d, d, acc[qi][j]);
                                     }
                             }
                         }
+                    }
+                    if (qi + 1 < QB) {
+#pragma unroll
+                        for (int i = 0; i < RW; i++) tc[i] = tn[i];
+                        mc = mn;
                     }
                 }
             }
