@@ -177,6 +177,22 @@ def main():
         ix.close()
         return out
 
+    # the index's recall and acceleration error against the window width
+    # (Section III.D's candidate-set trade-off), from the window autotuner
+    # on a seeded sample of 1024 front targets; the timed steps keep the
+    # workload's window
+    window_trials = None
+    if cfg.get("D"):
+        fz = native.fill_front(w.mask)
+        tz, mz = native.extract_targets(w.vol, w.mask, K, fz)
+        kz = min(1024, w.Q)
+        sz = torch.from_numpy(np.sort(np.random.default_rng(3).choice(w.Q, kz, replace=False))).cuda()
+        iz = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], **w.opts)
+        wz, window_trials = iz.autotune_window(tz[sz].contiguous(), mz[sz].contiguous(), 0.9)
+        iz.close()
+        del fz, tz, mz
+        log(f"window autotuner: W={wz} reaches recall 0.9 on the sample")
+
     # autotune the float32 scan's tile shape once on this workload (the
     # choice is remembered for every later handle of the same shape)
     f0 = native.fill_front(w.mask)
@@ -254,6 +270,7 @@ def main():
         "phase_ms": {k: round(float(v), 3) for k, v in zip(phase_names, ph)},
         "kernel_avg_ms": {k: round(v, 3) for k, v in kavg.items()},
         "fp32_scan_shape": chosen,
+        "index_window_trials": window_trials,
         "scan_queries": Qs,
         "index_recall_at_1_pct": round(100 * recall, 3),
         "index_acceleration_error_pct": round(ae, 4),

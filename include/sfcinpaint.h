@@ -193,6 +193,26 @@ sfc_status sfc_query_coords(sfc_index *idx, const float *targets,
 sfc_status sfc_autotune(sfc_index *idx, const float *targets, const uint8_t *target_masks,
                         int64_t Q, int32_t *chosen_host);
 
+/* One window width tried by sfc_autotune_window. */
+typedef struct {
+    int32_t window;        /* W */
+    float recall;          /* fraction of targets whose index answer is the full scan's */
+    float accel_error;     /* mean sqrt(cost_index) / sqrt(cost_scan) - 1 over targets with
+                              a nonzero scan cost (Section III.C's acceleration error) */
+    float ms;              /* index query time on these targets (HIP events) */
+} sfc_window_trial;
+
+/* Window autotuner for SFC_MODE_INDEX: answers the targets with the float32
+ * full scan, then with the index at W = 2, 4, 6, 8, 12, ..., 256 (while
+ * n_curves * W <= 512), and keeps on the handle the smallest W whose recall
+ * reaches target_recall (in [0, 1]; the largest W tried if none does).
+ * *window_host receives it; the trials (up to capacity) go to trials_host and
+ * their number to *count_host. The window is a query-time parameter: the
+ * index itself is not rebuilt. Synchronises. */
+sfc_status sfc_autotune_window(sfc_index *idx, const float *targets, const uint8_t *target_masks,
+                               int64_t Q, float target_recall, sfc_window_trial *trials_host,
+                               int32_t capacity, int32_t *count_host, int32_t *window_host);
+
 /* Statistics of the last sfc_query call on this handle (host values):
  * n_fallback = queries a reduced-precision scan could not certify. */
 sfc_status sfc_query_stats(const sfc_index *idx, int64_t *n_fallback_host);

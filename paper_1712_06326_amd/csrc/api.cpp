@@ -1,6 +1,7 @@
 // C ABI: argument checks, handle lifetime and orchestration of the kernels.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -476,6 +477,105 @@ sfc_status sfc_autotune(sfc_index* ix, const float* targets, const uint8_t* targ
     ix->tuned_variant = bestv;
     remember_variant(g.nd, g.K, g.C, bestv);
     *chosen = bestv + 1;
+    return SFC_OK;
+}
+
+sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_t* target_masks,
+                               int64_t Q, float target_recall, sfc_window_trial* trials,
+                               int32_t capacity, int32_t* count, int32_t* window) {
+    clear_error();
+    if (!ix || !targets || !target_masks || !count || !window || (capacity > 0 && !trials))
+        return fail(SFC_EINVAL, "null pointer");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "window autotuning needs an SFC index handle");
+    if (Q < 1) return fail(SFC_EINVAL, "window autotuning needs Q >= 1");
+    if (!(target_recall >= 0.0f && target_recall <= 1.0f))
+        return fail(SFC_EINVAL, "target_recall must be in [0, 1]");
+    ix->timer.reset(false);
+    const int saved = ix->opt.window;
+    std::vector<int64_t> ref_id(Q), got_id(Q);
+    std::vector<float> ref_cost(Q), got_cost(Q);
+    int64_t* d_id = nullptr;
+    float* d_cost = nullptr;
+    SFC_TRY(dev_alloc((void**)&d_id, (size_t)Q * 8, "autotune ids"));
+    sfc_status s = dev_alloc((void**)&d_cost, (size_t)Q * 4, "autotune costs");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s == SFC_OK) {
+        hipError_t he = hipEventCreate(&e0);
+        if (he == hipSuccess) he = hipEventCreate(&e1);
+        if (he != hipSuccess) s = check_hip(he, "hipEventCreate");
+    }
+    // reference: the float32 full scan
+    if (s == SFC_OK) {
+        s = ix->best.reserve((size_t)Q * sizeof(uint64_t), "query results");
+        if (s == SFC_OK) s = query_brute_fp32(ix, targets, target_masks, Q, static_cast<uint64_t*>(ix->best.ptr));
+        if (s == SFC_OK) s = launch_unpack_best(static_cast<uint64_t*>(ix->best.ptr), Q, d_id, d_cost, ix->st);
+        if (s == SFC_OK) {
+            hipError_t he = hipMemcpyAsync(ref_id.data(), d_id, (size_t)Q * 8, hipMemcpyDeviceToHost, ix->st);
+            if (he == hipSuccess) he = hipMemcpyAsync(ref_cost.data(), d_cost, (size_t)Q * 4, hipMemcpyDeviceToHost, ix->st);
+            if (he == hipSuccess) he = hipStreamSynchronize(ix->st);
+            if (he != hipSuccess) s = check_hip(he, "autotune reference");
+        }
+    }
+    static const int kWindows[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    int best_w = -1, largest = -1, n_trials = 0;
+    float best_recall = 0.0f, largest_recall = 0.0f;
+    for (int w : kWindows) {
+        if (s != SFC_OK) break;
+        if ((int64_t)ix->L * w > 512) break;
+        ix->opt.window = w;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && s == SFC_OK; rep++) {   // the first run warms up
+            hipError_t he = hipEventRecord(e0, ix->st);
+            if (he == hipSuccess) s = query_index(ix, targets, target_masks, Q, d_id, d_cost, nullptr, nullptr);
+            if (s == SFC_OK && he == hipSuccess) he = hipEventRecord(e1, ix->st);
+            if (s == SFC_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+            if (s == SFC_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (s == SFC_OK && he != hipSuccess) s = check_hip(he, "autotune timing");
+        }
+        if (s != SFC_OK) break;
+        hipError_t he = hipMemcpyAsync(got_id.data(), d_id, (size_t)Q * 8, hipMemcpyDeviceToHost, ix->st);
+        if (he == hipSuccess) he = hipMemcpyAsync(got_cost.data(), d_cost, (size_t)Q * 4, hipMemcpyDeviceToHost, ix->st);
+        if (he == hipSuccess) he = hipStreamSynchronize(ix->st);
+        if (he != hipSuccess) {
+            s = check_hip(he, "autotune results");
+            break;
+        }
+        int64_t hits = 0, nz = 0;
+        double ae = 0.0;
+        for (int64_t q = 0; q < Q; q++) {
+            hits += got_id[q] == ref_id[q];
+            if (ref_cost[q] > 0.0f) {
+                ae += std::sqrt((double)got_cost[q]) / std::sqrt((double)ref_cost[q]) - 1.0;
+                nz++;
+            }
+        }
+        const float recall = (float)hits / (float)Q;
+        if (n_trials < capacity)
+            trials[n_trials] = sfc_window_trial{w, recall, nz ? (float)(ae / nz) : 0.0f, ms};
+        n_trials++;
+        largest = w;
+        largest_recall = recall;
+        if (best_w < 0 && recall >= target_recall) {
+            best_w = w;
+            best_recall = recall;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(d_id);
+    dev_free(d_cost);
+    if (s != SFC_OK || largest < 0) {
+        ix->opt.window = saved;
+        return s != SFC_OK ? s : fail(SFC_EUNSUPPORTED, "no window fits n_curves * window <= 512");
+    }
+    if (best_w < 0) {
+        best_w = largest;
+        best_recall = largest_recall;
+    }
+    (void)best_recall;
+    ix->opt.window = best_w;
+    *window = best_w;
+    *count = n_trials;
     return SFC_OK;
 }
 

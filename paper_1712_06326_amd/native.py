@@ -39,6 +39,11 @@ class Options(C.Structure):
                 ("timing", C.c_int32)]
 
 
+class WindowTrial(C.Structure):
+    _fields_ = [("window", C.c_int32), ("recall", C.c_float), ("accel_error", C.c_float),
+                ("ms", C.c_float)]
+
+
 class KernelTime(C.Structure):
     _fields_ = [("kernel", C.c_char_p), ("launches", C.c_int32), ("ms", C.c_float)]
 
@@ -78,6 +83,8 @@ _SIG = {
     "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
     "sfc_query_kernel_times": (ST, [P, P, I32, C.POINTER(C.c_int32)]),
     "sfc_query_filter_tiles": (ST, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "sfc_autotune_window": (ST, [P, P, P, I64, C.c_float, P, I32, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]),
     "sfc_autotune": (ST, [P, P, P, I64, C.POINTER(C.c_int32)]),
     "sfc_index_info_get": (ST, [P, C.POINTER(IndexInfo)]),
     "sfc_index_dictionary": (ST, [P, P]),
@@ -236,6 +243,20 @@ class Index:
         v = C.c_int32()
         _check(_L.sfc_autotune(self._h, _ptr(t), _ptr(m), m.shape[0], C.byref(v)))
         return v.value
+
+    def autotune_window(self, t: torch.Tensor, m: torch.Tensor, target_recall: float = 0.9):
+        """Smallest window reaching target_recall against the float32 scan on
+        these targets; set on the handle. Returns (window, [trials])."""
+        cap = 32
+        arr = (WindowTrial * cap)()
+        n, w = C.c_int32(), C.c_int32()
+        _check(_L.sfc_autotune_window(self._h, _ptr(t), _ptr(m), m.shape[0],
+                                      C.c_float(target_recall), C.cast(arr, C.c_void_p), cap,
+                                      C.byref(n), C.byref(w)))
+        trials = [{"window": arr[i].window, "recall": arr[i].recall,
+                   "accel_error": arr[i].accel_error, "ms": arr[i].ms}
+                  for i in range(min(n.value, cap))]
+        return w.value, trials
 
     def kernel_times(self) -> dict:
         """{kernel: (launches, total ms)} of the last query (timing=True)."""

@@ -79,3 +79,30 @@ def test_index_config1():
 def test_index_with_given_basis():
     d = synth.small_image(40, 50, 2, 8)
     _check(d["volume"], d["mask"], 5, 5, 3, 12, "hilbert", 16, with_basis=True)
+
+
+def test_window_autotuner():
+    """The windows are nested, so recall never drops and the acceleration
+    error never rises with W; the tuner keeps the smallest W reaching the
+    target, and the handle then answers exactly like an index built with it."""
+    nat = need_gpu()
+    d = synth.config1()
+    vol, mask, K = d["volume"], d["mask"], 9
+    vd, md = dev(vol), dev(mask)
+    f = nat.fill_front(md)
+    t, m = nat.extract_targets(vd, md, K, f)
+    kw = dict(reduced_dim=8, n_curves=4, key_bits=8)
+    ix = nat.Index(vd, md, K, window=32, **kw)
+    W, trials = ix.autotune_window(t, m, 0.9)
+    say("  " + ", ".join(f"W={x['window']}: {x['recall']:.3f}/{x['accel_error']:.4f}" for x in trials))
+    rec = [x["recall"] for x in trials]
+    ae = [x["accel_error"] for x in trials]
+    assert all(b >= a for a, b in zip(rec, rec[1:]))
+    assert all(b <= a + 1e-7 for a, b in zip(ae, ae[1:]))
+    first = next((x["window"] for x in trials if x["recall"] >= 0.9), trials[-1]["window"])
+    assert W == first and ix.info.window == W
+    bi, bc = ix.query(t, m, "index")
+    ix2 = nat.Index(vd, md, K, window=W, **kw)
+    b2, c2 = ix2.query(t, m, "index")
+    assert np.array_equal(host(bi), host(b2))
+    assert np.array_equal(host(bc).view(np.uint32), host(c2).view(np.uint32))
