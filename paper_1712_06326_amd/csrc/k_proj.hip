@@ -104,29 +104,40 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs a) {
 }
 
 // ------------------------------------------------------------ keys
-__global__ void key_kernel(KeyArgs a) {
+// One thread per (subset, rank): grid cell of the projection, then one key
+// per shifted curve. MD bounds the reduced dimension at compile time so the
+// per-axis arrays stay in registers.
+template <int MD>
+__global__ __launch_bounds__(256) void key_kernel(KeyArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.cnt * a.S) return;
     const int s = (int)(i / a.cnt);
     const int64_t r = i - (int64_t)s * a.cnt;
-    uint32_t u[kMaxD], v[kMaxD];
+    uint32_t u[MD], v[MD];
     const uint64_t sp = (uint64_t)a.span[s];
-    for (int d = 0; d < a.D; d++) {
-        const int64_t rel = (int64_t)a.y[r * a.ystride + s * a.D + d] - a.lo[s * a.D + d];
-        uint64_t q = rel > 0 ? ((uint64_t)rel * (uint64_t)(a.R - 1)) / sp : 0;
-        if (q > (uint64_t)(a.R - 1)) q = a.R - 1;
-        u[d] = (uint32_t)q;
+#pragma unroll
+    for (int d = 0; d < MD; d++) {
+        u[d] = 0;
+        if (d < a.D) {
+            const int64_t rel = (int64_t)a.y[r * a.ystride + s * a.D + d] - a.lo[s * a.D + d];
+            uint64_t q = rel > 0 ? ((uint64_t)rel * (uint64_t)(a.R - 1)) / sp : 0;
+            if (q > (uint64_t)(a.R - 1)) q = a.R - 1;
+            u[d] = (uint32_t)q;
+        }
     }
     const int64_t rank = a.r0 + r;
     const uint32_t id = a.dict[rank];
     for (int j = 0; j < a.L; j++) {
         const uint32_t sh = (uint32_t)(((int64_t)j * a.R) / (a.D + 1));
-        for (int d = 0; d < a.D; d++) v[d] = u[d] + sh;
-        if (a.curve == SFC_CURVE_HILBERT) hilbert_axes_to_transpose(v, a.D, a.b);
+#pragma unroll
+        for (int d = 0; d < MD; d++) v[d] = u[d] + sh;
+        if (a.curve == SFC_CURVE_HILBERT) hilbert_axes_to_transpose<MD>(v, a.D, a.b);
         uint64_t w[kMaxKeyWords];
-        interleave_words(v, a.D, a.b, a.W64, w);
+        interleave_words<MD>(v, a.D, a.b, a.W64, w);
         const int64_t arr = (int64_t)s * a.L + j;
-        for (int k = 0; k < a.W64; k++) a.keys[(arr * a.W64 + k) * a.n + rank] = w[k];
+#pragma unroll
+        for (int k = 0; k < kMaxKeyWords; k++)
+            if (k < a.W64) a.keys[(arr * a.W64 + k) * a.n + rank] = w[k];
         a.ids[arr * a.n + rank] = id;
     }
 }
@@ -213,7 +224,11 @@ sfc_status launch_span(const int32_t* mn, const int32_t* mx, int S, int D, int64
 
 sfc_status launch_keys(const KeyArgs& a, hipStream_t st) {
     if (a.cnt == 0) return SFC_OK;
-    key_kernel<<<blocks_for(a.cnt * a.S), 256, 0, st>>>(a);
+    if (a.D < 1 || a.D > kMaxD) return fail(SFC_EINVAL, "keys: reduced dimension out of range");
+    const unsigned nb = blocks_for(a.cnt * a.S);
+    if (a.D <= 8) key_kernel<8><<<nb, 256, 0, st>>>(a);
+    else if (a.D <= 16) key_kernel<16><<<nb, 256, 0, st>>>(a);
+    else key_kernel<kMaxD><<<nb, 256, 0, st>>>(a);
     return launched("key_kernel");
 }
 

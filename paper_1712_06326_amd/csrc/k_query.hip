@@ -145,9 +145,9 @@ __global__ __launch_bounds__(64) void prologue_kernel(QueryIndexView v, const fl
         const uint32_t sh = (uint32_t)(((int64_t)j * v.R) / (D + 1));
 #pragma unroll
         for (int d = 0; d < D; d++) cell[d] = u[d] + sh;
-        if (v.curve == SFC_CURVE_HILBERT) hilbert_axes_to_transpose(cell, D, v.b);
+        if (v.curve == SFC_CURVE_HILBERT) hilbert_axes_to_transpose<D>(cell, D, v.b);
         uint64_t w[kMaxKeyWords];
-        interleave_words(cell, D, v.b, v.W64, w);
+        interleave_words<D>(cell, D, v.b, v.W64, w);
         for (int k = 0; k < v.W64; k++) qkeys[(q * v.L + j) * v.W64 + k] = w[k];
     }
 }

@@ -7,40 +7,63 @@
 namespace sfc {
 
 // Hilbert index of a point by J. Skilling's transpose method ("Programming
-// the Hilbert curve", AIP Conf. Proc. 707, 2004), in place on X[0..D).
+// the Hilbert curve", AIP Conf. Proc. 707, 2004), in place on X[0..D). The
+// loops over axes run to the compile-time bound MD >= D with guards, so X
+// stays in registers; the conditional exchanges are written as selects.
+template <int MD>
 __device__ __forceinline__ void hilbert_axes_to_transpose(uint32_t* X, int D, int b) {
     const uint32_t top = 1u << (b - 1);
     for (uint32_t q = top; q > 1; q >>= 1) {
         const uint32_t low = q - 1;
-        for (int i = 0; i < D; i++) {
-            if (X[i] & q) {
-                X[0] ^= low;
-            } else {
-                const uint32_t sw = (X[0] ^ X[i]) & low;
-                X[0] ^= sw;
+#pragma unroll
+        for (int i = 0; i < MD; i++) {
+            if (i < D) {
+                const bool on = (X[i] & q) != 0;
+                const uint32_t sw = on ? 0u : ((X[0] ^ X[i]) & low);
+                X[0] ^= on ? low : sw;
                 X[i] ^= sw;
             }
         }
     }
-    for (int i = 1; i < D; i++) X[i] ^= X[i - 1];
+#pragma unroll
+    for (int i = 1; i < MD; i++)
+        if (i < D) X[i] ^= X[i - 1];
+    uint32_t last = 0;
+#pragma unroll
+    for (int i = 0; i < MD; i++)
+        if (i == D - 1) last = X[i];
     uint32_t flip = 0;
     for (uint32_t q = top; q > 1; q >>= 1)
-        if (X[D - 1] & q) flip ^= q - 1;
-    for (int i = 0; i < D; i++) X[i] ^= flip;
+        if (last & q) flip ^= q - 1;
+#pragma unroll
+    for (int i = 0; i < MD; i++)
+        if (i < D) X[i] ^= flip;
 }
 
 // Bit l of coordinate d lands at bit l*D + (D-1-d) of the D*b-bit key:
 // level by level from the top, dim 0 first. Word 0 is the most significant.
-// Each level's D bits are gathered into one group and placed at once.
+// The levels enter a 256-bit accumulator from the top level down: each
+// shifts it left by D and puts its D bits (dim 0 highest) at the bottom.
+template <int MD>
 __device__ __forceinline__ void interleave_words(const uint32_t* v, int D, int b, int W64, uint64_t* w) {
-    for (int i = 0; i < W64; i++) w[i] = 0;
-    for (int l = 0; l < b; l++) {
+    static_assert(kMaxKeyWords == 4, "the accumulator holds four words");
+    uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;   // a0 most significant
+    const int rs = 64 - D;                     // 1 <= D <= 32
+    for (int l = b - 1; l >= 0; l--) {
         uint64_t grp = 0;
-        for (int d = 0; d < D; d++) grp = (grp << 1) | ((v[d] >> l) & 1u);
-        const int pos = l * D;
-        const int wi = W64 - 1 - (pos >> 6), sh = pos & 63;
-        w[wi] |= grp << sh;
-        if (sh + D > 64) w[wi - 1] |= grp >> (64 - sh);
+#pragma unroll
+        for (int d = 0; d < MD; d++)
+            if (d < D) grp = (grp << 1) | ((v[d] >> l) & 1u);
+        a0 = (a0 << D) | (a1 >> rs);
+        a1 = (a1 << D) | (a2 >> rs);
+        a2 = (a2 << D) | (a3 >> rs);
+        a3 = (a3 << D) | grp;
+    }
+    // the key's words are the low W64 words of (a0, a1, a2, a3)
+#pragma unroll
+    for (int k = 0; k < kMaxKeyWords; k++) {
+        const int src = kMaxKeyWords - W64 + k;
+        w[k] = src == 0 ? a0 : src == 1 ? a1 : src == 2 ? a2 : a3;
     }
 }
 
