@@ -32,6 +32,8 @@ constexpr int kWaitScalar = 0xC07F;
 
 typedef const __attribute__((address_space(4))) float cfloat_as4;
 typedef const __attribute__((address_space(4))) uint32_t cu32_as4;
+// four floats at dword alignment
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
 // Wave-uniform loads through the scalar cache.
 __device__ inline float ldu(const float* p) { return *(cfloat_as4*)p; }
@@ -90,8 +92,19 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
                 const float* vp = p.vol + (base + roff + x0) * C;
                 float v[SEG];
                 if (whole) {
+                    // 16-byte loads at 4-byte alignment (global loads of
+                    // this width need only dword alignment)
+                    const f4u* vp4 = reinterpret_cast<const f4u*>(vp);
 #pragma unroll
-                    for (int i = 0; i < SEG; i++) v[i] = vp[i];
+                    for (int i = 0; i < SEG / 4; i++) {
+                        const f4u x = vp4[i];
+                        v[4 * i] = x.x;
+                        v[4 * i + 1] = x.y;
+                        v[4 * i + 2] = x.z;
+                        v[4 * i + 3] = x.w;
+                    }
+#pragma unroll
+                    for (int i = (SEG / 4) * 4; i < SEG; i++) v[i] = vp[i];
                 } else {
 #pragma unroll
                     for (int i = 0; i < SEG; i++)
@@ -344,6 +357,27 @@ const ScanEntry* scan_entry(int nd, int K, int C, int v) {
 
 inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+// Workgroups of a table entry resident on the whole device at once (its
+// occupancy per CU from its register use, times the CUs), cached per entry.
+int64_t resident_slots(const ScanEntry* e) {
+    constexpr int kEntries = sizeof(kScanTable) / sizeof(kScanTable[0]);
+    static int64_t slots[kEntries] = {0};
+    const int idx = (int)(e - kScanTable);
+    if (slots[idx] == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(e->fn),
+                                                         kLanes, 0) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = 4;
+        slots[idx] = (int64_t)per_cu * cus;
+    }
+    return slots[idx];
+}
+
 }  // namespace
 
 bool scan_supported(int nd, int K, int C) { return scan_entry(nd, K, C, 0) != nullptr; }
@@ -399,14 +433,17 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     p.tiles_per_line = (p.line_len + tw - 1) / tw;
     p.n_tiles = n_lines * p.tiles_per_line;
     // queries per workgroup, then tiles per workgroup so that the grid holds
-    // about 4096 workgroups (16 per CU)
-    int64_t qpw = a.query_block > 0 ? a.query_block : 512;
+    // about 16 rounds of the workgroups resident at once: with equal
+    // workgroups the last, partly filled round then costs a few percent
+    // instead of up to a third of the launch
+    int64_t qpw = a.query_block > 0 ? a.query_block : 256;
     qpw = ((qpw + ent->qb - 1) / ent->qb) * ent->qb;
     if (qpw > a.Q) qpw = ((a.Q + ent->qb - 1) / ent->qb) * ent->qb;
     p.q_per_wg = qpw;
     p.qpad = scan_qpad(a.Q);
     const int64_t qsplit = (a.Q + qpw - 1) / qpw;
-    int64_t tpw = (p.n_tiles * qsplit + 4095) / 4096;
+    const int64_t target = 16 * resident_slots(ent);
+    int64_t tpw = (p.n_tiles * qsplit + target - 1) / target;
     tpw = ((tpw + 3) / 4) * 4;
     if (tpw < 4) tpw = 4;
     p.tiles_per_wg = tpw;
