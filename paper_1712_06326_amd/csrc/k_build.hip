@@ -371,10 +371,12 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
     const TriStore<kSplit> T{lds, Tg, G, m};
     const double tiny = state[s].tiny;
     const int done0 = state[s].done;
-    // this thread's blocks: items u = tid + k * kJacThreads of the np x np
-    // grid, (a, b) = (u / np, u % np), stepped without division; a < b only
-    const int da = kJacThreads / np, db = kJacThreads % np;
-    const int a0 = tid / np, b0 = tid % np;
+    // this thread's blocks: items u = tid + k * kJacThreads of the block
+    // enumeration, (r, c) = (u / np, u % np) stepped without division
+    const int nblk = np * (np - 1) / 2;
+    const int nfull = (np & 1) ? nblk : np * (np / 2 - 1);
+    const int dr = kJacThreads / np, dc = kJacThreads % np;
+    const int r0 = tid / np, c0 = tid % np;
     __syncthreads();
 
     int sw = 0;
@@ -416,18 +418,29 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
             }
             __syncthreads();
             {
-                int a = a0, b = b0;
-                while (a < np) {
-                    if (a < b) {
-                        const double2 ea = scs[a], eb = scs[b];
-                        if (ea.x >= 0.0 || eb.x >= 0.0)
-                            rotate_cross(T, spair[a], spair[b], ea.x, ea.y, eb.x, eb.y, m);
+                // the np (np - 1) / 2 blocks a < b, by cyclic distance: row r
+                // of an np-wide rectangle pairs c with (c + r + 1) mod np;
+                // for even np a last half row holds the pairs np / 2 apart
+                int r = r0, c = c0;
+                for (int u = tid; u < nblk; u += kJacThreads) {
+                    int a, b;
+                    if (u < nfull) {
+                        int y = c + r + 1;
+                        if (y >= np) y -= np;
+                        a = c < y ? c : y;
+                        b = c < y ? y : c;
+                    } else {
+                        a = u - nfull;
+                        b = a + np / 2;
                     }
-                    a += da;
-                    b += db;
-                    if (b >= np) {
-                        b -= np;
-                        a++;
+                    const double2 ea = scs[a], eb = scs[b];
+                    if (ea.x >= 0.0 || eb.x >= 0.0)
+                        rotate_cross(T, spair[a], spair[b], ea.x, ea.y, eb.x, eb.y, m);
+                    r += dr;
+                    c += dc;
+                    if (c >= np) {
+                        c -= np;
+                        r++;
                     }
                 }
             }
