@@ -58,18 +58,24 @@ __device__ inline int64_t blocked_index(int64_t row, int k, int64_t rows) {
 
 // B[c][k] for dictionary entry c (rank order): per pixel C codes v', then
 // the high and low byte of sum_ch v'^2; zero rows pad n to the tile size.
-__global__ void dict_operand_kernel(const uint8_t* __restrict__ xq, const uint32_t* __restrict__ dict,
-                                    int64_t n, int64_t npad, const int32_t* __restrict__ elem_off,
-                                    int Kd, int C, int Kp, uint16_t* __restrict__ B) {
+// One thread writes 8 consecutive columns of a row (16 bytes); four lanes
+// cover a row's 32-column chunk and a wave 16 consecutive rows of it, one
+// contiguous kilobyte. blockIdx.y is the chunk.
+__global__ __launch_bounds__(256) void dict_operand_kernel(
+    const uint8_t* __restrict__ xq, const uint32_t* __restrict__ dict, int64_t n, int64_t npad,
+    const int32_t* __restrict__ elem_off, int Kd, int C, int Kp, uint16_t* __restrict__ B) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npad * 4) return;
+    const int64_t c = t >> 2;
     const int cols = C + 2;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npad * Kp;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = i / Kp;
-        const int k = (int)(i - c * Kp);
-        const int rho = k / cols, j = k - rho * cols;
+    const int k0 = (int)blockIdx.y * 32 + (int)(t & 3) * 8;
+    int rho = k0 / cols, j = k0 - rho * cols;
+    const uint8_t* base = c < n ? xq + (int64_t)dict[c] * C : nullptr;
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
         int v = 0;
-        if (c < n && rho < Kd) {
-            const uint8_t* base = xq + (int64_t)dict[c] * C;
+        if (base && rho < Kd) {
             if (j < C) {
                 v = (int)base[elem_off[rho * C + j]] - 128;
             } else {
@@ -81,8 +87,15 @@ __global__ void dict_operand_kernel(const uint8_t* __restrict__ xq, const uint32
                 v = (j == C) ? (sq >> 8) : (sq & 255);
             }
         }
-        B[blocked_index(c, k, npad)] = bf16_bits_of_int(v);
+        const uint32_t bits = bf16_bits_of_int(v);
+        if (e & 1) w[e >> 1] |= bits << 16;
+        else w[e >> 1] = bits;
+        if (++j == cols) {
+            j = 0;
+            rho++;
+        }
     }
+    *reinterpret_cast<u32x4*>(B + blocked_index(c, k0, npad)) = u32x4{w[0], w[1], w[2], w[3]};
 }
 
 // A[q][k] (same column layout as B), T2[q] = sum_known t'^2, kq[q] = known
@@ -571,8 +584,10 @@ sfc_status plan_filter(int Kd, int C, int64_t Q, int64_t n, FilterArgs* a) {
 sfc_status launch_dict_operand(const uint8_t* xq, const uint32_t* dict, int64_t n, int64_t npad,
                                const int32_t* elem_off, int Kd, int C, int Kp, uint16_t* B,
                                hipStream_t st) {
-    const unsigned nb = (unsigned)std::min<int64_t>(1 << 20, (npad * Kp + 255) / 256);
-    dict_operand_kernel<<<nb, 256, 0, st>>>(xq, dict, n, npad, elem_off, Kd, C, Kp, B);
+    if (Kp % 32 != 0 || Kp / 32 > 65535 || npad * 4 > (int64_t)0x7fffffff * 256)
+        return fail(SFC_EUNSUPPORTED, "dictionary operand: shape out of range");
+    dict_operand_kernel<<<dim3(blocks_for(npad * 4), Kp / 32), 256, 0, st>>>(xq, dict, n, npad,
+                                                                             elem_off, Kd, C, Kp, B);
     return launched("dict_operand_kernel");
 }
 
