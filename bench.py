@@ -412,6 +412,9 @@ def large_pass(torch, native, synth, ev):
         torch.cuda.synchronize()
     idx_ms = a.elapsed_time(b)
     ts, ms = t[w.sel].contiguous(), m[w.sel].contiguous()
+    # the float32 scan's tile shape, autotuned on the first 512 sampled targets
+    shape = ix.autotune(ts[:512].contiguous(), ms[:512].contiguous())
+    log(f"n~1.25e8: autotuned float32-scan shape {shape}")
     for _ in range(2):
         a = ev()
         bi_s, bc_s = ix.query(ts, ms, "fp32")
@@ -432,6 +435,7 @@ def large_pass(torch, native, synth, ev):
            "fp32_scan_qps": round(ms.shape[0] / (scan_ms * 1e-3), 2),
            "fp32_scan_tflops": round(scan_tf, 2),
            "fp32_scan_frac_of_fp32_peak": round(scan_tf / PEAK_FP32_VALU, 4),
+           "fp32_scan_shape": shape,
            "index_recall_at_1_pct": round(100 * float(np.mean(bx == bs)), 3),
            "index_acceleration_error_pct": round(
                float(np.mean(np.sqrt(cx[ok].astype(np.float64)) / np.sqrt(cs[ok]) - 1)) * 100, 4),

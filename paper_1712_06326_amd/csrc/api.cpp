@@ -186,6 +186,21 @@ sfc_status build_dictionary(sfc_index* ix, const uint8_t* mask) {
     ix->n = n;
     SFC_TRY(dev_alloc((void**)&ix->dict, (size_t)n * sizeof(uint32_t), "dictionary ids"));
     SFC_TRY(launch_compact(ix->valid, g.nvox, nullptr, ix->dict, n, count_dev, cscratch, st));
+    // the full scan's spans: flagged, counted, compacted (the flags reuse
+    // the scratch, which holds nvox bytes and there are nvox / 8 slots)
+    const int64_t slots = scan_span_slots(g);
+    if (slots > 0 && slots < (int64_t)0xffffffffLL) {
+        SFC_TRY(launch_span_flags(g, ix->valid, t8, st));
+        SFC_TRY(launch_compact(t8, slots, nullptr, nullptr, 0, count_dev, cscratch, st));
+        int64_t ns = 0;
+        SFC_HIP(hipMemcpyAsync(&ns, count_dev, sizeof(ns), hipMemcpyDeviceToHost, st));
+        SFC_HIP(hipStreamSynchronize(st));
+        if (ns > 0) {
+            SFC_TRY(dev_alloc((void**)&ix->spans, (size_t)ns * sizeof(uint32_t), "scan spans"));
+            SFC_TRY(launch_compact(t8, slots, nullptr, ix->spans, ns, count_dev, cscratch, st));
+            ix->n_spans = ns;
+        }
+    }
     SFC_HIP(hipStreamSynchronize(st));
     return SFC_OK;
 }
@@ -195,6 +210,7 @@ sfc_status build_dictionary(sfc_index* ix, const uint8_t* mask) {
 sfc_index::~sfc_index() {
     sfc::dev_free(valid);
     sfc::dev_free(dict);
+    sfc::dev_free(spans);
     sfc::release_sfc(this);
 }
 
@@ -216,7 +232,8 @@ sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int
     SFC_TRY(launch_zero_f32(tp + (size_t)Q * g.Kd * g.C, (int64_t)(qpad - Q) * g.Kd * g.C, ix->st));
     SFC_TRY(launch_fill_u64(best_dev, Q, ~0ull, ix->st));
     ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best_dev, ix->opt.query_block,
-               ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant};
+               ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant,
+               ix->spans, ix->n_spans};
     SFC_TRY(ix->timer.begin("scan_fp32_kernel", ix->st));
     SFC_TRY(launch_scan_fp32(g, a, ix->st));
     return ix->timer.end(ix->st);

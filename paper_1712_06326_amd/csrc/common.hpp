@@ -85,11 +85,17 @@ struct ScanArgs {
     uint64_t* best;            // [Q], pre-filled with ~0
     int query_block;           // 0 = default
     int variant;               // scan shape variant (0 = default)
+    const uint32_t* spans;     // dictionary spans (null: whole lines)
+    int64_t n_spans;
 };
 sfc_status launch_pack_rowmask(const uint8_t* m, const Grid& g, int64_t Q, uint32_t* rowmask,
                                hipStream_t st);
 sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st);
 int64_t scan_qpad(int64_t Q);  // row-mask query stride
+// spans of 8 consecutive line positions (the scan's tiling of the interior)
+// that hold at least one dictionary centre: slots, flags, compacted list
+int64_t scan_span_slots(const Grid& g);
+sfc_status launch_span_flags(const Grid& g, const uint8_t* valid, uint8_t* flags, hipStream_t st);
 int scan_variants(int nd, int K, int C);
 sfc_status launch_unpack_best(const uint64_t* best, int64_t Q, int64_t* id, float* cost,
                               hipStream_t st);

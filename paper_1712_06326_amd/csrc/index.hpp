@@ -52,6 +52,8 @@ struct sfc_index {
     const float* vol = nullptr;      // borrowed
     uint8_t* valid = nullptr;        // [nvox] 1 = dictionary centre
     uint32_t* dict = nullptr;        // [n] ascending centre ids
+    uint32_t* spans = nullptr;       // [n_spans] scan spans holding a centre
+    int64_t n_spans = 0;
     int64_t n = 0;
 
     // ---- SFC multi-index (Section II)

@@ -68,15 +68,31 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
             bid[qi] = 0xffffffffu;
         }
         for (int64_t tl = tl0 + wave; tl < tl1; tl += kLanes / 64) {
-            const int64_t line = tl / p.tiles_per_line;
-            const int64_t x0 = (tl - line * p.tiles_per_line) * (64 * NX) + (int64_t)lane * NX;
+            int64_t line, x0;
+            if (p.spans) {
+                // 8 * NX spans per wave tile, NX adjacent candidates per lane
+                static_assert(8 % NX == 0, "a lane's candidates lie in one span");
+                const int64_t li = tl * (8 * NX) + (lane * NX) / 8;
+                if (li < p.n_spans) {
+                    const uint32_t sp = p.spans[li];
+                    const uint32_t ln = sp / (uint32_t)p.spans_per_line;
+                    line = ln;
+                    x0 = (int64_t)(sp - ln * (uint32_t)p.spans_per_line) * 8 + (lane * NX) % 8;
+                } else {
+                    line = 0;            // past the list: no candidate
+                    x0 = p.line_len;
+                }
+            } else {
+                line = tl / p.tiles_per_line;
+                x0 = (tl - line * p.tiles_per_line) * (64 * NX) + (int64_t)lane * NX;
+            }
             int64_t base;
             if (ND == 2) {
                 base = (line + H) * p.stride[0];
             } else {
-                const int64_t iy = p.shape[1] - 2 * H;
-                const int64_t z = line / iy, y = line - z * iy;
-                base = (z + H) * p.stride[0] + (y + H) * p.stride[1];
+                const uint32_t iy = (uint32_t)(p.shape[1] - 2 * H);
+                const uint32_t z = (uint32_t)line / iy, y = (uint32_t)line - z * iy;
+                base = ((int64_t)z + H) * p.stride[0] + ((int64_t)y + H) * p.stride[1];
             }
             const bool whole = x0 + NX <= p.line_len;   // all NX candidates inside the line
             float acc[QB][NX];
@@ -316,6 +332,27 @@ __global__ void unpack_best_kernel(const uint64_t* __restrict__ best, int64_t Q,
     }
 }
 
+// flags[s] = 1 when span s (positions 8 (s % spl) .. + 7 of interior line
+// s / spl) holds a dictionary centre
+__global__ void span_flags_kernel(const uint8_t* __restrict__ valid, int nd, int64_t st0,
+                                  int64_t st1, int64_t iy, int H, int64_t line_len, int64_t spl,
+                                  int64_t slots, uint8_t* __restrict__ flags) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= slots) return;
+    const int64_t line = s / spl, x8 = s - line * spl;
+    int64_t base;
+    if (nd == 2) {
+        base = (line + H) * st0;
+    } else {
+        const int64_t z = line / iy, y = line - z * iy;
+        base = (z + H) * st0 + (y + H) * st1;
+    }
+    uint8_t any = 0;
+    const int64_t x1 = min(x8 * 8 + 8, line_len);
+    for (int64_t x = x8 * 8; x < x1; x++) any |= valid[base + x + H];
+    flags[s] = any ? 1 : 0;
+}
+
 using ScanFn = void (*)(ScanParams);
 
 struct ScanEntry {
@@ -390,6 +427,34 @@ int scan_variants(int nd, int K, int C) {
 
 int64_t scan_qpad(int64_t Q) { return ((Q + kScanQB - 1) / kScanQB) * kScanQB; }  // multiple of every QB
 
+namespace {
+void scan_lines(const Grid& g, int64_t* n_lines, int64_t* line_len) {
+    int64_t nl = 1;
+    for (int i = 0; i < g.nd - 1; i++) nl *= (g.shape[i] - 2 * g.h);
+    *n_lines = nl;
+    *line_len = g.shape[g.nd - 1] - 2 * g.h;
+}
+}  // namespace
+
+int64_t scan_span_slots(const Grid& g) {
+    int64_t nl, len;
+    scan_lines(g, &nl, &len);
+    if (nl <= 0 || len <= 0) return 0;
+    return nl * ((len + 7) / 8);
+}
+
+sfc_status launch_span_flags(const Grid& g, const uint8_t* valid, uint8_t* flags, hipStream_t st) {
+    int64_t nl, len;
+    scan_lines(g, &nl, &len);
+    const int64_t slots = scan_span_slots(g);
+    if (slots == 0) return SFC_OK;
+    span_flags_kernel<<<blocks_for(slots), 256, 0, st>>>(
+        valid, g.nd, g.stride[0], g.nd == 3 ? g.stride[1] : 0,
+        g.nd == 3 ? g.shape[1] - 2 * g.h : 1, g.h, len, (len + 7) / 8, slots, flags);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SFC_OK : check_hip(e, "span_flags_kernel");
+}
+
 sfc_status launch_pack_rowmask(const uint8_t* m, const Grid& g, int64_t Q, uint32_t* rowmask,
                                hipStream_t st) {
     if (Q == 0) return SFC_OK;
@@ -432,6 +497,13 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     const int64_t tw = 64 * ent->nx;   // candidates per wave tile
     p.tiles_per_line = (p.line_len + tw - 1) / tw;
     p.n_tiles = n_lines * p.tiles_per_line;
+    if (a.spans && a.n_spans > 0) {
+        // the tiles walk the spans that hold a centre (8 * NX per tile)
+        p.spans = a.spans;
+        p.n_spans = a.n_spans;
+        p.spans_per_line = (p.line_len + 7) / 8;
+        p.n_tiles = (a.n_spans + 8 * ent->nx - 1) / (8 * ent->nx);
+    }
     // queries per workgroup, then tiles per workgroup so that the grid holds
     // about 16 rounds of the workgroups resident at once: with equal
     // workgroups the last, partly filled round then costs a few percent
