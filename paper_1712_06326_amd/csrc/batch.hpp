@@ -49,9 +49,11 @@ struct BatchMeta {
 bool batch_scan_supported(int K);
 int batch_query_block(int shape);
 // (QB, NX) of shape set `shape` (0, 1, 2) and the image's tile count
+// spans/n_spans: the image's dictionary spans (null: whole lines)
 ScanParams batch_image_params(const Grid& g, const float* vol, const uint8_t* valid,
-                              const float* t, const uint32_t* rowmask, uint64_t* best, int64_t Q,
-                              int64_t qpad, int shape, int64_t* n_tiles);
+                              const uint32_t* spans, int64_t n_spans, const float* t,
+                              const uint32_t* rowmask, uint64_t* best, int64_t Q, int64_t qpad,
+                              int shape, int64_t* n_tiles);
 sfc_status launch_batch_prep(const float* targets, const uint8_t* masks, const BatchMeta* meta,
                              const int64_t* pad_start, int n_images, int K, int64_t total_pad,
                              float* tpad, uint32_t* rowmask, uint64_t* best, hipStream_t st);

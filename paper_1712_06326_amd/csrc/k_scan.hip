@@ -567,8 +567,9 @@ sfc_status launch_batch_scan(int K, int shape, const ScanParams* imgs, const int
 }
 
 ScanParams batch_image_params(const Grid& g, const float* vol, const uint8_t* valid,
-                              const float* t, const uint32_t* rowmask, uint64_t* best, int64_t Q,
-                              int64_t qpad, int shape, int64_t* n_tiles) {
+                              const uint32_t* spans, int64_t n_spans, const float* t,
+                              const uint32_t* rowmask, uint64_t* best, int64_t Q, int64_t qpad,
+                              int shape, int64_t* n_tiles) {
     ScanParams p{};
     p.vol = vol;
     p.valid = valid;
@@ -585,6 +586,12 @@ ScanParams batch_image_params(const Grid& g, const float* vol, const uint8_t* va
     const int64_t lines = g.shape[0] - 2 * g.h;
     p.tiles_per_line = p.line_len > 0 ? (p.line_len + 64 * nx - 1) / (64 * nx) : 0;
     p.n_tiles = lines > 0 ? lines * p.tiles_per_line : 0;
+    if (spans && n_spans > 0 && p.n_tiles > 0) {
+        p.spans = spans;
+        p.n_spans = n_spans;
+        p.spans_per_line = (p.line_len + 7) / 8;
+        p.n_tiles = (n_spans + 8 * nx - 1) / (8 * nx);
+    }
     p.qpad = qpad;
     *n_tiles = p.n_tiles;
     return p;

@@ -109,7 +109,8 @@ sfc_status build_graph(sfc_batch* b, const float* targets, const uint8_t* masks,
     int64_t work = 0;
     for (int i = 0; i < n; i++) {
         const sfc_index* h = b->imgs[i];
-        params[i] = batch_image_params(h->g, h->vol, h->valid, tp + meta[i].tpad_off,
+        params[i] = batch_image_params(h->g, h->vol, h->valid, h->spans, h->n_spans,
+                                       tp + meta[i].tpad_off,
                                        rm + meta[i].rm_off, bs + meta[i].q_off, meta[i].Q,
                                        meta[i].qpad, b->shape, &tiles[i]);
         chan[i] = h->g.C;
