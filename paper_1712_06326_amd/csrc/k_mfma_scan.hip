@@ -262,9 +262,11 @@ __global__ __launch_bounds__(256, 2) void filter_kernel(FilterArgs a) {
         while (nt < a.ntiles && !filter_tile(a, MODE, nt, nqt, nct)) nt += G;
         const bool more = nt < a.ntiles;
         if (MODE != 1) {
-            // this tile's query thresholds (read after the next barrier)
+            // this tile's query thresholds (read after the next barrier); a
+            // query whose list already overflowed (the float32 scan will
+            // answer it) takes no more hits
             const int64_t q = qt * BM + tid;
-            sth[tid] = q < a.Q ? a.thr[q] - a.T2[q] : (int32_t)0x80000000;
+            sth[tid] = (q < a.Q && a.cnt[q] < a.cap) ? a.thr[q] - a.T2[q] : (int32_t)0x80000000;
         }
         __syncthreads();
         f32x16 acc[TI][TJ];
