@@ -273,6 +273,21 @@ sfc_status sfc_index_export(const sfc_index *idx, int32_t subset, int32_t curve,
 /* Release the handle and its device memory. NULL is a no-op. */
 void sfc_index_free(sfc_index *idx);
 
+/* The sort that orders every curve of an index (Section II.C: a curve's
+ * entries by curve position), on caller arrays: each of `arrays`
+ * consecutive arrays of n (key, id) pairs is sorted in place by key
+ * ascending, stably (equal keys keep their input order; with ids ascending
+ * on entry that is (key, id) order). keys: device uint64
+ * [arrays][key_words][n], word 0 the most significant; ids: device uint32
+ * [arrays][n]. An LSD radix sort over 8-bit digits that skips digit
+ * positions constant over the arrays; its scratch (about 24 bytes per pair,
+ * at most 8 GiB at a time) is allocated and freed inside the call, which
+ * synchronizes `stream` (hipStream_t, NULL = default) before returning.
+ * SFC_EINVAL: null pointer, n < 0, arrays < 1 or key_words outside 1..4;
+ * SFC_EUNSUPPORTED: n >= 2^32. n <= 1 is a no-op. */
+sfc_status sfc_sort_pairs(uint64_t *keys, uint32_t *ids, int64_t n, int32_t key_words,
+                          int32_t arrays, void *stream);
+
 /* Fill loop (Section I, Criminisi order): while a voxel is unknown, pick the
  * front voxel of highest (priority, confidence, -id) (SFC_ORDER_CRIMINISI)
  * or the lowest front id (SFC_ORDER_RASTER), query its target patch in

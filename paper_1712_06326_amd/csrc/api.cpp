@@ -11,6 +11,7 @@
 #include <tuple>
 #include <vector>
 
+#include "build.hpp"
 #include "common.hpp"
 #include "index.hpp"
 
@@ -495,6 +496,18 @@ sfc_status sfc_autotune(sfc_index* ix, const float* targets, const uint8_t* targ
     remember_variant(g.nd, g.K, g.C, bestv);
     *chosen = bestv + 1;
     return SFC_OK;
+}
+
+sfc_status sfc_sort_pairs(uint64_t* keys, uint32_t* ids, int64_t n, int32_t key_words,
+                          int32_t arrays, void* stream) {
+    clear_error();
+    if (!keys || !ids) return fail(SFC_EINVAL, "sfc_sort_pairs: null pointer");
+    if (n < 0 || arrays < 1 || key_words < 1 || key_words > kMaxKeyWords)
+        return fail(SFC_EINVAL, "sfc_sort_pairs: n < 0, arrays < 1 or key_words outside 1..4");
+    if (n >= (int64_t(1) << 32)) return fail(SFC_EUNSUPPORTED, "sfc_sort_pairs: n >= 2^32");
+    if (n <= 1) return SFC_OK;
+    return sort_key_arrays(keys, ids, n, key_words, arrays, 64 * key_words,
+                           static_cast<hipStream_t>(stream));
 }
 
 sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_t* target_masks,

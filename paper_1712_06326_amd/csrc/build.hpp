@@ -31,6 +31,13 @@ sfc_status launch_cov_matrix(const uint64_t* sum, const uint64_t* gram, int64_t 
 size_t jacobi_scratch_bytes(int S, int mmax);
 sfc_status launch_jacobi(double* A, double* V, void* scratch, const int32_t* m, int S, int mmax,
                          int32_t* sweeps, hipStream_t st);
+// ---- sort of key arrays (allocates and frees its scratch; synchronizes st)
+// narr arrays of n (key, id) pairs, keys [narr][W64][n] (word 0 most
+// significant), ids [narr][n]: each array by (key, position), stable, over
+// the key bits below nbits.
+sfc_status sort_key_arrays(uint64_t* keys, uint32_t* ids, int64_t n, int W64, int narr,
+                           int nbits, hipStream_t st);
+
 // int8 basis [S][mmax][D] (row-major per subset) from A/V
 sfc_status launch_basis(const double* A, const double* V, const int32_t* m, int S, int mmax,
                         int D, int8_t* basis, hipStream_t st);

@@ -160,6 +160,42 @@ QueryIndexView view_of(const sfc_index* ix) {
 
 }  // namespace
 
+// Sorts narr consecutive arrays of n (key, id) pairs (keys [narr][W64][n],
+// ids [narr][n]) by (key, position), stable. The arrays are sorted in groups
+// whose ping-pong copies fit a fixed budget, each group with the union of
+// its arrays' varying 8-bit digit positions below nbits.
+sfc_status sort_key_arrays(uint64_t* keys, uint32_t* ids, int64_t n, int W64, int narr,
+                           int nbits, hipStream_t st) {
+    if (n <= 1 || narr <= 0) return SFC_OK;
+    Temp tmp;
+    uint64_t* varying = nullptr;
+    SFC_TRY(tmp.alloc((void**)&varying, (size_t)narr * W64 * 8, "varying bits"));
+    SFC_TRY(zero(varying, (size_t)narr * W64 * 8, st));
+    SFC_TRY(launch_varying_bits(keys, n, W64, narr, varying, st));
+    std::vector<uint64_t> hv((size_t)narr * W64);
+    SFC_HIP(hipMemcpyAsync(hv.data(), varying, hv.size() * 8, hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    const size_t per_arr = sort_scratch_bytes(n, W64, 1);
+    int group = (int)std::max<size_t>(1, std::min<size_t>(narr, (size_t(8) << 30) / per_arr));
+    void* sscratch = nullptr;
+    SFC_TRY(tmp.alloc(&sscratch, sort_scratch_bytes(n, W64, group), "sort scratch"));
+    for (int a0 = 0; a0 < narr; a0 += group) {
+        const int na = std::min(group, narr - a0);
+        SortPlan plan{};
+        for (int pb = 0; pb < nbits; pb += 8) {
+            const int w = W64 - 1 - (pb >> 6);
+            uint64_t bits = 0;
+            for (int a = a0; a < a0 + na; a++) bits |= (hv[(size_t)a * W64 + w] >> (pb & 63)) & 0xffull;
+            if (bits) plan.pass_bits[plan.n_passes++] = pb;
+        }
+        SFC_TRY(radix_sort(keys + (size_t)a0 * W64 * n, ids + (size_t)a0 * n, n, W64, na, plan,
+                           sscratch, st));
+    }
+    // the scratch is freed on return
+    SFC_HIP(hipStreamSynchronize(st));
+    return SFC_OK;
+}
+
 sfc_status check_sfc_args(const sfc_geometry* g, int K, int D, int L, const sfc_options& o) {
     if (D < 1) return fail(SFC_EINVAL, "reduced_dim must be >= 1");
     if (L < 1) return fail(SFC_EINVAL, "n_curves must be >= 1");
@@ -383,33 +419,7 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
     }
 
     // sort every (subset, curve) by (key, id)
-    uint64_t* varying = nullptr;
-    SFC_TRY(tmp.alloc((void**)&varying, (size_t)S * L * ix->W64 * 8, "varying bits"));
-    SFC_TRY(zero(varying, (size_t)S * L * ix->W64 * 8, st));
-    SFC_TRY(launch_varying_bits(ix->keys, ix->n, ix->W64, S * L, varying, st));
-    std::vector<uint64_t> hv((size_t)S * L * ix->W64);
-    SFC_HIP(hipMemcpyAsync(hv.data(), varying, hv.size() * 8, hipMemcpyDeviceToHost, st));
-    SFC_HIP(hipStreamSynchronize(st));
-    // arrays are sorted in groups whose ping-pong copies fit a fixed budget,
-    // each group with the union of its arrays' varying digit positions
-    const int narr = S * L;
-    const size_t per_arr = sort_scratch_bytes(ix->n, ix->W64, 1);
-    int group = (int)std::max<size_t>(1, std::min<size_t>(narr, (size_t(8) << 30) / per_arr));
-    void* sscratch = nullptr;
-    SFC_TRY(tmp.alloc(&sscratch, sort_scratch_bytes(ix->n, ix->W64, group), "sort scratch"));
-    const int nbits = D * ix->b;
-    for (int a0 = 0; a0 < narr; a0 += group) {
-        const int na = std::min(group, narr - a0);
-        SortPlan plan{};
-        for (int pb = 0; pb < nbits; pb += 8) {
-            const int w = ix->W64 - 1 - (pb >> 6);
-            uint64_t bits = 0;
-            for (int a = a0; a < a0 + na; a++) bits |= (hv[(size_t)a * ix->W64 + w] >> (pb & 63)) & 0xffull;
-            if (bits) plan.pass_bits[plan.n_passes++] = pb;
-        }
-        SFC_TRY(radix_sort(ix->keys + (size_t)a0 * ix->W64 * ix->n, ix->ids + (size_t)a0 * ix->n,
-                           ix->n, ix->W64, na, plan, sscratch, st));
-    }
+    SFC_TRY(sort_key_arrays(ix->keys, ix->ids, ix->n, ix->W64, S * L, D * ix->b, st));
 
     // host copies of the small parameters
     ix->h_basis.assign((size_t)S * mmax * D, 0);

@@ -94,6 +94,7 @@ _SIG = {
     "sfc_index_projection": (ST, [P, I32, P]),
     "sfc_index_export": (ST, [P, I32, I32, P, P]),
     "sfc_index_free": (None, [P]),
+    "sfc_sort_pairs": (ST, [P, P, I64, I32, I32, P]),
     "sfc_batch_create": (ST, [I32, P, P, P, I32, C.POINTER(Options), C.POINTER(P)]),
     "sfc_batch_query": (ST, [P, P, P, P, P, P]),
     "sfc_batch_autotune": (ST, [P, P, P, P, P, P, C.POINTER(C.c_int32)]),
@@ -170,6 +171,18 @@ def fill_front(mask: torch.Tensor) -> torch.Tensor:
     out = torch.empty(max(n.value, 1), dtype=torch.int64, device=mask.device)
     _check(_L.sfc_fill_front(_ptr(mask), C.byref(g), _ptr(out), n.value, C.byref(n), _stream()))
     return out[:n.value]
+
+
+def sort_pairs(keys: torch.Tensor, ids: torch.Tensor) -> None:
+    """Sorts in place, per array, (key, id) pairs by key (stable): keys int64
+    [arrays, key_words, n] holding the uint64 words (word 0 most
+    significant), ids int32 [arrays, n]."""
+    if keys.dim() != 3 or ids.dim() != 2 or keys.dtype != torch.int64 or ids.dtype != torch.int32:
+        raise ValueError("keys int64 [arrays, key_words, n], ids int32 [arrays, n]")
+    arrays, words, n = keys.shape
+    if tuple(ids.shape) != (arrays, n) or not keys.is_contiguous() or not ids.is_contiguous():
+        raise ValueError("ids must be [arrays, n]; both contiguous")
+    _check(_L.sfc_sort_pairs(_ptr(keys), _ptr(ids), n, words, arrays, _stream()))
 
 
 def extract_targets(volume: torch.Tensor, mask: torch.Tensor, K: int, centres: torch.Tensor):

@@ -61,3 +61,22 @@ def test_batch_argument_errors():
     assert lib.sfc_batch_create(1, arr, arr, geo, 4, None, ctypes.byref(out)) == -5
     assert b"K must be" in lib.sfc_last_error()
     assert lib.sfc_batch_query(None, None, None, None, None, None) == -1
+
+
+def test_sort_pairs_argument_errors():
+    lib = ctypes.CDLL(LIB)
+    f = lib.sfc_sort_pairs
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                  ctypes.c_int32, ctypes.c_void_p]
+    p = ctypes.c_void_p(16)   # never dereferenced: every case fails validation
+    assert f(None, p, 10, 1, 1, None) == -1
+    assert f(p, None, 10, 1, 1, None) == -1
+    assert f(p, p, -1, 1, 1, None) == -1
+    assert f(p, p, 10, 0, 1, None) == -1
+    assert f(p, p, 10, 5, 1, None) == -1
+    assert f(p, p, 10, 1, 0, None) == -1
+    assert f(p, p, 1 << 32, 1, 1, None) == -5
+    # n <= 1 is a no-op that touches nothing
+    assert f(p, p, 1, 3, 2, None) == 0
+    assert f(p, p, 0, 3, 2, None) == 0
