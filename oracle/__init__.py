@@ -55,7 +55,7 @@ class OrcIndex(C.Structure):
         ("b", C.c_int), ("curve", C.c_int), ("window", C.c_int),
         ("n", C.c_int64), ("dict", P), ("vmin", C.c_float), ("qscale", C.c_float),
         ("npix", P), ("pix", P), ("basis", P), ("basis_off", P), ("lo", P), ("span", P),
-        ("sum", P), ("nsub", C.c_int64), ("keys", P), ("ids", P),
+        ("sum", P), ("nsub", C.c_int64), ("keys", P), ("ids", P), ("norm", C.c_int),
     ]
 
 
@@ -66,7 +66,9 @@ def _declare(L):
         "orc_dictionary": (I64, [P, I32, P, I32, P, I64]),
         "orc_cost_one": (C.c_float, [P, I32, P, I32, I32, I64, P, P]),
         "orc_cost64_one": (C.c_double, [P, I32, P, I32, I32, I64, P, P]),
-        "orc_brute": (None, [P, I32, P, I32, I32, P, I64, P, P, I64, P, P]),
+        "orc_cost_l1_one": (C.c_float, [P, I32, P, I32, I32, I64, P, P]),
+        "orc_cost64_l1_one": (C.c_double, [P, I32, P, I32, I32, I64, P, P]),
+        "orc_brute": (None, [P, I32, P, I32, I32, P, I64, P, P, I64, P, P, I32]),
         "orc_quantize": (I32, [P, P, I64, I32, P, P, P]),
         "orc_subsets": (I32, [I32, I32, P, P]),
         "orc_cov_sums": (I64, [P, I32, P, I32, I32, P, I64, P, P]),
@@ -131,21 +133,28 @@ def dictionary(mask, K):
     return out[:n].copy()
 
 
-def cost(volume, shape, K, centre, t, m):
+NORMS = {"l2": 0, "l1": 1}
+
+
+def cost(volume, shape, K, centre, t, m, norm="l2"):
+    """The float32 cost that ranks candidates: masked L2 (Section II) or the
+    L1 variant of Section III.K."""
     volume = _c(volume, np.float32)
     t, m = _c(t, np.float32), _c(m, np.uint8)
-    return float(lib().orc_cost_one(_p(volume), len(shape), _p(_shape(shape)),
-                                    volume.shape[-1], K, int(centre), _p(t), _p(m)))
+    f = lib().orc_cost_l1_one if NORMS[norm] else lib().orc_cost_one
+    return float(f(_p(volume), len(shape), _p(_shape(shape)), volume.shape[-1], K, int(centre),
+                   _p(t), _p(m)))
 
 
-def cost64(volume, shape, K, centre, t, m):
+def cost64(volume, shape, K, centre, t, m, norm="l2"):
     volume = _c(volume, np.float32)
     t, m = _c(t, np.float32), _c(m, np.uint8)
-    return float(lib().orc_cost64_one(_p(volume), len(shape), _p(_shape(shape)),
-                                      volume.shape[-1], K, int(centre), _p(t), _p(m)))
+    f = lib().orc_cost64_l1_one if NORMS[norm] else lib().orc_cost64_one
+    return float(f(_p(volume), len(shape), _p(_shape(shape)), volume.shape[-1], K, int(centre),
+                   _p(t), _p(m)))
 
 
-def brute(volume, shape, K, dict_ids, t, m):
+def brute(volume, shape, K, dict_ids, t, m, norm="l2"):
     volume = _c(volume, np.float32)
     dict_ids = _c(dict_ids, np.int64)
     t, m = _c(t, np.float32), _c(m, np.uint8)
@@ -153,7 +162,7 @@ def brute(volume, shape, K, dict_ids, t, m):
     bi = np.empty(Q, dtype=np.int64)
     bc = np.empty(Q, dtype=np.float32)
     lib().orc_brute(_p(volume), len(shape), _p(_shape(shape)), volume.shape[-1], K,
-                    _p(dict_ids), dict_ids.size, _p(t), _p(m), Q, _p(bi), _p(bc))
+                    _p(dict_ids), dict_ids.size, _p(t), _p(m), Q, _p(bi), _p(bc), NORMS[norm])
     return bi, bc
 
 
@@ -277,13 +286,14 @@ class Index:
     curves, sort by curve position (Sections II, II.A-C)."""
 
     def __init__(self, volume, mask, K, D, L, key_bits=8, curve="morton", window=32,
-                 bases=None, keep_y=False):
+                 bases=None, keep_y=False, norm="l2"):
         self.volume = _c(volume, np.float32)
         self.mask = _c(mask, np.uint8)
         self.shape = tuple(self.mask.shape)
         self.nd = len(self.shape)
         self.C = self.volume.shape[-1]
         self.K, self.D, self.L, self.b, self.window = K, D, L, key_bits, window
+        self.norm = NORMS[norm]   # the rescoring cost (the index itself is norm-free)
         self.curve = CURVES[curve] if isinstance(curve, str) else int(curve)
         self.xq, self.vmin, self.qscale = quantize(self.volume, self.mask)
         self.dict = dictionary(self.mask, K)
@@ -345,6 +355,7 @@ class Index:
             st.lo, st.span = _p(self._lo), _p(self._span)
             st.sum, st.nsub = _p(self.sum), self.nsub
             st.keys, st.ids = _p(self.keys), _p(self.ids)
+            st.norm = self.norm
             self._struct = st
         return self._struct
 

@@ -1,7 +1,8 @@
 /*
  * oracle.c -- CPU oracle for the masked-L2 patch search of exemplar-based
  * inpainting (Dahmen et al., "Space-Filling Curve Indices as Acceleration
- * Structure for Exemplar-Based Inpainting").
+ * Structure for Exemplar-Based Inpainting"), and its L1 variant
+ * (Section III.K).
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the product path may call, link or
  * load this file; only the test suite, the smoke check and the benchmark's
@@ -187,6 +188,33 @@ float orc_cost(const float *vol, const grid_t *g, int C, int K, int64_t centre,
     return acc;
 }
 
+/* Masked L1 cost, the distance of Section III.K's variant: the same known
+ * elements in the same order as the L2 cost, |d| with d = t - V added in
+ * float32 (round to nearest) to an accumulator starting at +0. */
+float orc_cost_l1(const float *vol, const grid_t *g, int C, int K, int64_t centre,
+                  const float *t, const uint8_t *m)
+{
+    int64_t Kd = ipow(K, g->nd), cc[ORC_MAXD];
+    coords_of(g, centre, cc);
+    float acc = 0.0f;
+    for (int64_t rho = 0; rho < Kd; rho++) {
+        if (!m[rho]) continue;
+        int64_t v = voxel_at(g, cc, K, rho);
+        for (int ch = 0; ch < C; ch++) {
+            float d = t[rho * C + ch] - vol[v * C + ch];
+            acc = acc + fabsf(d);
+        }
+    }
+    return acc;
+}
+
+/* The cost that ranks candidates under norm 0 (L2) or 1 (L1). */
+static float cost_of(int norm, const float *vol, const grid_t *g, int C, int K, int64_t centre,
+                     const float *t, const uint8_t *m)
+{
+    return norm ? orc_cost_l1(vol, g, C, K, centre, t, m) : orc_cost(vol, g, C, K, centre, t, m);
+}
+
 /* The same cost in float64 (no fused operations), for error checks. */
 double orc_cost64_one(const float *vol, int nd, const int64_t *shape, int C, int K,
                       int64_t centre, const float *t, const uint8_t *m)
@@ -213,12 +241,37 @@ float orc_cost_one(const float *vol, int nd, const int64_t *shape, int C, int K,
     return orc_cost(vol, &g, C, K, centre, t, m);
 }
 
+float orc_cost_l1_one(const float *vol, int nd, const int64_t *shape, int C, int K,
+                      int64_t centre, const float *t, const uint8_t *m)
+{
+    grid_t g = make_grid(nd, shape);
+    return orc_cost_l1(vol, &g, C, K, centre, t, m);
+}
+
+/* The L1 cost in float64, for error checks. */
+double orc_cost64_l1_one(const float *vol, int nd, const int64_t *shape, int C, int K,
+                         int64_t centre, const float *t, const uint8_t *m)
+{
+    grid_t g = make_grid(nd, shape);
+    int64_t Kd = ipow(K, nd), cc[ORC_MAXD];
+    coords_of(&g, centre, cc);
+    double acc = 0.0;
+    for (int64_t rho = 0; rho < Kd; rho++) {
+        if (!m[rho]) continue;
+        int64_t v = voxel_at(&g, cc, K, rho);
+        for (int ch = 0; ch < C; ch++)
+            acc += fabs((double)t[rho * C + ch] - (double)vol[v * C + ch]);
+    }
+    return acc;
+}
+
 /* Full scan (Section I: evaluate the cost for every dictionary patch and take
- * the global minimum). Ties go to the lowest id, because dict is ascending and
- * only a strictly smaller cost replaces the current best. */
+ * the global minimum), under norm 0 (L2) or 1 (L1). Ties go to the lowest id,
+ * because dict is ascending and only a strictly smaller cost replaces the
+ * current best. */
 void orc_brute(const float *vol, int nd, const int64_t *shape, int C, int K,
                const int64_t *dict, int64_t n, const float *t, const uint8_t *m,
-               int64_t Q, int64_t *best_id, float *best_cost)
+               int64_t Q, int64_t *best_id, float *best_cost, int norm)
 {
     grid_t g = make_grid(nd, shape);
     int64_t Kd = ipow(K, nd);
@@ -228,7 +281,7 @@ void orc_brute(const float *vol, int nd, const int64_t *shape, int C, int K,
         int64_t bi = -1;
         float bc = INFINITY;
         for (int64_t i = 0; i < n; i++) {
-            float c = orc_cost(vol, &g, C, K, dict[i], tq, mq);
+            float c = cost_of(norm, vol, &g, C, K, dict[i], tq, mq);
             if (bi < 0 || c < bc) {
                 bc = c;
                 bi = dict[i];
@@ -736,6 +789,7 @@ typedef struct {
     int64_t nsub;
     const uint64_t *keys;         /* [S][L][n][W64] */
     const int64_t *ids;           /* [S][L][n] */
+    int norm;                     /* cost of the rescoring: 0 L2, 1 L1 */
 } orc_index;
 
 static int key_cmp(const uint64_t *a, const uint64_t *b, int W64)
@@ -912,7 +966,7 @@ int64_t orc_query_one(const orc_index *ix, const float *vol, const float *t,
     int64_t bi = -1;
     float bc = INFINITY;
     for (int64_t i = 0; i < u; i++) {
-        float c = orc_cost(vol, &g, ix->C, ix->K, cand[i], t, m);
+        float c = cost_of(ix->norm, vol, &g, ix->C, ix->K, cand[i], t, m);
         if (bi < 0 || c < bc) { bc = c; bi = cand[i]; }
     }
     *best_id = bi;
@@ -1048,7 +1102,7 @@ int64_t orc_inpaint(float *vol, uint8_t *mask, int nd, const int64_t *shape, int
         if (mode == 3 && ix) {
             orc_query_one(ix, vol, t, m, &src, &cost, cand, 0);
         } else {
-            orc_brute(vol, nd, shape, C, K, dict, n, t, m, 1, &src, &cost);
+            orc_brute(vol, nd, shape, C, K, dict, n, t, m, 1, &src, &cost, 0);
         }
         int64_t sc[ORC_MAXD];
         coords_of(&g, best, cc);

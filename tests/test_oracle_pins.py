@@ -141,6 +141,94 @@ def test_cost_float32_vs_float64_and_numpy_bruteforce(orc):
         assert abs(float(bc[q]) - e) <= 1e-5 * max(e, 1e-30) or (bc[q] == 0 and e == 0)
 
 
+# ------------------------------------------------------------------ L1 cost (Section III.K)
+def test_l1_verbatim_copy_costs_zero_and_is_found(orc):
+    vol, mask = _img(c=3, seed=11)
+    K = 5
+    d = orc.dictionary(mask, K)
+    cen = d[[3, 50, 200, len(d) - 1]]
+    t, m = orc.extract(vol, mask, K, cen)
+    bi, bc = orc.brute(vol, mask.shape, K, d, t, m, norm="l1")
+    assert np.all(bc == 0.0)
+    for q, c in enumerate(cen):
+        assert bi[q] <= c
+        t2, _ = orc.extract(vol, mask, K, [bi[q]])
+        assert np.array_equal(t2[0], t[q])
+
+
+def test_l1_one_known_pixel_is_nearest_value(orc):
+    vol, mask = _img(seed=5)
+    K = 5
+    d = orc.dictionary(mask, K)
+    t = np.zeros((1, K * K, 1), np.float32)
+    m = np.zeros((1, K * K), np.uint8)
+    m[0, 7] = 1
+    t[0, 7, 0] = np.float32(0.4321)
+    bi, bc = orc.brute(vol, mask.shape, K, d, t, m, norm="l1")
+    W = mask.shape[1]
+    ad = np.abs((np.float32(0.4321) - vol.reshape(-1)[d - W]).astype(np.float32))
+    k = int(np.argmin(ad))
+    assert bi[0] == d[k] and bc[0] == ad[k]
+
+
+def test_l1_and_l2_choose_different_patches(orc):
+    # middle row known, target 0: candidate centre (1, 2) reads (1, 1, 1),
+    # L1 = 3, L2 = 3; centre (1, 6) reads (0, 2.5, 0), L1 = 2.5, L2 = 6.25;
+    # every other candidate meets a 10
+    vol = np.zeros((3, 9, 1), np.float32)
+    vol[1, :, 0] = [10, 1, 1, 1, 10, 0, 2.5, 0, 10]
+    mask = np.ones((3, 9), np.uint8)
+    K = 3
+    d = orc.dictionary(mask, K)
+    assert np.array_equal(d, 9 + np.arange(1, 8))
+    t = np.zeros((1, 9, 1), np.float32)
+    m = np.zeros((1, 9), np.uint8)
+    m[0, 3:6] = 1
+    b2, c2 = orc.brute(vol, mask.shape, K, d, t, m, norm="l2")
+    b1, c1 = orc.brute(vol, mask.shape, K, d, t, m, norm="l1")
+    assert (b2[0], c2[0]) == (11, 3.0)
+    assert (b1[0], c1[0]) == (15, 2.5)
+    assert orc.cost(vol, mask.shape, K, 15, t[0], m[0], norm="l2") == 6.25
+    assert orc.cost(vol, mask.shape, K, 11, t[0], m[0], norm="l1") == 3.0
+
+
+def test_l1_float32_vs_float64_and_numpy_bruteforce(orc):
+    vol, mask = _img(h=36, w=30, c=3, seed=9)
+    K = 5
+    d = orc.dictionary(mask, K)
+    f = orc.front(mask)[::7]
+    t, m = orc.extract(vol, mask, K, f)
+    bi, bc = orc.brute(vol, mask.shape, K, d, t, m, norm="l1")
+    W = mask.shape[1]
+    off = (np.arange(K * K) // K - 2) * W + (np.arange(K * K) % K - 2)
+    V = vol.reshape(-1, 3).astype(np.float64)
+    u = 2.0 ** -24
+    for q in range(len(f)):
+        patches = V[d[:, None] + off[None, :]]
+        c64 = (np.abs(t[q].astype(np.float64)[None] - patches) * m[q][None, :, None]).sum(axis=(1, 2))
+        k_terms = int(m[q].sum()) * 3
+        tol = (k_terms + 1) * u   # k rounded differences and k - 1 rounded additions
+        k = int(np.argmin(c64))
+        gap = np.sort(c64)[1] - c64.min()
+        if gap > 2 * tol * max(c64.min(), 1e-30):
+            assert bi[q] == d[k]
+        e = orc.cost64(vol, mask.shape, K, bi[q], t[q], m[q], norm="l1")
+        assert abs(float(bc[q]) - e) <= tol * e or (bc[q] == 0 and e == 0)
+
+
+def test_l1_index_equals_bruteforce_when_windows_cover_all(orc):
+    vol, mask = _img(h=18, w=17, c=2, seed=12, frac=0.08, holes=1)
+    K = 5
+    ix = orc.Index(vol, mask, K, D=4, L=2, key_bits=6, window=256, norm="l1")
+    assert ix.n <= 256
+    f = orc.front(mask)
+    t, m = orc.extract(vol, mask, K, f)
+    bi, bc, _, nc, _ = ix.query(vol, t, m)
+    b2, c2 = orc.brute(vol, mask.shape, K, ix.dict, t, m, norm="l1")
+    assert np.array_equal(bi, b2) and np.array_equal(bc, c2)
+    assert np.all(nc == ix.n)
+
+
 # ------------------------------------------------------------------ quantisation
 def test_quantize_hand_cases(orc):
     vol = np.array([[0.0, 1.0], [2.0, 0.5], [255.0 / 510.0 * 2.0, 9.0]], np.float32)[..., None]
