@@ -61,6 +61,11 @@ typedef enum {
 
 typedef enum { SFC_ORDER_CRIMINISI = 0, SFC_ORDER_RASTER = 1 } sfc_order;
 
+/* The patch distance that ranks candidates: the masked squared L2 sum of
+ * Section II, or the masked L1 sum of Section III.K's variant (the same
+ * known elements in the same order, |t - v| added in float32). */
+typedef enum { SFC_NORM_L2 = 0, SFC_NORM_L1 = 1 } sfc_norm;
+
 typedef struct {
     int32_t ndim;       /* 2 or 3 */
     int32_t channels;   /* C >= 1 */
@@ -83,6 +88,11 @@ typedef struct {
     int32_t timing;        /* 1: record HIP events around the main kernels of
                               each sfc_query call (sfc_query_kernel_times);
                               default 0 */
+    int32_t norm;          /* sfc_norm of the float32 scan and the index's
+                              rescoring, default SFC_NORM_L2. With SFC_NORM_L1
+                              the reduced-precision modes, batches, the fill
+                              loop and sfc_autotune return SFC_EUNSUPPORTED, and
+                              the float32 scan uses its default tile shape. */
 } sfc_options;
 
 typedef struct sfc_index sfc_index;  /* opaque */
@@ -197,8 +207,10 @@ sfc_status sfc_autotune(sfc_index *idx, const float *targets, const uint8_t *tar
 typedef struct {
     int32_t window;        /* W */
     float recall;          /* fraction of targets whose index answer is the full scan's */
-    float accel_error;     /* mean sqrt(cost_index) / sqrt(cost_scan) - 1 over targets with
-                              a nonzero scan cost (Section III.C's acceleration error) */
+    float accel_error;     /* mean distance ratio index / scan - 1 over targets with a
+                              nonzero scan cost (Section III.C's acceleration error):
+                              sqrt(cost_index / cost_scan) - 1 for L2, cost_index /
+                              cost_scan - 1 for L1 */
     float ms;              /* index query time on these targets (HIP events) */
 } sfc_window_trial;
 

@@ -148,6 +148,7 @@ sfc_status validate_options(const sfc_options& o) {
         return fail(SFC_EINVAL, "unknown curve");
     if (o.rescore_top < 1 || o.rescore_top > 64) return fail(SFC_EINVAL, "rescore_top must be 1..64");
     if (o.query_block < 0) return fail(SFC_EINVAL, "query_block must be >= 0");
+    if (o.norm != SFC_NORM_L2 && o.norm != SFC_NORM_L1) return fail(SFC_EINVAL, "unknown norm");
     return SFC_OK;
 }
 
@@ -234,7 +235,7 @@ sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int
     SFC_TRY(launch_fill_u64(best_dev, Q, ~0ull, ix->st));
     ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best_dev, ix->opt.query_block,
                ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant,
-               ix->spans, ix->n_spans};
+               ix->spans, ix->n_spans, ix->opt.norm};
     SFC_TRY(ix->timer.begin("scan_fp32_kernel", ix->st));
     SFC_TRY(launch_scan_fp32(g, a, ix->st));
     return ix->timer.end(ix->st);
@@ -455,6 +456,8 @@ sfc_status sfc_autotune(sfc_index* ix, const float* targets, const uint8_t* targ
     clear_error();
     if (!ix || !targets || !target_masks || !chosen) return fail(SFC_EINVAL, "null pointer");
     if (Q < 1) return fail(SFC_EINVAL, "autotuning needs Q >= 1");
+    if (ix->opt.norm != SFC_NORM_L2)
+        return fail(SFC_EUNSUPPORTED, "autotuning: the L1 scan has one tile shape");
     const Grid& g = ix->g;
     const int nv = scan_variants(g.nd, g.K, g.C);
     if (nv == 0) return fail(SFC_EUNSUPPORTED, "no float32 scan for this shape");
@@ -575,7 +578,11 @@ sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_
         for (int64_t q = 0; q < Q; q++) {
             hits += got_id[q] == ref_id[q];
             if (ref_cost[q] > 0.0f) {
-                ae += std::sqrt((double)got_cost[q]) / std::sqrt((double)ref_cost[q]) - 1.0;
+                // the ratio of the patch distances: the L2 cost is a squared norm
+                ae += (ix->opt.norm == SFC_NORM_L1
+                           ? (double)got_cost[q] / (double)ref_cost[q]
+                           : std::sqrt((double)got_cost[q]) / std::sqrt((double)ref_cost[q])) -
+                      1.0;
                 nz++;
             }
         }

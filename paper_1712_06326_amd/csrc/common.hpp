@@ -87,6 +87,7 @@ struct ScanArgs {
     int variant;               // scan shape variant (0 = default)
     const uint32_t* spans;     // dictionary spans (null: whole lines)
     int64_t n_spans;
+    int norm;                  // 0: L2 cost, 1: L1 cost (default tile shape)
 };
 sfc_status launch_pack_rowmask(const uint8_t* m, const Grid& g, int64_t Q, uint32_t* rowmask,
                                hipStream_t st);

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int
 // ------------------------------------------------------------ rescore
 constexpr int kCap = 512;   // maximum L*W
 
-template <int ND, int K, int C>
+template <int ND, int K, int C, int NORM>
 __device__ inline float cand_cost(const QueryIndexView& v, const float* __restrict__ vol,
                                   const float* __restrict__ tq, const uint32_t* __restrict__ rm,
                                   int64_t qpad, uint32_t c) {
@@ -227,7 +227,9 @@ __device__ inline float cand_cost(const QueryIndexView& v, const float* __restri
 #pragma unroll
                 for (int ch = 0; ch < C; ch++) {
                     const float d = ldu(tp + dx * C + ch) - vv[dx * C + ch];
-                    acc = __builtin_fmaf(d, d, acc);
+                    // d*d fused (L2) or |d| added (L1, Section III.K)
+                    if (NORM == 0) acc = __builtin_fmaf(d, d, acc);
+                    else acc = acc + __builtin_fabsf(d);
                 }
             }
         }
@@ -237,7 +239,7 @@ __device__ inline float cand_cost(const QueryIndexView& v, const float* __restri
 
 // One wave per query: gather the window ids, sort them in LDS (bitonic),
 // keep the unique ones, then each lane rescores every 64th candidate.
-template <int ND, int K, int C>
+template <int ND, int K, int C, int NORM>
 __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const float* __restrict__ vol,
                                                       const float* __restrict__ t,
                                                       const uint32_t* __restrict__ rowmask,
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
     uint64_t best = ~0ull;
     for (int i = lane; i < nu; i += 64) {
         const uint32_t c = Bu[i];
-        const float cost = cand_cost<ND, K, C>(v, vol, tq, rm, qpad, c);
+        const float cost = cand_cost<ND, K, C, NORM>(v, vol, tq, rm, qpad, c);
         const uint64_t pk = ((uint64_t)__float_as_uint(cost) << 32) | c;
         if (pk < best) best = pk;
     }
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(256) void list_rescore_kernel(QueryIndexView v, con
     uint64_t best = ~0ull;
     for (int i = lane; i < nc; i += 64) {
         const uint32_t c = list[q * cap + i];
-        const float cost = cand_cost<ND, K, C>(v, vol, tq, rm, qpad, c);
+        const float cost = cand_cost<ND, K, C, 0>(v, vol, tq, rm, qpad, c);
         const uint64_t pk = ((uint64_t)__float_as_uint(cost) << 32) | c;
         if (pk < best) best = pk;
     }
@@ -369,10 +371,11 @@ using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32
 
 struct RescoreEntry {
     int nd, K, C;
-    RescoreFn fn;
+    RescoreFn fn, fn_l1;
     ListFn lfn;
 };
-#define SFC_RESCORE(ND, K, C) {ND, K, C, rescore_kernel<ND, K, C>, list_rescore_kernel<ND, K, C>}
+#define SFC_RESCORE(ND, K, C)                                                                 \
+    {ND, K, C, rescore_kernel<ND, K, C, 0>, rescore_kernel<ND, K, C, 1>, list_rescore_kernel<ND, K, C>}
 const RescoreEntry kRescore[] = {
     SFC_RESCORE(2, 3, 1), SFC_RESCORE(2, 3, 2), SFC_RESCORE(2, 3, 3),
     SFC_RESCORE(2, 5, 1), SFC_RESCORE(2, 5, 2), SFC_RESCORE(2, 5, 3),
@@ -452,7 +455,8 @@ bool rescore_supported(int nd, int K, int C) {
 sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const float* t,
                                 const uint32_t* rowmask, int64_t qpad, const int32_t* qsub,
                                 const int64_t* wstart, int64_t Q, int64_t* best_id,
-                                float* best_cost, int64_t* cand, int32_t* ncand, hipStream_t st) {
+                                float* best_cost, int64_t* cand, int32_t* ncand, int norm,
+                                hipStream_t st) {
     if (Q == 0) return SFC_OK;
     const RescoreEntry* ent = nullptr;
     for (const auto& e : kRescore)
@@ -461,8 +465,9 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
     int cap = 64;
     while (cap < v.L * v.window) cap <<= 1;
     if (cap > kCap) return fail(SFC_EUNSUPPORTED, "n_curves * window above 512");
-    hipLaunchKernelGGL(ent->fn, dim3(blocks_for(Q, 4)), dim3(256), 0, st, v, vol, t, rowmask, qpad,
-                       qsub, wstart, Q, cap, best_id, best_cost, cand, ncand);
+    hipLaunchKernelGGL(norm == 1 ? ent->fn_l1 : ent->fn, dim3(blocks_for(Q, 4)), dim3(256), 0, st,
+                       v, vol, t, rowmask, qpad, qsub, wstart, Q, cap, best_id, best_cost, cand,
+                       ncand);
     return launched("rescore_kernel");
 }
 

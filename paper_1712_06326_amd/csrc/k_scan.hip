@@ -49,7 +49,15 @@ __device__ inline uint32_t ldu(const uint32_t* p) { return *(cu32_as4*)p; }
 // global atomic per query.
 // Queries [q0, q1) against line tiles [tl0, tl1) of one image; the whole
 // workgroup calls it (it synchronises). sred: LDS [4][QB].
-template <int ND, int K, int C, int QB, int NX>
+// One known element's term: d*d fused into the sum (L2, Section II) or |d|
+// added to it (L1, Section III.K), in the definition's order either way.
+template <int NORM>
+__device__ __forceinline__ float accum(float acc, float d) {
+    if constexpr (NORM == 0) return __builtin_fmaf(d, d, acc);
+    else return acc + __builtin_fabsf(d);
+}
+
+template <int ND, int K, int C, int QB, int NX, int NORM = 0>
 __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int64_t q1, int64_t tl0,
                                            int64_t tl1, uint64_t* sred) {
     constexpr int H = (K - 1) / 2;
@@ -156,7 +164,7 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
 #pragma unroll
                             for (int j = 0; j < NX; j++) {
                                 const float d = tc[i] - v[j * C + i];
-                                acc[qi][j] = __builtin_fmaf(d, d, acc[qi][j]);
+                                acc[qi][j] = accum<NORM>(acc[qi][j], d);
                             }
                     } else if (mr != 0) {
 #pragma unroll
@@ -167,7 +175,7 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
 #pragma unroll
                                     for (int ch = 0; ch < C; ch++) {
                                         const float d = tc[dx * C + ch] - v[(j + dx) * C + ch];
-                                        acc[qi][j] = __builtin_fmaf(d, d, acc[qi][j]);
+                                        acc[qi][j] = accum<NORM>(acc[qi][j], d);
                                     }
                             }
                         }
@@ -218,7 +226,7 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
     }
 }
 
-template <int ND, int K, int C, int QB, int NX>
+template <int ND, int K, int C, int QB, int NX, int NORM>
 __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     __shared__ uint64_t sred[(kLanes / 64) * QB];
     // XCD-aware mapping: workgroups are dispatched to the 8 XCDs round-robin,
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     if (q0 >= q1) return;
     const int64_t tl0 = chunk * p.tiles_per_wg;
     const int64_t tl1 = min(p.n_tiles, tl0 + p.tiles_per_wg);
-    scan_range<ND, K, C, QB, NX>(p, q0, q1, tl0, tl1, sred);
+    scan_range<ND, K, C, QB, NX, NORM>(p, q0, q1, tl0, tl1, sred);
 }
 
 // ---- batches of 2D images
@@ -359,26 +367,30 @@ struct ScanEntry {
     int nd, K, C;
     int qb, nx;
     ScanFn fn;
+    ScanFn fn_l1;   // the L1 cost with this shape (default shapes only)
 };
 
 // (QB queries per pass, NX candidates per lane) shapes per (ndim, K, C); the
 // first entry of a shape is its default, the others are candidates for the
 // autotuner.
-#define SFC_SCAN(ND, K, C, QB, NX) {ND, K, C, QB, NX, scan_fp32_kernel<ND, K, C, QB, NX>}
+#define SFC_SCAN(ND, K, C, QB, NX) {ND, K, C, QB, NX, scan_fp32_kernel<ND, K, C, QB, NX, 0>, nullptr}
+// a default shape: also instantiated for the L1 cost
+#define SFC_SCAN1(ND, K, C, QB, NX)                                                           \
+    {ND, K, C, QB, NX, scan_fp32_kernel<ND, K, C, QB, NX, 0>, scan_fp32_kernel<ND, K, C, QB, NX, 1>}
 const ScanEntry kScanTable[] = {
-    SFC_SCAN(2, 3, 1, 16, 8), SFC_SCAN(2, 3, 2, 16, 8), SFC_SCAN(2, 3, 3, 16, 8),
-    SFC_SCAN(2, 5, 1, 16, 8), SFC_SCAN(2, 5, 2, 16, 4), SFC_SCAN(2, 5, 3, 16, 4),
-    SFC_SCAN(2, 7, 1, 16, 8), SFC_SCAN(2, 7, 2, 16, 4), SFC_SCAN(2, 7, 3, 16, 4),
-    SFC_SCAN(2, 9, 1, 16, 8), SFC_SCAN(2, 9, 1, 16, 4), SFC_SCAN(2, 9, 1, 8, 8),
-    SFC_SCAN(2, 9, 2, 16, 4),
-    SFC_SCAN(2, 9, 3, 16, 4), SFC_SCAN(2, 9, 3, 8, 4), SFC_SCAN(2, 9, 3, 16, 2),
+    SFC_SCAN1(2, 3, 1, 16, 8), SFC_SCAN1(2, 3, 2, 16, 8), SFC_SCAN1(2, 3, 3, 16, 8),
+    SFC_SCAN1(2, 5, 1, 16, 8), SFC_SCAN1(2, 5, 2, 16, 4), SFC_SCAN1(2, 5, 3, 16, 4),
+    SFC_SCAN1(2, 7, 1, 16, 8), SFC_SCAN1(2, 7, 2, 16, 4), SFC_SCAN1(2, 7, 3, 16, 4),
+    SFC_SCAN1(2, 9, 1, 16, 8), SFC_SCAN(2, 9, 1, 16, 4), SFC_SCAN(2, 9, 1, 8, 8),
+    SFC_SCAN1(2, 9, 2, 16, 4),
+    SFC_SCAN(2, 9, 3, 16, 4), SFC_SCAN1(2, 9, 3, 8, 4), SFC_SCAN(2, 9, 3, 16, 2),
     SFC_SCAN(2, 9, 3, 8, 8), SFC_SCAN(2, 9, 3, 12, 4),
-    SFC_SCAN(2, 11, 1, 16, 4), SFC_SCAN(2, 11, 3, 16, 2),
-    SFC_SCAN(2, 13, 1, 16, 4), SFC_SCAN(2, 13, 3, 8, 2),
-    SFC_SCAN(3, 3, 1, 16, 8), SFC_SCAN(3, 3, 2, 16, 8),
-    SFC_SCAN(3, 5, 1, 16, 8), SFC_SCAN(3, 5, 1, 16, 4), SFC_SCAN(3, 5, 1, 8, 8),
-    SFC_SCAN(3, 5, 2, 16, 4),
-    SFC_SCAN(3, 7, 1, 16, 4), SFC_SCAN(3, 7, 1, 16, 8), SFC_SCAN(3, 7, 1, 8, 8),
+    SFC_SCAN1(2, 11, 1, 16, 4), SFC_SCAN1(2, 11, 3, 16, 2),
+    SFC_SCAN1(2, 13, 1, 16, 4), SFC_SCAN1(2, 13, 3, 8, 2),
+    SFC_SCAN1(3, 3, 1, 16, 8), SFC_SCAN1(3, 3, 2, 16, 8),
+    SFC_SCAN(3, 5, 1, 16, 8), SFC_SCAN(3, 5, 1, 16, 4), SFC_SCAN1(3, 5, 1, 8, 8),
+    SFC_SCAN1(3, 5, 2, 16, 4),
+    SFC_SCAN(3, 7, 1, 16, 4), SFC_SCAN(3, 7, 1, 16, 8), SFC_SCAN1(3, 7, 1, 8, 8),
 };
 
 // variant v (0 = default) of a shape, or null
@@ -389,6 +401,13 @@ const ScanEntry* scan_entry(int nd, int K, int C, int v) {
             if (k == v) return &e;
             k++;
         }
+    return nullptr;
+}
+
+// the shape of (nd, K, C) that has an L1 kernel, or null
+const ScanEntry* scan_entry_l1(int nd, int K, int C) {
+    for (const auto& e : kScanTable)
+        if (e.nd == nd && e.K == K && e.C == C && e.fn_l1) return &e;
     return nullptr;
 }
 
@@ -475,10 +494,16 @@ sfc_status launch_unpack_best(const uint64_t* best, int64_t Q, int64_t* id, floa
 
 sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     if (a.Q == 0) return SFC_OK;
-    const ScanEntry* ent = scan_entry(g.nd, g.K, g.C, a.variant);
-    if (!ent) ent = scan_entry(g.nd, g.K, g.C, 0);
+    const ScanEntry* ent;
+    if (a.norm == 1) {
+        ent = scan_entry_l1(g.nd, g.K, g.C);
+    } else {
+        ent = scan_entry(g.nd, g.K, g.C, a.variant);
+        if (!ent) ent = scan_entry(g.nd, g.K, g.C, 0);
+    }
     if (!ent)
         return fail(SFC_EUNSUPPORTED, "float32 scan: no kernel for this (ndim, K, channels)");
+    const ScanFn fn = a.norm == 1 ? ent->fn_l1 : ent->fn;
     ScanParams p{};
     p.vol = a.vol;
     p.valid = a.valid;
@@ -525,7 +550,7 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     p.q_splits = qsplit;
     const int64_t nblocks = kXcds * p.chunks_per_xcd * qsplit;
     if (nblocks > 0x7fffffffLL) return fail(SFC_EUNSUPPORTED, "float32 scan: grid too large");
-    hipLaunchKernelGGL(ent->fn, dim3((unsigned)nblocks), dim3(kLanes), 0, st, p);
+    hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(kLanes), 0, st, p);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SFC_OK : check_hip(e, "scan_fp32_kernel");
 }

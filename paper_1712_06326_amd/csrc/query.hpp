@@ -29,11 +29,12 @@ sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const 
 // window start per (query, curve): wstart [Q][L]
 sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub,
                                const uint64_t* qkeys, int64_t Q, int64_t* wstart, hipStream_t st);
-// candidates = union of windows (sorted unique); best (cost, id) over them.
-// best_id/best_cost or cand/ncand may be null.
+// candidates = union of windows (sorted unique); best (cost, id) over them
+// under norm 0 (L2) or 1 (L1). best_id/best_cost or cand/ncand may be null.
 sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const float* t,
                                 const uint32_t* rowmask, int64_t qpad, const int32_t* qsub,
                                 const int64_t* wstart, int64_t Q, int64_t* best_id,
-                                float* best_cost, int64_t* cand, int32_t* ncand, hipStream_t st);
+                                float* best_cost, int64_t* cand, int32_t* ncand, int norm,
+                                hipStream_t st);
 
 }  // namespace sfc

@@ -211,6 +211,7 @@ sfc_status sfc_batch_create(int32_t n_images, const float* const* volumes, const
         if (!volumes[i] || !masks[i]) return fail(SFC_EINVAL, "sfc_batch_create: null image");
     }
     const sfc_options o = resolve_options(opt);
+    if (o.norm != SFC_NORM_L2) return fail(SFC_EUNSUPPORTED, "batched scan: L2 cost only");
     sfc_batch* b = new sfc_batch();
     b->K = K;
     b->user = static_cast<hipStream_t>(o.stream);

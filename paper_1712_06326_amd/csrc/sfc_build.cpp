@@ -464,7 +464,7 @@ sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t 
     SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->timer.begin("rescore_kernel", st));
     SFC_TRY(launch_query_rescore(v, ix->vol, t, rm, qpad, qsub, wstart, Q, best_id, best_cost, cand,
-                                 ncand, st));
+                                 ncand, ix->opt.norm, st));
     return ix->timer.end(st);
 }
 

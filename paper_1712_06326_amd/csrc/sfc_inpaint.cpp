@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <vector>
 
 #include "index.hpp"
@@ -42,6 +43,9 @@ extern "C" sfc_status sfc_inpaint(float* volume, uint8_t* mask, const sfc_geomet
     if (mode < SFC_MODE_BRUTE_FP32 || mode > SFC_MODE_INDEX) return fail(SFC_EINVAL, "unknown mode");
     if (log && (log->cap < 0 || (log->cap > 0 && (!log->centre_host || !log->source_host || !log->cost_host))))
         return fail(SFC_EINVAL, "sfc_inpaint: bad log");
+    if ((opt && opt->struct_size > offsetof(sfc_options, norm) && opt->norm != SFC_NORM_L2) ||
+        (idx && idx->opt.norm != SFC_NORM_L2))
+        return fail(SFC_EUNSUPPORTED, "sfc_inpaint: the fill loop uses the L2 cost");
     sfc_index* ix = idx;
     sfc_index* owned = nullptr;
     if (!ix) {

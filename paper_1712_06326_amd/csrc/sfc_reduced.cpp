@@ -49,6 +49,8 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
     if (mode == SFC_MODE_BRUTE_FP8)
         return fail(SFC_EUNSUPPORTED,
                     "fp8 scan: e4m3 cannot hold byte codes exactly; use SFC_MODE_BRUTE_BF16");
+    if (ix->opt.norm != SFC_NORM_L2)
+        return fail(SFC_EUNSUPPORTED, "reduced-precision scan: the L1 cost is not a dot product");
     const Grid& g = ix->g;
     hipStream_t st = ix->st;
     if ((int64_t)g.Kd * g.C > 1024)

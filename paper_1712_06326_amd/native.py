@@ -36,7 +36,7 @@ class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("key_bits", C.c_int32), ("window", C.c_int32),
                 ("curve", C.c_int32), ("rescore_top", C.c_int32), ("certify", C.c_int32),
                 ("query_block", C.c_int32), ("scan_variant", C.c_int32), ("stream", C.c_void_p),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("norm", C.c_int32)]
 
 
 class WindowTrial(C.Structure):
@@ -148,8 +148,11 @@ def geometry(mask: torch.Tensor, channels: int) -> Geometry:
     return g
 
 
+NORMS = {"l2": 0, "l1": 1}
+
+
 def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
-            query_block=0, scan_variant=0, timing=False) -> Options:
+            query_block=0, scan_variant=0, timing=False, norm="l2") -> Options:
     o = Options()
     _L.sfc_options_default(C.byref(o))
     o.key_bits = key_bits
@@ -161,6 +164,7 @@ def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
     o.scan_variant = scan_variant
     o.stream = _stream()
     o.timing = 1 if timing else 0
+    o.norm = NORMS[norm] if isinstance(norm, str) else int(norm)
     return o
 
 
