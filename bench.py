@@ -299,6 +299,20 @@ def main():
         "roofline": roofs[dom],
     }
 
+    # the L1 cost variant (Section III.K): the float32 scan of the same
+    # targets under L1 (second run timed; 2 flops per known element and
+    # candidate), outside the timed steps
+    ixl = native.Index(w.vol, w.mask, K, norm="l1", timing=True)
+    for _ in range(2):
+        bl, cl = ixl.query(res["t"], res["m"], "fp32")
+    torch.cuda.synchronize()
+    kl = ixl.kernel_times()["scan_fp32_kernel"]
+    ixl.close()
+    l1_ms = kl[1] / kl[0]
+    forms["l1_fp32_scan_qps"] = round(Qs / (l1_ms * 1e-3), 1)
+    forms["l1_fp32_scan_tflops"] = round(2.0 * known_elems * n / (l1_ms * 1e-3) / 1e12, 2)
+    log(f"L1 float32 scan: {l1_ms:.2f} ms for {Qs} queries")
+
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
@@ -323,6 +337,12 @@ def main():
                       f"float32 full scan (n={n}), single thread, {cpu_s:.1f}s; index build "
                       f"and index queries excluded (under 0.1% of the oracle's per-query time)"}
         forms["fp32_vs_oracle_agreement_pct"] = round(100 * agree, 2)
+        # the L1 scan's answers against the oracle's L1 scan on 4 of them
+        s4 = sel[:4]
+        ob1, oc1 = oracle.brute(w.vol_h, w.mask_h.shape, K, d_h, t_h[:4], m_h[s4], norm="l1")
+        bl_h, cl_h = bl.cpu().numpy()[s4], cl.cpu().numpy()[s4]
+        forms["l1_vs_oracle_agreement_pct"] = round(
+            100 * float(np.mean((ob1 == bl_h) & (oc1.view(np.uint32) == cl_h.view(np.uint32)))), 2)
 
     if args.workload == "config2" and not args.no_n1e8:
         del w, res
