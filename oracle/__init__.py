@@ -81,6 +81,8 @@ def _declare(L):
         "orc_keys": (None, [P, I64, I32, P, I64, I32, I32, I32, I32, P]),
         "orc_sort": (None, [P, P, I64, I32]),
         "orc_query": (None, [C.POINTER(OrcIndex), P, P, P, I64, P, P, P, P, P]),
+        "orc_knn": (I32, [C.POINTER(OrcIndex), P, P, P, I64, I32, P, P, P, P]),
+        "orc_morton_decode": (None, [P, I32, I32, P]),
         "orc_query_point": (I32, [C.POINTER(OrcIndex), P, P, P]),
         "orc_inpaint": (I64, [P, P, I32, P, I32, I32, I32, I32, P, I64,
                               C.POINTER(OrcIndex), I64, P, P, P]),
@@ -387,6 +389,32 @@ class Index:
         lib().orc_query(C.byref(self.struct()), _p(volume), _p(t), _p(m), Q, _p(bi), _p(bc),
                         _p(cand), _p(nc), _p(sub))
         return bi, bc, cand, nc, sub
+
+    def knn_query(self, volume, t, m, k=80):
+        """Exact k-NN query of Section II.D on the unshifted Morton curve.
+        Returns (best_id, best_cost, candidates [Q, k] ascending ids padded
+        -1, ncand [Q])."""
+        volume = _c(volume, np.float32)
+        t, m = _c(t, np.float32), _c(m, np.uint8)
+        Q = m.shape[0]
+        bi = np.empty(Q, dtype=np.int64)
+        bc = np.empty(Q, dtype=np.float32)
+        cand = np.empty((Q, k), dtype=np.int64)
+        nc = np.empty(Q, dtype=np.int32)
+        r = lib().orc_knn(C.byref(self.struct()), _p(volume), _p(t), _p(m), Q, k, _p(bi), _p(bc),
+                          _p(cand), _p(nc))
+        if r != 0:
+            raise ValueError("k-NN needs a Morton-ordered index and k >= 1")
+        return bi, bc, cand, nc
+
+
+def morton_decode(key_words, D, b):
+    """Coordinates [D] (uint32) of one Morton key (uint64 words, word 0 most
+    significant)."""
+    kw = _c(np.asarray(key_words, dtype=np.uint64), np.uint64)
+    v = np.empty(D, dtype=np.uint32)
+    lib().orc_morton_decode(_p(kw), D, b, _p(v))
+    return v
 
 
 def inpaint(volume, mask, K, order="criminisi", mode="brute", index: Index | None = None,

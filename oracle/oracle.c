@@ -991,6 +991,107 @@ void orc_query(const orc_index *ix, const float *vol, const float *t, const uint
 }
 
 /* ------------------------------------------------------------------ */
+/* Exact k-NN query (Sections II.D-E)                                   */
+/* ------------------------------------------------------------------ */
+
+/* Inverse of the Morton interleave: bit l*D + (D-1-d) of the key (word 0
+ * most significant) is bit l of coordinate d. */
+void orc_morton_decode(const uint64_t *key, int D, int b, uint32_t *v)
+{
+    int W64 = (D * b + 63) / 64;
+    for (int d = 0; d < D; d++) v[d] = 0;
+    for (int l = 0; l < b; l++)
+        for (int d = 0; d < D; d++) {
+            int pos = l * D + (D - 1 - d);
+            uint64_t bit = (key[W64 - 1 - pos / 64] >> (pos % 64)) & 1u;
+            v[d] |= (uint32_t)bit << l;
+        }
+}
+
+typedef struct { int64_t dist, id; } dist_id;
+
+static int cmp_dist_id(const void *a, const void *b)
+{
+    const dist_id *x = (const dist_id *)a, *y = (const dist_id *)b;
+    if (x->dist != y->dist) return x->dist < y->dist ? -1 : 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+/* The k-NN query of Section II.D on the unshifted Morton curve, written as
+ * what it computes: the query's subset and grid cell as in the windowed
+ * query (steps 1-3 and the cell of curve 0), every dictionary patch's cell
+ * on that curve (decoded from its key), the k patches of smallest squared
+ * Euclidean cell distance (ties by lower id), then the cost of Section II
+ * (or its L1 variant) over those k, lowest (cost, id). The recursive
+ * outside-in traversal of the paper only avoids visiting the rest, so its
+ * result is this set. cand receives the k ids ascending (fewer when
+ * n < k); returns their count, or -1 for a Hilbert-ordered index. */
+int64_t orc_knn_one(const orc_index *ix, const float *vol, const float *t, const uint8_t *m,
+                    int k, int64_t *best_id, float *best_cost, int64_t *cand)
+{
+    if (ix->curve != 0 || k < 1) return -1;
+    grid_t g = make_grid(ix->nd, ix->shape);
+    int64_t Kd = ipow(ix->K, ix->nd);
+    int W64 = (ix->D * ix->b + 63) / 64;
+    int64_t R = (ix->L > 1) ? ((int64_t)1 << (ix->b - 1)) : ((int64_t)1 << ix->b);
+    int sb = 0;
+    int64_t kb = -1, nb = 1;
+    for (int s = 0; s < ix->S; s++) {
+        int64_t kk = 0, ns = ix->npix[s];
+        for (int i = 0; i < ns; i++) kk += m[ix->pix[s * Kd + i]];
+        if (kb < 0 || kk * nb > kb * ns) { sb = s; kb = kk; nb = ns; }
+    }
+    double yq[64];
+    query_coords(ix, t, m, sb, yq);
+    uint32_t u[64], v[64];
+    cell_of_real(yq, ix->D, ix->lo + sb * ix->D, ix->span[sb], R, 0, u);
+    const uint64_t *keys = ix->keys + ((int64_t)(sb * ix->L) * ix->n) * W64;
+    const int64_t *ids = ix->ids + (int64_t)(sb * ix->L) * ix->n;
+    dist_id *all = malloc(sizeof(dist_id) * (size_t)ix->n);
+    for (int64_t i = 0; i < ix->n; i++) {
+        orc_morton_decode(keys + i * W64, ix->D, ix->b, v);
+        int64_t dsum = 0;
+        for (int d = 0; d < ix->D; d++) {
+            int64_t e = (int64_t)v[d] - (int64_t)u[d];
+            dsum += e * e;
+        }
+        all[i].dist = dsum;
+        all[i].id = ids[i];
+    }
+    qsort(all, (size_t)ix->n, sizeof(dist_id), cmp_dist_id);
+    int64_t nk = ix->n < k ? ix->n : k;
+    for (int64_t i = 0; i < nk; i++) cand[i] = all[i].id;
+    free(all);
+    qsort(cand, (size_t)nk, sizeof(int64_t), cmp_i64);
+    int64_t bi = -1;
+    float bc = INFINITY;
+    for (int64_t i = 0; i < nk; i++) {
+        float c = cost_of(ix->norm, vol, &g, ix->C, ix->K, cand[i], t, m);
+        if (bi < 0 || c < bc) { bc = c; bi = cand[i]; }
+    }
+    *best_id = bi;
+    *best_cost = bc;
+    return nk;
+}
+
+/* Batch form: cand is [Q][k] padded with -1, ncand[Q]; returns -1 if the
+ * index cannot answer k-NN queries (Hilbert order, k < 1). */
+int orc_knn(const orc_index *ix, const float *vol, const float *t, const uint8_t *m, int64_t Q,
+            int k, int64_t *best_id, float *best_cost, int64_t *cand, int32_t *ncand)
+{
+    int64_t Kd = ipow(ix->K, ix->nd);
+    for (int64_t q = 0; q < Q; q++) {
+        int64_t *cq = cand + q * k;
+        for (int i = 0; i < k; i++) cq[i] = -1;
+        int64_t nc = orc_knn_one(ix, vol, t + q * Kd * ix->C, m + q * Kd, k, best_id + q,
+                                 best_cost + q, cq);
+        if (nc < 0) return -1;
+        ncand[q] = (int32_t)nc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Inpainting loop (Section I; Criminisi order)                        */
 /* ------------------------------------------------------------------ */
 

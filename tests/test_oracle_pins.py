@@ -509,6 +509,67 @@ def test_index_finds_verbatim_copies_with_unique_keys(orc):
     assert hits > len(sel) // 2
 
 
+# ------------------------------------------------------------------ exact k-NN query (Section II.D)
+@pytest.mark.parametrize("D,b", [(2, 4), (5, 8), (8, 21), (10, 8), (16, 12)])
+def test_morton_decode_inverts_the_interleave(orc, D, b):
+    rng = np.random.default_rng(D * 100 + b)
+    for _ in range(50):
+        v = rng.integers(0, 1 << b, size=D, dtype=np.uint32)
+        assert np.array_equal(orc.morton_decode(orc.key_of(v, b, 0), D, b), v)
+
+
+def test_knn_equals_full_scan_when_k_covers_dictionary(orc):
+    vol, mask = _img(h=18, w=17, c=2, seed=12, frac=0.08, holes=1)
+    K = 5
+    ix = orc.Index(vol, mask, K, D=4, L=2, key_bits=6, window=8)
+    f = orc.front(mask)
+    t, m = orc.extract(vol, mask, K, f)
+    bi, bc, cand, nc = ix.knn_query(vol, t, m, k=ix.n + 5)
+    b2, c2 = orc.brute(vol, mask.shape, K, ix.dict, t, m)
+    assert np.array_equal(bi, b2) and np.array_equal(bc.view(np.uint32), c2.view(np.uint32))
+    assert np.all(nc == ix.n) and np.all(cand[:, :ix.n] == ix.dict[None, :])
+
+
+def test_knn_set_is_the_k_nearest_cells(orc):
+    # cells recomputed in numpy from the projections (not from the keys),
+    # squared distances, k smallest by (distance, id)
+    vol, mask = _img(h=40, w=44, c=1, seed=3)
+    K, D, L, b, k = 5, 4, 3, 10, 20
+    ix = orc.Index(vol, mask, K, D=D, L=L, key_bits=b, window=8, keep_y=True)
+    R = 1 << (b - 1)
+    f = orc.front(mask)[::5]
+    t, m = orc.extract(vol, mask, K, f)
+    _, _, cand, nc = ix.knn_query(vol, t, m, k=k)
+    sub, yq = ix.query_point(t, m)
+    for q in range(len(f)):
+        s = sub[q]
+        lo, span = ix.lo[s], ix.span[s]
+        cells = np.clip(np.floor_divide((ix.y[s] - lo) * (R - 1), span), 0, R - 1)
+        uq = np.clip(np.floor(((yq[q] - lo) * (R - 1)) / span), 0, R - 1).astype(np.int64)
+        dist = ((cells - uq[None, :]) ** 2).sum(axis=1)
+        order = np.lexsort((ix.dict, dist))[:k]
+        assert nc[q] == k
+        assert np.array_equal(cand[q], np.sort(ix.dict[order]))
+
+
+def test_knn_finds_verbatim_copies(orc):
+    vol, mask = _img(h=36, w=40, c=3, seed=21)
+    K = 5
+    ix = orc.Index(vol, mask, K, D=6, L=2, key_bits=12, window=8)
+    cen = ix.dict[[5, 77, 300, ix.n - 2]]
+    t, m = orc.extract(vol, mask, K, cen)
+    _, bc, _, _ = ix.knn_query(vol, t, m, k=16)
+    assert np.all(bc == 0.0)
+
+
+def test_knn_needs_a_morton_index(orc):
+    vol, mask = _img(h=20, w=22, c=1, seed=2)
+    ix = orc.Index(vol, mask, 3, D=2, L=2, key_bits=6, curve="hilbert")
+    t, m = orc.extract(vol, mask, 3, orc.front(mask)[:2])
+    with pytest.raises(ValueError):
+        ix.knn_query(vol, t, m, k=4)
+
+
 def test_query_coords_full_mask_exact_and_partial_least_squares(orc):
     import ctypes
     vol, mask = _img(h=40, w=40, c=1, seed=14)
