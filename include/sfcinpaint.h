@@ -182,6 +182,23 @@ sfc_status sfc_index_build_with_basis(const float *volume, const uint8_t *mask,
 sfc_status sfc_query(sfc_index *idx, const float *targets, const uint8_t *target_masks,
                      int64_t Q, sfc_mode mode, int64_t *best_id, float *best_cost);
 
+/* Exact k-NN query of Section II.D on an index built with Morton curves:
+ * for each target, the chosen subset and grid cell as in SFC_MODE_INDEX, the
+ * k dictionary patches whose cells on the unshifted curve (curve 0) are
+ * nearest in squared Euclidean distance (ties: lower id), found by the
+ * outside-in traversal of the curve (litmax/bigmin splits at the most
+ * significant differing bit, searches restricted to the parent interval,
+ * nearer part first, parts farther than the k-th distance skipped, regions
+ * of at most mu entries scanned); the answer minimises (cost, id) over those
+ * k, with the handle's norm. best_id int64 [Q], best_cost float32 [Q];
+ * cand (nullable) int64 [Q, k] the k ids ascending, padded with -1 when the
+ * dictionary has fewer; ncand (nullable) int32 [Q]. Q = 0 is a no-op.
+ * SFC_EINVAL: no SFC index, k outside 1..256, mu < 1, null targets or
+ * results; SFC_EUNSUPPORTED: Hilbert curves, reduced_dim above 16. */
+sfc_status sfc_query_knn(sfc_index *idx, const float *targets, const uint8_t *target_masks,
+                         int64_t Q, int32_t k, int32_t mu, int64_t *best_id, float *best_cost,
+                         int64_t *cand, int32_t *ncand);
+
 /* Candidate sets of the index query: cand int64 [Q, n_curves*window], the
  * sorted unique dictionary ids per query padded with -1; ncand int32 [Q]. */
 sfc_status sfc_query_candidates(sfc_index *idx, const float *targets,

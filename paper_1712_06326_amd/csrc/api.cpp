@@ -439,6 +439,23 @@ sfc_status sfc_query_candidates(sfc_index* ix, const float* targets, const uint8
     return query_index(ix, targets, target_masks, Q, nullptr, nullptr, cand, ncand);
 }
 
+sfc_status sfc_query_knn(sfc_index* ix, const float* targets, const uint8_t* target_masks,
+                         int64_t Q, int32_t k, int32_t mu, int64_t* best_id, float* best_cost,
+                         int64_t* cand, int32_t* ncand) {
+    clear_error();
+    if (!ix) return fail(SFC_EINVAL, "index is NULL");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "k-NN queries need an SFC index handle");
+    if (Q < 0) return fail(SFC_EINVAL, "Q must be >= 0");
+    if (k < 1 || k > 256) return fail(SFC_EINVAL, "k must be 1..256");
+    if (mu < 1) return fail(SFC_EINVAL, "mu must be >= 1");
+    if (ix->opt.curve != SFC_CURVE_MORTON)
+        return fail(SFC_EUNSUPPORTED, "k-NN queries need Morton curves (litmax/bigmin)");
+    if (Q == 0) return SFC_OK;
+    if (!targets || !target_masks || !best_id || !best_cost)
+        return fail(SFC_EINVAL, "sfc_query_knn: null pointer");
+    return query_knn(ix, targets, target_masks, Q, k, mu, best_id, best_cost, cand, ncand);
+}
+
 sfc_status sfc_query_coords(sfc_index* ix, const float* targets, const uint8_t* target_masks,
                             int64_t Q, int32_t* subset, double* coords) {
     clear_error();

@@ -109,5 +109,7 @@ sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t 
                        int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
 sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                         int32_t* subset, double* coords);
+sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int k, int mu,
+                     int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
 
 }  // namespace sfc

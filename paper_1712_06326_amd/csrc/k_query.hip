@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
 }
 
 // One wave per query: exact cost of every listed candidate, (cost, id) min.
-template <int ND, int K, int C>
+template <int ND, int K, int C, int NORM>
 __global__ __launch_bounds__(256) void list_rescore_kernel(QueryIndexView v, const float* __restrict__ vol,
                                                            const float* __restrict__ t,
                                                            const uint32_t* __restrict__ rowmask,
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void list_rescore_kernel(QueryIndexView v, con
     uint64_t best = ~0ull;
     for (int i = lane; i < nc; i += 64) {
         const uint32_t c = list[q * cap + i];
-        const float cost = cand_cost<ND, K, C, 0>(v, vol, tq, rm, qpad, c);
+        const float cost = cand_cost<ND, K, C, NORM>(v, vol, tq, rm, qpad, c);
         const uint64_t pk = ((uint64_t)__float_as_uint(cost) << 32) | c;
         if (pk < best) best = pk;
     }
@@ -358,6 +358,333 @@ __global__ __launch_bounds__(256) void list_rescore_kernel(QueryIndexView v, con
 
 using PrologueFn = void (*)(QueryIndexView, const float*, const uint8_t*, int64_t, int32_t*,
                             double*, uint64_t*);
+// ------------------------------------------------------------ exact k-NN
+// The k-NN query of Section II.D on the unshifted Morton curve (curve 0 of
+// the chosen subset), one wave per query. A region is a box of grid cells
+// whose curve interval [a, z) holds exactly the entries whose keys lie
+// between the keys of its corners. It is split where the corners first
+// differ, at the most significant bit (dimension 0 first among equal
+// levels): the low part keeps the upper corner but takes litmax in the split
+// dimension (that bit 0, the bits below it 1), the high part keeps the lower
+// corner but takes bigmin (that bit 1, the bits below 0). Each part's
+// interval comes from a search restricted to the parent's (Section II.E).
+// The nearer part is visited first; a part farther from the query cell than
+// the k-th nearest entry found so far is skipped. Regions of at most mu
+// entries, or of one cell, are scanned: each entry's cell is decoded from
+// its key and kept if it ranks among the k smallest (squared distance, id).
+// The stack holds only the far parts along the current path, at most
+// D*b + 1 frames, in LDS with the k-best list.
+constexpr int kKnnMax = 256;   // largest k
+
+struct KnnFrame {
+    uint32_t a, z;   // curve interval
+    int64_t bd;      // squared distance from the query cell to the box
+};
+
+struct KnnArgs {
+    QueryIndexView v;
+    const int32_t* qsub;
+    const double* qcoords;   // [Q][D]
+    int64_t Q;
+    int k, mu, depth;        // depth: frames of stack space
+    uint32_t* list;          // [Q][k] ids of the k nearest, ascending
+    int32_t* cnt;            // [Q] entries in list (0 if the query failed)
+    int32_t* thr;            // [Q] set to 0 (a valid list for the rescoring)
+    unsigned int* overflow;  // set when a stack would overflow
+};
+
+__device__ inline bool di_less(int64_t d, uint32_t i, int64_t e, uint32_t j) {
+    return d < e || (d == e && i < j);
+}
+
+// -1, 0, 1: the key at pos against qk
+__device__ inline int key_cmp3(const uint64_t* Kk, int64_t n, int64_t pos, const uint64_t* qk,
+                               int W64) {
+    for (int w = 0; w < W64; w++) {
+        const uint64_t x = Kk[(int64_t)w * n + pos];
+        if (x != qk[w]) return x < qk[w] ? -1 : 1;
+    }
+    return 0;
+}
+
+// First position in [a, z) whose key is >= qk (strict: > qk), by rounds of
+// 64 probes as in search_kernel; the whole wave calls it.
+__device__ int64_t coop_bound(const uint64_t* Kk, int64_t n, int64_t a, int64_t z,
+                              const uint64_t* qk, int W64, bool strict, int lane) {
+    while (z - a > 64) {
+        const int64_t len = z - a;
+        const int64_t pos = a + ((int64_t)(lane + 1) * len) / 65;
+        const int c = key_cmp3(Kk, n, pos, qk, W64);
+        const bool before = strict ? c <= 0 : c < 0;
+        const int cnt = __popcll(__ballot(before));
+        const int64_t na = cnt > 0 ? a + ((int64_t)cnt * len) / 65 + 1 : a;
+        const int64_t nz = cnt < 64 ? a + ((int64_t)(cnt + 1) * len) / 65 : z;
+        a = na;
+        z = nz;
+    }
+    bool before = false;
+    if (lane < z - a) {
+        const int c = key_cmp3(Kk, n, a + lane, qk, W64);
+        before = strict ? c <= 0 : c < 0;
+    }
+    return a + __popcll(__ballot(before));
+}
+
+template <int MD>
+__device__ inline int64_t box_dist(const uint32_t* lo, const uint32_t* hi, const int64_t* u, int D) {
+    int64_t acc = 0;
+#pragma unroll
+    for (int d = 0; d < MD; d++) {
+        if (d < D) {
+            int64_t e = 0;
+            if (u[d] < (int64_t)lo[d]) e = (int64_t)lo[d] - u[d];
+            else if (u[d] > (int64_t)hi[d]) e = u[d] - (int64_t)hi[d];
+            acc += e * e;
+        }
+    }
+    return acc;
+}
+
+template <int MD>
+__global__ __launch_bounds__(64) void knn_kernel(KnnArgs A) {
+    extern __shared__ __align__(16) uint8_t knn_smem[];
+    const QueryIndexView& v = A.v;
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    if (q >= A.Q) return;
+    const int D = v.D, W64 = v.W64, b = v.b, k = A.k;
+    const int64_t n = v.n;
+    const int s = A.qsub[q];
+    const uint64_t* Kk = v.keys + (int64_t)s * v.L * W64 * n;   // curve 0 of subset s
+    const uint32_t* ids = v.ids + (int64_t)s * v.L * n;
+    int64_t* ldist = reinterpret_cast<int64_t*>(knn_smem);
+    uint32_t* lid = reinterpret_cast<uint32_t*>(ldist + kKnnMax);
+    KnnFrame* fr = reinterpret_cast<KnnFrame*>(lid + kKnnMax);
+    uint32_t* flo = reinterpret_cast<uint32_t*>(fr + A.depth);
+    uint32_t* fhi = flo + (int64_t)A.depth * MD;
+
+    // the query's cell on the unshifted curve, by the index query's rule
+    int64_t u[MD];
+    {
+        const double span = (double)v.span[s], rm1 = (double)(v.R - 1);
+#pragma unroll
+        for (int d = 0; d < MD; d++) {
+            u[d] = 0;
+            if (d < D) {
+                double uu = floor(((A.qcoords[q * D + d] - (double)v.lo[s * D + d]) * rm1) / span);
+                if (!(uu >= 0.0)) uu = 0.0;
+                if (uu > rm1) uu = rm1;
+                u[d] = (int64_t)uu;
+            }
+        }
+    }
+    int cntl = 0;                  // entries in the list
+    int64_t kd = 0;                // largest (distance, id) of a full list
+    uint32_t kid = 0;
+    int kpos = 0;
+    auto find_max = [&]() {
+        int64_t bd = -1;
+        uint32_t bi = 0;
+        int bp = -1;
+        for (int j = lane; j < k; j += 64) {
+            const int64_t d = ldist[j];
+            const uint32_t i2 = lid[j];
+            if (bp < 0 || di_less(bd, bi, d, i2)) {
+                bd = d;
+                bi = i2;
+                bp = j;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const int64_t od = (int64_t)__shfl_xor((long long)bd, off, 64);
+            const uint32_t oi = (uint32_t)__shfl_xor((int)bi, off, 64);
+            const int op = __shfl_xor(bp, off, 64);
+            if (op >= 0 && (bp < 0 || di_less(bd, bi, od, oi))) {
+                bd = od;
+                bi = oi;
+                bp = op;
+            }
+        }
+        kd = bd;
+        kid = bi;
+        kpos = bp;
+    };
+    int sp = 0;
+    bool overflow = false;
+    auto push = [&](uint32_t a, uint32_t z, int64_t bd, const uint32_t* lo, const uint32_t* hi) {
+        if (lane == 0) {
+            fr[sp] = KnnFrame{a, z, bd};
+#pragma unroll
+            for (int d = 0; d < MD; d++) {
+                flo[sp * MD + d] = lo[d];
+                fhi[sp * MD + d] = hi[d];
+            }
+        }
+        sp++;
+    };
+    {
+        uint32_t lo[MD], hi[MD];
+#pragma unroll
+        for (int d = 0; d < MD; d++) {
+            lo[d] = 0;
+            hi[d] = d < D ? (uint32_t)(v.R - 1) : 0u;
+        }
+        push(0u, (uint32_t)n, box_dist<MD>(lo, hi, u, D), lo, hi);
+    }
+    while (sp > 0) {
+        __syncthreads();   // the frame lane 0 wrote is visible
+        sp--;
+        const KnnFrame f = fr[sp];
+        uint32_t lo[MD], hi[MD];
+#pragma unroll
+        for (int d = 0; d < MD; d++) {
+            lo[d] = flo[sp * MD + d];
+            hi[d] = fhi[sp * MD + d];
+        }
+        __syncthreads();   // every lane has read it before it is overwritten
+        if (cntl == k && f.bd > kd) continue;
+        bool single = true;
+#pragma unroll
+        for (int d = 0; d < MD; d++)
+            if (d < D) single = single && lo[d] == hi[d];
+        if ((int64_t)(f.z - f.a) <= A.mu || single) {
+            for (int64_t base = f.a; base < f.z; base += 64) {
+                const int64_t i = base + lane;
+                const bool live = i < f.z;
+                int64_t dist = 0;
+                uint32_t id = 0;
+                if (live) {
+                    uint64_t w[kMaxKeyWords];
+#pragma unroll
+                    for (int j = 0; j < kMaxKeyWords; j++) w[j] = j < W64 ? Kk[(int64_t)j * n + i] : 0ull;
+                    uint32_t c[MD];
+                    morton_decode<MD>(w, D, b, W64, c);
+#pragma unroll
+                    for (int d = 0; d < MD; d++) {
+                        if (d < D) {
+                            const int64_t e = (int64_t)c[d] - u[d];
+                            dist += e * e;
+                        }
+                    }
+                    id = ids[i];
+                }
+                uint64_t mask = __ballot(live && (cntl < k || di_less(dist, id, kd, kid)));
+                while (mask) {
+                    const int src = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    const int64_t dd = (int64_t)__shfl((long long)dist, src, 64);
+                    const uint32_t ii = (uint32_t)__shfl((int)id, src, 64);
+                    if (cntl < k) {
+                        if (lane == 0) {
+                            ldist[cntl] = dd;
+                            lid[cntl] = ii;
+                        }
+                        cntl++;
+                        if (cntl == k) {
+                            __syncthreads();
+                            find_max();
+                        }
+                    } else if (di_less(dd, ii, kd, kid)) {
+                        if (lane == 0) {
+                            ldist[kpos] = dd;
+                            lid[kpos] = ii;
+                        }
+                        __syncthreads();
+                        find_max();
+                    }
+                }
+            }
+            continue;
+        }
+        // split at the most significant differing bit
+        int sd = 0, sh = -1;
+#pragma unroll
+        for (int d = 0; d < MD; d++) {
+            if (d < D) {
+                const uint32_t x = lo[d] ^ hi[d];
+                if (x) {
+                    const int h = 31 - __builtin_clz(x);
+                    if (h > sh) {
+                        sh = h;
+                        sd = d;
+                    }
+                }
+            }
+        }
+        uint32_t lit[MD], big[MD];
+#pragma unroll
+        for (int d = 0; d < MD; d++) {
+            lit[d] = hi[d];
+            big[d] = lo[d];
+        }
+        uint32_t hs = 0, ls = 0;
+#pragma unroll
+        for (int d = 0; d < MD; d++)
+            if (d == sd) hs = hi[d];
+        const uint32_t pre = (uint32_t)(((uint64_t)hs >> (sh + 1)) << (sh + 1));
+        ls = pre | ((1u << sh) - 1u);
+        hs = pre | (1u << sh);
+#pragma unroll
+        for (int d = 0; d < MD; d++) {
+            if (d == sd) {
+                lit[d] = ls;
+                big[d] = hs;
+            }
+        }
+        uint64_t kl[kMaxKeyWords], kb[kMaxKeyWords];
+        interleave_words<MD>(lit, D, b, W64, kl);
+        interleave_words<MD>(big, D, b, W64, kb);
+        const int64_t zl = coop_bound(Kk, n, f.a, f.z, kl, W64, true, lane);
+        const int64_t ah = coop_bound(Kk, n, zl, f.z, kb, W64, false, lane);
+        const int64_t bl = box_dist<MD>(lo, lit, u, D), bh = box_dist<MD>(big, hi, u, D);
+        const bool use_l = f.a < zl && !(cntl == k && bl > kd);
+        const bool use_h = ah < f.z && !(cntl == k && bh > kd);
+        if (sp + 2 > A.depth) {
+            overflow = true;
+            break;
+        }
+        // the far part first, so that the near one is popped next
+        if (bl <= bh) {
+            if (use_h) push((uint32_t)ah, f.z, bh, big, hi);
+            if (use_l) push(f.a, (uint32_t)zl, bl, lo, lit);
+        } else {
+            if (use_l) push(f.a, (uint32_t)zl, bl, lo, lit);
+            if (use_h) push((uint32_t)ah, f.z, bh, big, hi);
+        }
+    }
+    __syncthreads();
+    if (overflow) {
+        if (lane == 0) {
+            A.cnt[q] = 0;
+            A.thr[q] = 0;
+            atomicOr(A.overflow, 1u);
+        }
+        return;
+    }
+    // ascending ids (they are distinct: every entry is visited at most once)
+    for (int j = lane; j < cntl; j += 64) {
+        const uint32_t x = lid[j];
+        int r = 0;
+        for (int t2 = 0; t2 < cntl; t2++) r += lid[t2] < x ? 1 : 0;
+        A.list[q * k + r] = x;
+    }
+    if (lane == 0) {
+        A.cnt[q] = cntl;
+        A.thr[q] = 0;
+    }
+}
+
+__global__ void knn_cand_kernel(const uint32_t* __restrict__ list, const int32_t* __restrict__ cnt,
+                                int64_t Q, int k, int64_t* __restrict__ cand,
+                                int32_t* __restrict__ ncand) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q * k) return;
+    const int64_t q = i / k;
+    const int j = (int)(i - q * k);
+    if (cand) cand[i] = j < cnt[q] ? (int64_t)list[i] : -1;
+    if (ncand && j == 0) ncand[q] = cnt[q];
+}
+
 using RescoreFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
                            const int32_t*, const int64_t*, int64_t, int, int64_t*, float*,
                            int64_t*, int32_t*);
@@ -372,10 +699,11 @@ using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32
 struct RescoreEntry {
     int nd, K, C;
     RescoreFn fn, fn_l1;
-    ListFn lfn;
+    ListFn lfn, lfn_l1;
 };
 #define SFC_RESCORE(ND, K, C)                                                                 \
-    {ND, K, C, rescore_kernel<ND, K, C, 0>, rescore_kernel<ND, K, C, 1>, list_rescore_kernel<ND, K, C>}
+    {ND, K, C, rescore_kernel<ND, K, C, 0>, rescore_kernel<ND, K, C, 1>,                     \
+     list_rescore_kernel<ND, K, C, 0>, list_rescore_kernel<ND, K, C, 1>}
 const RescoreEntry kRescore[] = {
     SFC_RESCORE(2, 3, 1), SFC_RESCORE(2, 3, 2), SFC_RESCORE(2, 3, 3),
     SFC_RESCORE(2, 5, 1), SFC_RESCORE(2, 5, 2), SFC_RESCORE(2, 5, 3),
@@ -426,7 +754,8 @@ sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub, con
 sfc_status launch_list_rescore(const Grid& g, const float* vol, const float* t,
                                const uint32_t* rowmask, int64_t qpad, const uint32_t* list,
                                const int32_t* cnt, const int32_t* thr, int cap, int64_t Q,
-                               int64_t* best_id, float* best_cost, uint8_t* fb, hipStream_t st) {
+                               int64_t* best_id, float* best_cost, uint8_t* fb, int norm,
+                               hipStream_t st) {
     if (Q == 0) return SFC_OK;
     const RescoreEntry* ent = nullptr;
     for (const auto& e : kRescore)
@@ -441,8 +770,8 @@ sfc_status launch_list_rescore(const Grid& g, const float* vol, const float* t,
         v.shape[i] = g.shape[i];
         v.stride[i] = g.stride[i];
     }
-    hipLaunchKernelGGL(ent->lfn, dim3(blocks_for(Q * 64)), dim3(256), 0, st, v, vol, t, rowmask,
-                       qpad, list, cnt, thr, cap, Q, best_id, best_cost, fb);
+    hipLaunchKernelGGL(norm == 1 ? ent->lfn_l1 : ent->lfn, dim3(blocks_for(Q * 64)), dim3(256), 0,
+                       st, v, vol, t, rowmask, qpad, list, cnt, thr, cap, Q, best_id, best_cost, fb);
     return launched("list_rescore_kernel");
 }
 
@@ -469,6 +798,45 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
                        v, vol, t, rowmask, qpad, qsub, wstart, Q, cap, best_id, best_cost, cand,
                        ncand);
     return launched("rescore_kernel");
+}
+
+sfc_status launch_knn(const QueryIndexView& v, const int32_t* qsub, const double* qcoords,
+                      int64_t Q, int k, int mu, uint32_t* list, int32_t* cnt, int32_t* thr,
+                      unsigned int* overflow, hipStream_t st) {
+    if (Q == 0) return SFC_OK;
+    if (k < 1 || k > kKnnMax) return fail(SFC_EINVAL, "k-NN query: k must be 1..256");
+    if (v.D < 1 || v.D > 16) return fail(SFC_EUNSUPPORTED, "k-NN query: reduced dimension above 16");
+    const int md = v.D <= 8 ? 8 : 16;
+    KnnArgs A{};
+    A.v = v;
+    A.qsub = qsub;
+    A.qcoords = qcoords;
+    A.Q = Q;
+    A.k = k;
+    A.mu = mu;
+    A.depth = v.D * v.b + 2;
+    A.list = list;
+    A.cnt = cnt;
+    A.thr = thr;
+    A.overflow = overflow;
+    const size_t lds = (size_t)kKnnMax * 12 + (size_t)A.depth * (sizeof(KnnFrame) + 8 * md);
+    if (lds > 160 * 1024) return fail(SFC_EUNSUPPORTED, "k-NN query: D * key_bits too large");
+    const void* fn = md == 8 ? (const void*)knn_kernel<8> : (const void*)knn_kernel<16>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return check_hip(e, "k-NN LDS attribute");
+    }
+    if (Q > 0x7fffffffLL) return fail(SFC_EUNSUPPORTED, "k-NN query: too many queries");
+    if (md == 8) knn_kernel<8><<<(unsigned)Q, 64, lds, st>>>(A);
+    else knn_kernel<16><<<(unsigned)Q, 64, lds, st>>>(A);
+    return launched("knn_kernel");
+}
+
+sfc_status launch_knn_cand(const uint32_t* list, const int32_t* cnt, int64_t Q, int k,
+                           int64_t* cand, int32_t* ncand, hipStream_t st) {
+    if (Q == 0 || (!cand && !ncand)) return SFC_OK;
+    knn_cand_kernel<<<blocks_for(Q * k), 256, 0, st>>>(list, cnt, Q, k, cand, ncand);
+    return launched("knn_cand_kernel");
 }
 
 }  // namespace sfc

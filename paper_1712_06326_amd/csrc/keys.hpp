@@ -67,4 +67,34 @@ __device__ __forceinline__ void interleave_words(const uint32_t* v, int D, int b
     }
 }
 
+// Inverse of interleave_words for the Morton order: w holds the key's W64
+// words (word 0 most significant) in w[0..W64); bit l*D + (D-1-d) of the key
+// is bit l of coordinate d. The words are right-aligned in a 256-bit
+// accumulator that shifts right by D per level, lowest level first.
+template <int MD>
+__device__ __forceinline__ void morton_decode(const uint64_t* w, int D, int b, int W64,
+                                              uint32_t* v) {
+    static_assert(kMaxKeyWords == 4, "the accumulator holds four words");
+    uint64_t a[4];   // a[3] least significant
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int src = W64 - 4 + j;
+        a[j] = src == 0 ? w[0] : src == 1 ? w[1] : src == 2 ? w[2] : src == 3 ? w[3] : 0ull;
+    }
+#pragma unroll
+    for (int d = 0; d < MD; d++) v[d] = 0;
+    const int ls = 64 - D;   // 1 <= D <= 32
+    const uint64_t low = (D == 64) ? ~0ull : ((1ull << D) - 1);
+    for (int l = 0; l < b; l++) {
+        const uint64_t grp = a[3] & low;
+#pragma unroll
+        for (int d = 0; d < MD; d++)
+            if (d < D) v[d] |= (uint32_t)((grp >> (D - 1 - d)) & 1u) << l;
+        a[3] = (a[3] >> D) | (a[2] << ls);
+        a[2] = (a[2] >> D) | (a[1] << ls);
+        a[1] = (a[1] >> D) | (a[0] << ls);
+        a[0] >>= D;
+    }
+}
+
 }  // namespace sfc

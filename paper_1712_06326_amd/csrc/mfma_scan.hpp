@@ -59,6 +59,7 @@ sfc_status launch_filter_list(FilterArgs a, int64_t nwork, hipStream_t st);
 sfc_status launch_list_rescore(const Grid& g, const float* vol, const float* t,
                                const uint32_t* rowmask, int64_t qpad, const uint32_t* list,
                                const int32_t* cnt, const int32_t* thr, int cap, int64_t Q,
-                               int64_t* best_id, float* best_cost, uint8_t* fb, hipStream_t st);
+                               int64_t* best_id, float* best_cost, uint8_t* fb, int norm,
+                               hipStream_t st);
 
 }  // namespace sfc

@@ -37,4 +37,15 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
                                 float* best_cost, int64_t* cand, int32_t* ncand, int norm,
                                 hipStream_t st);
 
+// Exact k-NN query (Section II.D) on curve 0 of each query's subset: the k
+// nearest entries by (squared cell distance, id), ids ascending in list
+// [Q][k], counts in cnt; thr[q] = 0. overflow (one word, zeroed by the
+// caller) is set if a traversal stack would overflow.
+sfc_status launch_knn(const QueryIndexView& v, const int32_t* qsub, const double* qcoords,
+                      int64_t Q, int k, int mu, uint32_t* list, int32_t* cnt, int32_t* thr,
+                      unsigned int* overflow, hipStream_t st);
+// list/cnt -> cand int64 [Q][k] padded -1 and ncand [Q] (either may be null)
+sfc_status launch_knn_cand(const uint32_t* list, const int32_t* cnt, int64_t Q, int k,
+                           int64_t* cand, int32_t* ncand, hipStream_t st);
+
 }  // namespace sfc

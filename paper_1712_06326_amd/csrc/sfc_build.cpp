@@ -10,6 +10,7 @@
 
 #include "build.hpp"
 #include "index.hpp"
+#include "mfma_scan.hpp"
 #include "proj.hpp"
 #include "query.hpp"
 
@@ -466,6 +467,51 @@ sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t 
     SFC_TRY(launch_query_rescore(v, ix->vol, t, rm, qpad, qsub, wstart, Q, best_id, best_cost, cand,
                                  ncand, ix->opt.norm, st));
     return ix->timer.end(st);
+}
+
+sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int k, int mu,
+                     int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand) {
+    const Grid& g = ix->g;
+    hipStream_t st = ix->st;
+    const int64_t qpad = scan_qpad(Q);
+    SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
+    uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
+    SFC_TRY(launch_pack_rowmask(m, g, Q, rm, st));
+    const size_t need = (size_t)Q * (4 + 8 * ix->D + 8 * ix->L * ix->W64 + 4 * k + 4 + 4 + 1) + 1024;
+    SFC_TRY(ix->qtmp.reserve(need, "k-NN query scratch"));
+    char* p = static_cast<char*>(ix->qtmp.ptr);
+    auto take = [&](size_t bytes) {
+        char* r = p;
+        p += (bytes + 63) & ~size_t(63);
+        return r;
+    };
+    double* coords = reinterpret_cast<double*>(take((size_t)Q * 8 * ix->D));
+    uint64_t* qkeys = reinterpret_cast<uint64_t*>(take((size_t)Q * 8 * ix->L * ix->W64));
+    int32_t* qsub = reinterpret_cast<int32_t*>(take((size_t)Q * 4));
+    uint32_t* list = reinterpret_cast<uint32_t*>(take((size_t)Q * 4 * k));
+    int32_t* cnt = reinterpret_cast<int32_t*>(take((size_t)Q * 4));
+    int32_t* thr = reinterpret_cast<int32_t*>(take((size_t)Q * 4));
+    uint8_t* fb = reinterpret_cast<uint8_t*>(take((size_t)Q));
+    uint64_t* flag = reinterpret_cast<uint64_t*>(take(8));
+    SFC_TRY(launch_fill_u64(flag, 1, 0ull, st));
+    const QueryIndexView v = view_of(ix);
+    SFC_TRY(ix->timer.begin("prologue_kernel", st));
+    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, st));
+    SFC_TRY(ix->timer.end(st));
+    SFC_TRY(ix->timer.begin("knn_kernel", st));
+    SFC_TRY(launch_knn(v, qsub, coords, Q, k, mu, list, cnt, thr,
+                       reinterpret_cast<unsigned int*>(flag), st));
+    SFC_TRY(ix->timer.end(st));
+    SFC_TRY(ix->timer.begin("list_rescore_kernel", st));
+    SFC_TRY(launch_list_rescore(g, ix->vol, t, rm, qpad, list, cnt, thr, k, Q, best_id, best_cost,
+                                fb, ix->opt.norm, st));
+    SFC_TRY(ix->timer.end(st));
+    SFC_TRY(launch_knn_cand(list, cnt, Q, k, cand, ncand, st));
+    uint64_t over = 0;
+    SFC_HIP(hipMemcpyAsync(&over, flag, 8, hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    if (over) return fail(SFC_EDEVICE, "k-NN query: a traversal stack overflowed");
+    return SFC_OK;
 }
 
 sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int32_t* subset,

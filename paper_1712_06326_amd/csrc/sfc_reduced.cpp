@@ -156,7 +156,7 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
     SFC_TRY(launch_pack_rowmask(m, g, Q, rm, st));
     SFC_TRY(ix->timer.begin("list_rescore_kernel", st));
     SFC_TRY(launch_list_rescore(g, ix->vol, t, rm, qpad_rm, list, cnt, thr, cap, Q, best_id,
-                                best_cost, fb, st));
+                                best_cost, fb, SFC_NORM_L2, st));
     SFC_TRY(ix->timer.end(st));
     // queries the filter could not settle go through the float32 scan
     SFC_TRY(launch_compact(fb, Q, fidx, nullptr, Q, nfb_dev, cscratch, st));

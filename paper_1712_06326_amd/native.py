@@ -79,6 +79,7 @@ _SIG = {
                                         C.POINTER(Options), P, C.POINTER(P)]),
     "sfc_query": (ST, [P, P, P, I64, C.c_int, P, P]),
     "sfc_query_candidates": (ST, [P, P, P, I64, P, P]),
+    "sfc_query_knn": (ST, [P, P, P, I64, I32, I32, P, P, P, P]),
     "sfc_query_coords": (ST, [P, P, P, I64, P, P]),
     "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
     "sfc_query_kernel_times": (ST, [P, P, I32, C.POINTER(C.c_int32)]),
@@ -254,6 +255,19 @@ class Index:
         bc = torch.empty(Q, dtype=torch.float32, device=t.device)
         _check(_L.sfc_query(self._h, _ptr(t), _ptr(m), Q, MODES[mode], _ptr(bi), _ptr(bc)))
         return bi, bc
+
+    def knn(self, t: torch.Tensor, m: torch.Tensor, k: int = 80, mu: int = 256,
+            candidates: bool = False):
+        """Exact k-NN query (Section II.D): (best_id, best_cost), plus
+        (cand [Q, k] ascending ids padded -1, ncand [Q]) if candidates."""
+        Q = m.shape[0]
+        bi = torch.empty(Q, dtype=torch.int64, device=t.device)
+        bc = torch.empty(Q, dtype=torch.float32, device=t.device)
+        cand = torch.empty((Q, k), dtype=torch.int64, device=t.device) if candidates else None
+        nc = torch.empty(Q, dtype=torch.int32, device=t.device) if candidates else None
+        _check(_L.sfc_query_knn(self._h, _ptr(t), _ptr(m), Q, k, mu, _ptr(bi), _ptr(bc),
+                                _ptr(cand), _ptr(nc)))
+        return (bi, bc, cand, nc) if candidates else (bi, bc)
 
     def autotune(self, t: torch.Tensor, m: torch.Tensor) -> int:
         """Picks the fastest float32-scan tile shape on these targets."""
