@@ -299,6 +299,28 @@ def main():
         "roofline": roofs[dom],
     }
 
+    # the exact k-NN query of Section II.D (k = 80, mu = 256, the paper's
+    # parameters) on the same targets, against the float32 scan's answers;
+    # Morton indices only, outside the timed steps
+    if cfg.get("D") and cfg["curve"] == "morton":
+        ixk = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], timing=True,
+                           **w.opts)
+        for _ in range(2):
+            bk, ck = ixk.knn(res["t"], res["m"], k=80, mu=256)
+        torch.cuda.synchronize()
+        kk = ixk.kernel_times()
+        ixk.close()
+        k_ms = sum(v[1] for v in kk.values())
+        bk, ck = bk.cpu().numpy(), ck.cpu().numpy()
+        okk = bi_s >= 0
+        forms["index_knn"] = {
+            "k": 80, "mu": 256, "qps": round(Qs / (k_ms * 1e-3), 1),
+            "kernel_ms": {k_: round(v[1] / v[0], 3) for k_, v in kk.items()},
+            "recall_at_1_pct": round(100 * float(np.mean(bk[okk] == bi_s[okk])), 3),
+            "acceleration_error_pct": round(float(np.mean(
+                np.sqrt(ck[ok].astype(np.float64)) / np.sqrt(bc_s[ok]) - 1.0)) * 100, 4)}
+        log(f"k-NN query: {k_ms:.2f} ms for {Qs} queries")
+
     # the L1 cost variant (Section III.K): the float32 scan of the same
     # targets under L1 (second run timed; 2 flops per known element and
     # candidate), outside the timed steps
@@ -443,6 +465,12 @@ def large_pass(torch, native, synth, ev):
     scan_ms = a.elapsed_time(b)
     kt = ix.kernel_times()
     n = ix.info.n
+    # the exact k-NN query of Section II.D on the same sample (k = 80, mu = 256)
+    for _ in range(2):
+        bk, ck = ix.knn(ts, ms, k=80, mu=256)
+    torch.cuda.synchronize()
+    kk = ix.kernel_times()
+    knn_ms = sum(v[1] for v in kk.values())
     ix.close()
     bx, cx = bi_x[w.sel].cpu().numpy(), bc_x[w.sel].cpu().numpy()
     bs, cs = bi_s.cpu().numpy(), bc_s.cpu().numpy()
@@ -459,7 +487,12 @@ def large_pass(torch, native, synth, ev):
            "index_recall_at_1_pct": round(100 * float(np.mean(bx == bs)), 3),
            "index_acceleration_error_pct": round(
                float(np.mean(np.sqrt(cx[ok].astype(np.float64)) / np.sqrt(cs[ok]) - 1)) * 100, 4),
-           "index_cost_never_below_scan": bool(np.all(cx >= cs))}
+           "index_cost_never_below_scan": bool(np.all(cx >= cs)),
+           "index_knn": {"k": 80, "mu": 256, "qps": round(ms.shape[0] / (knn_ms * 1e-3), 1),
+                         "recall_at_1_pct": round(100 * float(np.mean(bk.cpu().numpy() == bs)), 3),
+                         "acceleration_error_pct": round(float(np.mean(
+                             np.sqrt(ck.cpu().numpy()[ok].astype(np.float64)) / np.sqrt(cs[ok])
+                             - 1)) * 100, 4)}}
     del w, t, m, ts, ms
     torch.cuda.empty_cache()
     return out

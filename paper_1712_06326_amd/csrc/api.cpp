@@ -453,6 +453,7 @@ sfc_status sfc_query_knn(sfc_index* ix, const float* targets, const uint8_t* tar
     if (Q == 0) return SFC_OK;
     if (!targets || !target_masks || !best_id || !best_cost)
         return fail(SFC_EINVAL, "sfc_query_knn: null pointer");
+    ix->timer.reset(ix->opt.timing != 0);
     return query_knn(ix, targets, target_masks, Q, k, mu, best_id, best_cost, cand, ncand);
 }
 

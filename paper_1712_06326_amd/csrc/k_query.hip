@@ -548,9 +548,13 @@ __global__ __launch_bounds__(64) void knn_kernel(KnnArgs A) {
         for (int d = 0; d < MD; d++)
             if (d < D) single = single && lo[d] == hi[d];
         if ((int64_t)(f.z - f.a) <= A.mu || single) {
-            for (int64_t base = f.a; base < f.z; base += 64) {
+            // entries of one cell share their distance and are in id order
+            // (the curve is sorted by (key, id)), so only the first k of a
+            // one-cell region can rank among the k smallest
+            const int64_t zend = single ? min((int64_t)f.z, (int64_t)f.a + k) : (int64_t)f.z;
+            for (int64_t base = f.a; base < zend; base += 64) {
                 const int64_t i = base + lane;
-                const bool live = i < f.z;
+                const bool live = i < zend;
                 int64_t dist = 0;
                 uint32_t id = 0;
                 if (live) {
