@@ -302,6 +302,28 @@ sfc_status sfc_index_export(const sfc_index *idx, int32_t subset, int32_t curve,
 /* Release the handle and its device memory. NULL is a no-op. */
 void sfc_index_free(sfc_index *idx);
 
+/* Saved indices, for dictionaries used again (the paper precomputes and
+ * stores its indices; Sections III and IV). sfc_index_save writes to the
+ * host file `path` what defines an SFC index handle: a header (geometry,
+ * K, reduced_dim, n_curves, key_bits, curve, window, dictionary size, a
+ * hash of the dictionary ids and a checksum of the known voxels' byte
+ * codes), the subsample statistics, the int8 bases and the grid origin and
+ * span of every subset (a few KiB). sfc_index_load makes a handle from such
+ * a file for the same volume and mask (borrowed and copied as in
+ * sfc_index_build): the dictionary and byte codes are rebuilt and must
+ * match the file's (size, hash, quantisation, checksum); the statistics and
+ * bases are read, the curves rebuilt from them (projection, keys, sort: on
+ * the GPU that is faster than reading sorted curves from host storage) and
+ * the rebuilt grid must equal the saved one. reduced_dim, n_curves,
+ * key_bits, curve and window come from the file, the other options from
+ * `opt`. The loaded handle answers every query exactly as the saved one.
+ * SFC_EINVAL: null pointer, a dictionary-only handle, an unreadable,
+ * truncated or inconsistent file, or one made for another geometry, K,
+ * volume or mask. */
+sfc_status sfc_index_save(const sfc_index *idx, const char *path);
+sfc_status sfc_index_load(const float *volume, const uint8_t *mask, const sfc_geometry *g,
+                          int32_t K, const sfc_options *opt, const char *path, sfc_index **out);
+
 /* The sort that orders every curve of an index (Section II.C: a curve's
  * entries by curve position), on caller arrays: each of `arrays`
  * consecutive arrays of n (key, id) pairs is sorted in place by key

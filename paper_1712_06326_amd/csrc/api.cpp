@@ -365,6 +365,176 @@ sfc_status sfc_index_build_with_basis(const float* volume, const uint8_t* mask,
     return SFC_OK;
 }
 
+// ---- saved indices (reuse of an index built once; Section III's
+// precomputed indices for dictionaries used again)
+extern "C++" {
+namespace {
+struct IndexFileHeader {
+    char magic[8];        // "SFCINDEX"
+    uint32_t version;     // 1
+    int32_t nd, C, K, D, L, b, curve, window, W64, S, mmax, pad[2];
+    int64_t shape[3], n, nsub, R;
+    float vmin, qscale;
+    uint64_t dict_hash;   // FNV-1a over the dictionary ids
+    uint64_t code_hash;   // checksum of the known voxels' byte codes
+};
+static_assert(sizeof(IndexFileHeader) == 136, "index file header has no implicit padding");
+constexpr char kIndexMagic[8] = {'S', 'F', 'C', 'I', 'N', 'D', 'E', 'X'};
+
+uint64_t fnv1a(const std::vector<uint32_t>& v) {
+    uint64_t h = 1469598103934665603ull;
+    for (uint32_t x : v)
+        for (int k = 0; k < 4; k++) {
+            h ^= (x >> (8 * k)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    return h;
+}
+
+template <typename T>
+sfc_status fetch(std::vector<T>& h, const void* d, size_t count, hipStream_t st) {
+    h.resize(count);
+    if (count) {
+        hipError_t e = hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return check_hip(e, "index copy to the host");
+    }
+    return SFC_OK;
+}
+
+struct File {
+    FILE* f = nullptr;
+    ~File() {
+        if (f) std::fclose(f);
+    }
+};
+
+template <typename T>
+bool put(FILE* f, const std::vector<T>& v) {
+    return v.empty() || std::fwrite(v.data(), sizeof(T), v.size(), f) == v.size();
+}
+template <typename T>
+bool get(FILE* f, std::vector<T>& v, size_t count) {
+    v.resize(count);
+    return count == 0 || std::fread(v.data(), sizeof(T), count, f) == count;
+}
+}  // namespace
+}  // extern "C++"
+
+sfc_status sfc_index_save(const sfc_index* ix, const char* path) {
+    clear_error();
+    if (!ix || !path) return fail(SFC_EINVAL, "sfc_index_save: null pointer");
+    if (!ix->has_sfc) return fail(SFC_EINVAL, "sfc_index_save: a dictionary-only handle has no index");
+    const Grid& g = ix->g;
+    const size_t P = (size_t)g.Kd * g.C, S = ix->S, n = (size_t)ix->n;
+    IndexFileHeader h{};
+    std::memcpy(h.magic, kIndexMagic, 8);
+    h.version = 1;
+    h.nd = g.nd;
+    h.C = g.C;
+    h.K = g.K;
+    h.D = ix->D;
+    h.L = ix->L;
+    h.b = ix->b;
+    h.curve = ix->opt.curve;
+    h.window = ix->opt.window;
+    h.W64 = ix->W64;
+    h.S = ix->S;
+    h.mmax = ix->mmax;
+    for (int i = 0; i < g.nd; i++) h.shape[i] = g.shape[i];
+    h.n = ix->n;
+    h.nsub = ix->nsub;
+    h.R = ix->R;
+    h.vmin = ix->vmin;
+    h.qscale = ix->qscale;
+    std::vector<uint64_t> sum;
+    std::vector<int8_t> basis;
+    std::vector<int64_t> lo, span;
+    std::vector<uint32_t> dict;
+    hipStream_t st = ix->st;
+    SFC_TRY(fetch(sum, ix->sum, P, st));
+    SFC_TRY(fetch(basis, ix->basis, S * ix->mmax * ix->D, st));
+    SFC_TRY(fetch(lo, ix->lo, S * ix->D, st));
+    SFC_TRY(fetch(span, ix->span, S, st));
+    SFC_TRY(fetch(dict, ix->dict, n, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    h.dict_hash = fnv1a(dict);
+    SFC_TRY(code_checksum(const_cast<sfc_index*>(ix), &h.code_hash));
+    File file;
+    file.f = std::fopen(path, "wb");
+    if (!file.f) return fail(SFC_EINVAL, std::string("sfc_index_save: cannot open ") + path);
+    const bool ok = std::fwrite(&h, sizeof(h), 1, file.f) == 1 && put(file.f, sum) &&
+                    put(file.f, basis) && put(file.f, lo) && put(file.f, span);
+    const bool closed = std::fclose(file.f) == 0;
+    file.f = nullptr;
+    if (!ok || !closed) return fail(SFC_EINVAL, std::string("sfc_index_save: write failed: ") + path);
+    return SFC_OK;
+}
+
+sfc_status sfc_index_load(const float* volume, const uint8_t* mask, const sfc_geometry* g,
+                          int32_t K, const sfc_options* opt, const char* path, sfc_index** out) {
+    clear_error();
+    if (!out || !path) return fail(SFC_EINVAL, "sfc_index_load: null pointer");
+    *out = nullptr;
+    SFC_TRY(check_geometry(g, K));
+    File file;
+    file.f = std::fopen(path, "rb");
+    if (!file.f) return fail(SFC_EINVAL, std::string("sfc_index_load: cannot open ") + path);
+    IndexFileHeader h{};
+    if (std::fread(&h, sizeof(h), 1, file.f) != 1 || std::memcmp(h.magic, kIndexMagic, 8) != 0 ||
+        h.version != 1)
+        return fail(SFC_EINVAL, "sfc_index_load: not an index file of this version");
+    bool same = h.nd == g->ndim && h.C == g->channels && h.K == K;
+    for (int i = 0; same && i < g->ndim; i++) same = h.shape[i] == g->shape[i];
+    if (!same) return fail(SFC_EINVAL, "sfc_index_load: the file was saved for another geometry or K");
+    sfc_options o = resolve_options(opt);
+    o.key_bits = h.b;
+    o.curve = h.curve;
+    o.window = h.window;
+    SFC_TRY(validate_options(o));
+    SFC_TRY(check_sfc_args(g, K, h.D, h.L, o));
+    if (h.n < 1 || h.S < 1 || h.mmax < 1 || h.W64 != (h.D * h.b + 63) / 64)
+        return fail(SFC_EINVAL, "sfc_index_load: inconsistent header");
+    SavedIndex sv;
+    sv.nsub = h.nsub;
+    sv.vmin = h.vmin;
+    sv.qscale = h.qscale;
+    const size_t P = (size_t)h.C;
+    size_t Kd = 1;
+    for (int i = 0; i < h.nd; i++) Kd *= (size_t)K;
+    const size_t S = h.S, n = (size_t)h.n;
+    const bool ok = get(file.f, sv.sum, Kd * P) && get(file.f, sv.basis, S * h.mmax * h.D) &&
+                    get(file.f, sv.lo, S * h.D) && get(file.f, sv.span, S);
+    if (!ok) return fail(SFC_EINVAL, "sfc_index_load: the file is truncated");
+    if (std::fgetc(file.f) != EOF) return fail(SFC_EINVAL, "sfc_index_load: data after the index");
+    sfc_index* ix = nullptr;
+    SFC_TRY(new_handle(volume, mask, g, K, &o, &ix));
+    sfc_status s = SFC_OK;
+    if (ix->n != h.n) s = fail(SFC_EINVAL, "index file was made from another volume or mask");
+    if (s == SFC_OK) {
+        std::vector<uint32_t> dict;
+        s = fetch(dict, ix->dict, n, ix->st);
+        if (s == SFC_OK) {
+            hipError_t e = hipStreamSynchronize(ix->st);
+            if (e != hipSuccess) s = check_hip(e, "dictionary copy");
+        }
+        if (s == SFC_OK && fnv1a(dict) != h.dict_hash)
+            s = fail(SFC_EINVAL, "index file was made from another volume or mask");
+    }
+    uint64_t codes = 0;
+    if (s == SFC_OK) s = code_checksum(ix, &codes);
+    if (s == SFC_OK && codes != h.code_hash)
+        s = fail(SFC_EINVAL, "index file was made from another volume or mask");
+    if (s == SFC_OK) s = build_sfc(ix, mask, h.D, h.L, nullptr, &sv);
+    if (s == SFC_OK && (ix->W64 != h.W64 || ix->R != h.R || ix->S != h.S || ix->mmax != h.mmax))
+        s = fail(SFC_EINVAL, "sfc_index_load: the file does not match this build's index layout");
+    if (s != SFC_OK) {
+        delete ix;
+        return s;
+    }
+    *out = ix;
+    return SFC_OK;
+}
+
 void sfc_index_free(sfc_index* idx) { delete idx; }
 
 sfc_status sfc_index_info_get(const sfc_index* ix, sfc_index_info* info) {

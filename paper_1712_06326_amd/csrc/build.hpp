@@ -10,6 +10,10 @@ namespace sfc {
 // params: float[3] = {vmin, scale, vmax} on the device
 sfc_status launch_quantize(const float* vol, const uint8_t* mask, const Grid& g, uint8_t* xq,
                            float* params, uint32_t* tmp2, hipStream_t st);
+// Order-free u64 checksum of the byte codes of the known voxels into *out
+// (device), which it clears first.
+sfc_status launch_code_checksum(const uint8_t* xq, const uint8_t* mask, int64_t nvox, int C,
+                                uint64_t* out, hipStream_t st);
 
 // ---- covariance sums over the strided subsample of dictionary ranks
 // elem_off[e] = (voxel offset of pixel e/C) * C + e%C relative to centre*C

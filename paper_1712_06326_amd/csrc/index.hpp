@@ -99,8 +99,23 @@ namespace sfc {
 sfc_status ensure_quantized(sfc_index* ix, const uint8_t* mask);
 sfc_status ensure_elem_offsets(sfc_index* ix);
 sfc_status check_sfc_args(const sfc_geometry* g, int K, int D, int L, const sfc_options& o);
-sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int8_t* bases_host);
+// What defines a saved index (host copies, in the device layouts); its
+// curves follow from these and the dictionary.
+struct SavedIndex {
+    int64_t nsub = 0;
+    float vmin = 0.0f, qscale = 0.0f;
+    std::vector<uint64_t> sum;     // [P]
+    std::vector<int8_t> basis;     // [S][mmax][D]
+    std::vector<int64_t> lo;       // [S][D]
+    std::vector<int64_t> span;     // [S]
+};
+// saved: the statistics and bases of a saved index instead of computing
+// them (bases_host unused); its grid must come out the same
+sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int8_t* bases_host,
+                     const SavedIndex* saved = nullptr);
 void release_sfc(sfc_index* ix);
+// checksum of the byte codes of the known voxels (quantises first if needed)
+sfc_status code_checksum(sfc_index* ix, uint64_t* out_host);
 sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                             uint64_t* best_dev);
 sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,

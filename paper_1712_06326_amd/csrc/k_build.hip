@@ -72,6 +72,36 @@ __global__ void quantize_kernel(const float* __restrict__ vol, int64_t n,
     xq[i] = (uint8_t)r;
 }
 
+// Order-free checksum of the byte codes of the known voxels: the sum, mod
+// 2^64, of (code + 1) times a mixed hash of the element's position.
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+__global__ __launch_bounds__(256) void code_checksum_kernel(const uint8_t* __restrict__ xq,
+                                                            const uint8_t* __restrict__ mask,
+                                                            int64_t nvox, int C,
+                                                            unsigned long long* __restrict__ out) {
+    unsigned long long acc = 0ull;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (!mask[v]) continue;
+        for (int ch = 0; ch < C; ch++) {
+            unsigned long long z = (unsigned long long)(v * C + ch) + 0x9e3779b97f4a7c15ull;
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+            z ^= z >> 31;
+            acc += z * (unsigned long long)(xq[v * C + ch] + 1u);
+        }
+    }
+    __shared__ unsigned long long part[256];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, part[0]);
+}
+
 // ------------------------------------------------------------ covariance
 // Xt[e][s4] packs the bytes of samples 4*s4 .. 4*s4+3 of element e.
 __global__ void gather_samples_kernel(const uint8_t* __restrict__ xq,
@@ -588,6 +618,16 @@ sfc_status launch_quantize(const float* vol, const uint8_t* mask, const Grid& g,
     const int64_t n = g.nvox * g.C;
     quantize_kernel<<<blocks_for(n), 256, 0, st>>>(vol, n, params, xq);
     return launched("quantize_kernel");
+}
+
+sfc_status launch_code_checksum(const uint8_t* xq, const uint8_t* mask, int64_t nvox, int C,
+                                uint64_t* out, hipStream_t st) {
+    auto* o = reinterpret_cast<unsigned long long*>(out);
+    zero_u64_kernel<<<1, 1, 0, st>>>(o);
+    SFC_TRY(launched("zero_u64_kernel"));
+    const unsigned nb = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (nvox + 255) / 256));
+    code_checksum_kernel<<<nb, 256, 0, st>>>(xq, mask, nvox, C, o);
+    return launched("code_checksum_kernel");
 }
 
 sfc_status launch_gather_samples(const uint8_t* xq, const uint32_t* dict, int64_t stride,

@@ -234,6 +234,20 @@ sfc_status ensure_quantized(sfc_index* ix, const uint8_t* mask) {
     return SFC_OK;
 }
 
+sfc_status code_checksum(sfc_index* ix, uint64_t* out_host) {
+    SFC_TRY(ensure_quantized(ix, ix->mask_copy));
+    uint64_t* d = nullptr;
+    SFC_TRY(dev_alloc((void**)&d, sizeof(uint64_t), "checksum"));
+    sfc_status s = launch_code_checksum(ix->xq, ix->mask_copy, ix->g.nvox, ix->g.C, d, ix->st);
+    if (s == SFC_OK) {
+        hipError_t e = hipMemcpyAsync(out_host, d, sizeof(uint64_t), hipMemcpyDeviceToHost, ix->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(ix->st);
+        if (e != hipSuccess) s = check_hip(e, "checksum");
+    }
+    dev_free(d);
+    return s;
+}
+
 sfc_status ensure_elem_offsets(sfc_index* ix) {
     if (ix->elem_off) return SFC_OK;
     const Grid& g = ix->g;
@@ -259,7 +273,48 @@ void release_sfc(sfc_index* ix) {
     ix->ids = nullptr;
 }
 
-sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int8_t* bases_host) {
+// W^T W of every basis (the query's least-squares imputation) and the bf16
+// projection weights, from the int8 bases already on the device.
+sfc_status basis_products(sfc_index* ix, hipStream_t st) {
+    const int S = ix->S, D = ix->D, mmax = ix->mmax, Pp = ix->Pp;
+    SFC_TRY(dev_alloc((void**)&ix->wtw, (size_t)S * D * D * 8, "basis gram"));
+    wtw_kernel<<<(S * D * D + 255) / 256, 256, 0, st>>>(ix->basis, ix->msz, S, mmax, D, ix->wtw);
+    SFC_HIP(hipGetLastError());
+
+    // projection weights (bf16)
+    const int ncols = S * D;
+    const int nt = proj_tiles(ncols);
+    if (nt > 16) return fail(SFC_EUNSUPPORTED, "subsets * reduced_dim above 512");
+    const size_t wbytes = (size_t)nt * 32 * Pp * 2;
+    SFC_TRY(dev_alloc(&ix->proj_w, wbytes, "projection weights"));
+    SFC_TRY(zero(ix->proj_w, wbytes, st));
+    SFC_TRY(launch_weights(ix->basis, ix->elems, ix->msz, S, mmax, D, Pp,
+                           static_cast<uint16_t*>(ix->proj_w), st));
+    return SFC_OK;
+}
+
+// Host copies of the small parameters; marks the handle as an SFC index.
+sfc_status finish_sfc(sfc_index* ix, hipStream_t st) {
+    const int S = ix->S, D = ix->D, mmax = ix->mmax;
+    ix->h_basis.assign((size_t)S * mmax * D, 0);
+    ix->h_lo.assign((size_t)S * D, 0);
+    ix->h_span.assign(S, 0);
+    float qp[2];
+    SFC_HIP(hipMemcpyAsync(ix->h_basis.data(), ix->basis, ix->h_basis.size(), hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipMemcpyAsync(ix->h_lo.data(), ix->lo, ix->h_lo.size() * 8, hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipMemcpyAsync(ix->h_span.data(), ix->span, ix->h_span.size() * 8, hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipMemcpyAsync(qp, ix->qparams, sizeof(qp), hipMemcpyDeviceToHost, st));
+    SFC_HIP(hipStreamSynchronize(st));
+    ix->vmin = qp[0];
+    ix->qscale = qp[1];
+    ix->has_sfc = true;
+    return SFC_OK;
+}
+
+sfc_status curves_from_basis(sfc_index* ix, hipStream_t st);
+
+sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int8_t* bases_host,
+                     const SavedIndex* saved) {
     const Grid& g = ix->g;
     hipStream_t st = ix->st;
     const int C = g.C, P = g.Kd * C;
@@ -301,60 +356,83 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
 
     // byte quantisation
     SFC_TRY(ensure_quantized(ix, mask));
-    Temp tmp;
+    if (saved) {
+        // a saved index: its statistics and bases, after checking that the
+        // rebuilt quantisation and subsample are the ones they came from
+        const int64_t stride = std::max<int64_t>(1, (ix->n + (1 << 20) - 1) >> 20);
+        const int64_t nsub = (ix->n + stride - 1) / stride;
+        if (saved->nsub != nsub || ix->vmin != saved->vmin || ix->qscale != saved->qscale)
+            return fail(SFC_EINVAL, "index file was made from another volume or mask");
+        if (saved->sum.size() != (size_t)P || saved->basis.size() != (size_t)S * mmax * D ||
+            saved->lo.size() != (size_t)S * D || saved->span.size() != (size_t)S)
+            return fail(SFC_EINVAL, "index file: array sizes do not match its header");
+        ix->nsub = nsub;
+        SFC_TRY(upload(reinterpret_cast<uint64_t**>(&ix->sum), saved->sum, "sample sums", st));
+        SFC_TRY(upload(&ix->basis, saved->basis, "bases", st));
+        SFC_TRY(curves_from_basis(ix, st));
+        if (ix->h_lo != saved->lo || ix->h_span != saved->span)
+            return fail(SFC_EINVAL, "index file: its grid does not match the rebuilt projections");
+        return SFC_OK;
+    }
+    {
+        // the statistics and the eigensolver's matrices are freed before
+        // the curves are built
+        Temp tmp;
 
-    // integer statistics over the strided subsample
-    const int64_t stride = (ix->n + (1 << 20) - 1) >> 20;
-    const int64_t st1 = stride < 1 ? 1 : stride;
-    ix->nsub = (ix->n + st1 - 1) / st1;
-    const int64_t nsp4 = (ix->nsub + 3) / 4;
-    uint32_t* Xt = nullptr;
-    uint64_t* gram = nullptr;
-    SFC_TRY(tmp.alloc((void**)&Xt, (size_t)P * nsp4 * 4, "sample matrix"));
-    SFC_TRY(dev_alloc((void**)&ix->sum, (size_t)P * 8, "sample sums"));
-    SFC_TRY(tmp.alloc((void**)&gram, (size_t)P * P * 8, "gram matrix"));
-    SFC_TRY(zero(gram, (size_t)P * P * 8, st));
-    SFC_TRY(launch_gather_samples(ix->xq, ix->dict, st1, ix->nsub, ix->elem_off, P, C, Xt, nsp4, st));
-    SFC_TRY(launch_gram(Xt, P, nsp4, reinterpret_cast<uint64_t*>(ix->sum), gram, st));
+        // integer statistics over the strided subsample
+        const int64_t stride = (ix->n + (1 << 20) - 1) >> 20;
+        const int64_t st1 = stride < 1 ? 1 : stride;
+        ix->nsub = (ix->n + st1 - 1) / st1;
+        const int64_t nsp4 = (ix->nsub + 3) / 4;
+        uint32_t* Xt = nullptr;
+        uint64_t* gram = nullptr;
+        SFC_TRY(tmp.alloc((void**)&Xt, (size_t)P * nsp4 * 4, "sample matrix"));
+        SFC_TRY(dev_alloc((void**)&ix->sum, (size_t)P * 8, "sample sums"));
+        SFC_TRY(tmp.alloc((void**)&gram, (size_t)P * P * 8, "gram matrix"));
+        SFC_TRY(zero(gram, (size_t)P * P * 8, st));
+        SFC_TRY(launch_gather_samples(ix->xq, ix->dict, st1, ix->nsub, ix->elem_off, P, C, Xt, nsp4, st));
+        SFC_TRY(launch_gram(Xt, P, nsp4, reinterpret_cast<uint64_t*>(ix->sum), gram, st));
 
-    // basis per subset
-    SFC_TRY(dev_alloc((void**)&ix->basis, (size_t)S * mmax * D, "bases"));
-    if (!bases_host) {
-        double *A = nullptr, *V = nullptr;
-        void* B = nullptr;
-        int32_t* sweeps = nullptr;
-        const size_t mat = (size_t)S * mmax * mmax * sizeof(double);
-        SFC_TRY(tmp.alloc((void**)&A, mat, "covariance matrices"));
-        SFC_TRY(tmp.alloc((void**)&V, mat, "eigenvectors"));
-        SFC_TRY(tmp.alloc(&B, jacobi_scratch_bytes(S, mmax), "eigensolver scratch"));
-        SFC_TRY(tmp.alloc((void**)&sweeps, S * sizeof(int32_t), "sweep counts"));
-        SFC_TRY(launch_cov_matrix(reinterpret_cast<uint64_t*>(ix->sum), gram, ix->nsub, P,
-                                  ix->elems, ix->msz, S, mmax, A, st));
-        SFC_TRY(launch_jacobi(A, V, B, ix->msz, S, mmax, sweeps, st));
-        SFC_TRY(launch_basis(A, V, ix->msz, S, mmax, D, ix->basis, st));
-    } else {
-        std::vector<int8_t> hb((size_t)S * mmax * D, 0);
-        size_t off = 0;
-        for (int s = 0; s < S; s++) {
-            std::memcpy(&hb[(size_t)s * mmax * D], bases_host + off, (size_t)msz[s] * D);
-            off += (size_t)msz[s] * D;
+        // basis per subset
+        SFC_TRY(dev_alloc((void**)&ix->basis, (size_t)S * mmax * D, "bases"));
+        if (!bases_host) {
+            double *A = nullptr, *V = nullptr;
+            void* B = nullptr;
+            int32_t* sweeps = nullptr;
+            const size_t mat = (size_t)S * mmax * mmax * sizeof(double);
+            SFC_TRY(tmp.alloc((void**)&A, mat, "covariance matrices"));
+            SFC_TRY(tmp.alloc((void**)&V, mat, "eigenvectors"));
+            SFC_TRY(tmp.alloc(&B, jacobi_scratch_bytes(S, mmax), "eigensolver scratch"));
+            SFC_TRY(tmp.alloc((void**)&sweeps, S * sizeof(int32_t), "sweep counts"));
+            SFC_TRY(launch_cov_matrix(reinterpret_cast<uint64_t*>(ix->sum), gram, ix->nsub, P,
+                                      ix->elems, ix->msz, S, mmax, A, st));
+            SFC_TRY(launch_jacobi(A, V, B, ix->msz, S, mmax, sweeps, st));
+            SFC_TRY(launch_basis(A, V, ix->msz, S, mmax, D, ix->basis, st));
+        } else {
+            std::vector<int8_t> hb((size_t)S * mmax * D, 0);
+            size_t off = 0;
+            for (int s = 0; s < S; s++) {
+                std::memcpy(&hb[(size_t)s * mmax * D], bases_host + off, (size_t)msz[s] * D);
+                off += (size_t)msz[s] * D;
+            }
+            SFC_HIP(hipMemcpyAsync(ix->basis, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
+            SFC_HIP(hipStreamSynchronize(st));
         }
-        SFC_HIP(hipMemcpyAsync(ix->basis, hb.data(), hb.size(), hipMemcpyHostToDevice, st));
         SFC_HIP(hipStreamSynchronize(st));
     }
-    SFC_TRY(dev_alloc((void**)&ix->wtw, (size_t)S * D * D * 8, "basis gram"));
-    wtw_kernel<<<(S * D * D + 255) / 256, 256, 0, st>>>(ix->basis, ix->msz, S, mmax, D, ix->wtw);
-    SFC_HIP(hipGetLastError());
+    return curves_from_basis(ix, st);
+}
 
-    // projection weights (bf16) and the projection itself
+// Everything that follows from the bases: projection weights, principal
+// coordinates of every dictionary patch, grid origin and span, keys of
+// every (subset, curve), the sort.
+sfc_status curves_from_basis(sfc_index* ix, hipStream_t st) {
+    const Grid& g = ix->g;
+    const int C = g.C, P = g.Kd * C, Pp = ix->Pp;
+    const int S = ix->S, D = ix->D, L = ix->L;
+    Temp tmp;
+    SFC_TRY(basis_products(ix, st));
     const int ncols = S * D;
-    const int nt = proj_tiles(ncols);
-    if (nt > 16) return fail(SFC_EUNSUPPORTED, "subsets * reduced_dim above 512");
-    const size_t wbytes = (size_t)nt * 32 * Pp * 2;
-    SFC_TRY(dev_alloc(&ix->proj_w, wbytes, "projection weights"));
-    SFC_TRY(zero(ix->proj_w, wbytes, st));
-    SFC_TRY(launch_weights(ix->basis, ix->elems, ix->msz, S, mmax, D, Pp,
-                           static_cast<uint16_t*>(ix->proj_w), st));
     int32_t *cmin = nullptr, *cmax = nullptr;
     SFC_TRY(tmp.alloc((void**)&cmin, ncols * 4, "column minima"));
     SFC_TRY(tmp.alloc((void**)&cmax, ncols * 4, "column maxima"));
@@ -422,20 +500,7 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
     // sort every (subset, curve) by (key, id)
     SFC_TRY(sort_key_arrays(ix->keys, ix->ids, ix->n, ix->W64, S * L, D * ix->b, st));
 
-    // host copies of the small parameters
-    ix->h_basis.assign((size_t)S * mmax * D, 0);
-    ix->h_lo.assign((size_t)S * D, 0);
-    ix->h_span.assign(S, 0);
-    float qp[2];
-    SFC_HIP(hipMemcpyAsync(ix->h_basis.data(), ix->basis, ix->h_basis.size(), hipMemcpyDeviceToHost, st));
-    SFC_HIP(hipMemcpyAsync(ix->h_lo.data(), ix->lo, ix->h_lo.size() * 8, hipMemcpyDeviceToHost, st));
-    SFC_HIP(hipMemcpyAsync(ix->h_span.data(), ix->span, ix->h_span.size() * 8, hipMemcpyDeviceToHost, st));
-    SFC_HIP(hipMemcpyAsync(qp, ix->qparams, sizeof(qp), hipMemcpyDeviceToHost, st));
-    SFC_HIP(hipStreamSynchronize(st));
-    ix->vmin = qp[0];
-    ix->qscale = qp[1];
-    ix->has_sfc = true;
-    return SFC_OK;
+    return finish_sfc(ix, st);
 }
 
 sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int64_t* best_id,

@@ -95,6 +95,9 @@ _SIG = {
     "sfc_index_projection": (ST, [P, I32, P]),
     "sfc_index_export": (ST, [P, I32, I32, P, P]),
     "sfc_index_free": (None, [P]),
+    "sfc_index_save": (ST, [P, C.c_char_p]),
+    "sfc_index_load": (ST, [P, P, C.POINTER(Geometry), I32, C.POINTER(Options), C.c_char_p,
+                            C.POINTER(P)]),
     "sfc_sort_pairs": (ST, [P, P, I64, I32, I32, P]),
     "sfc_batch_create": (ST, [I32, P, P, P, I32, C.POINTER(Options), C.POINTER(P)]),
     "sfc_batch_query": (ST, [P, P, P, P, P, P]),
@@ -226,6 +229,22 @@ class Index:
                 _ptr(volume), _ptr(mask), C.byref(g), K, reduced_dim, n_curves,
                 C.byref(self._opts), flat.ctypes.data_as(C.c_void_p), C.byref(h)))
         self._h = h
+
+    @classmethod
+    def load(cls, volume: torch.Tensor, mask: torch.Tensor, K: int, path: str, **opts):
+        """A handle from a file written by save() for the same volume and mask."""
+        self = cls.__new__(cls)
+        self.volume, self.mask, self.K = volume, mask, K
+        self._opts = options(**opts)
+        g = geometry(mask, volume.shape[-1])
+        h = C.c_void_p()
+        _check(_L.sfc_index_load(_ptr(volume), _ptr(mask), C.byref(g), K, C.byref(self._opts),
+                                 str(path).encode(), C.byref(h)))
+        self._h = h
+        return self
+
+    def save(self, path: str) -> None:
+        _check(_L.sfc_index_save(self._h, str(path).encode()))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -3,6 +3,7 @@ declares (CPU only: no compute calls)."""
 import ctypes
 import os
 import re
+import struct
 
 import pytest
 
@@ -80,3 +81,60 @@ def test_sort_pairs_argument_errors():
     # n <= 1 is a no-op that touches nothing
     assert f(p, p, 1, 3, 2, None) == 0
     assert f(p, p, 0, 3, 2, None) == 0
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("channels", ctypes.c_int32),
+                ("shape", ctypes.c_int64 * 3)]
+
+
+def _index_header(magic=b"SFCINDEX", nd=2, C=1, K=5, D=4, L=2, b=16, shape=(40, 44, 0), n=100):
+    # the header sfc_index_save writes: magic, version, 13 int32 (the last two
+    # zero), 6 int64, 2 float, 2 uint64 (136 bytes, no padding)
+    W64 = (D * b + 63) // 64
+    ints = (nd, C, K, D, L, b, 0, 16, W64, 5, 10, 0, 0)
+    return struct.pack("<8sI13i6q2f2Q", magic, 1, *ints, *shape, n, n, 1 << (b - 1),
+                       0.0, 1.0, 0, 0)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_index_file_errors(tmp_path):
+    """File and header errors of sfc_index_load are reported before any device
+    work; so are sfc_index_save's argument errors."""
+    lib = ctypes.CDLL(LIB)
+    lib.sfc_last_error.restype = ctypes.c_char_p
+    load = lib.sfc_index_load
+    load.restype = ctypes.c_int
+    load.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Geometry), ctypes.c_int32,
+                     ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+    save = lib.sfc_index_save
+    save.restype = ctypes.c_int
+    save.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    assert len(_index_header()) == 136
+    assert save(None, b"x") == -1
+    g = _Geometry(2, 1, (ctypes.c_int64 * 3)(40, 44, 0))
+    out = ctypes.c_void_p()
+    p = ctypes.c_void_p(16)   # never dereferenced: every case fails before device work
+
+    def run(data, K=5, geo=g):
+        f = tmp_path / "i.sfc"
+        f.write_bytes(data)
+        rc = load(p, p, ctypes.byref(geo), K, None, str(f).encode(), ctypes.byref(out))
+        assert rc == -1 and out.value is None
+        return lib.sfc_last_error()
+
+    assert load(p, p, ctypes.byref(g), 5, None, None, ctypes.byref(out)) == -1
+    assert load(p, p, ctypes.byref(g), 5, None, str(tmp_path / "none").encode(),
+                ctypes.byref(out)) == -1
+    assert b"cannot open" in lib.sfc_last_error()
+    assert b"not an index file" in run(b"")
+    assert b"not an index file" in run(_index_header(magic=b"SFCINDEY"))
+    assert b"another geometry" in run(_index_header(), K=7)
+    assert b"another geometry" in run(_index_header(shape=(40, 45, 0)))
+    assert b"another geometry" in run(_index_header(C=3))
+    assert b"inconsistent" in run(_index_header(n=0))
+    assert b"reduced_dim" in run(_index_header(D=30))
+    assert b"truncated" in run(_index_header())
+    # sums 25 * 8, bases 5 * 10 * 4, grid 5 * 4 * 8 + 5 * 8 bytes
+    assert b"truncated" in run(_index_header() + b"\0" * 599)
+    assert b"data after" in run(_index_header() + b"\0" * 601)
