@@ -157,8 +157,8 @@ sfc_status sfc_dictionary_build(const float *volume, const uint8_t *mask,
  * as sfc_dictionary_build. Errors: SFC_EINVAL for K even, K > a side,
  * reduced_dim < 1 or > a subset's element count, n_curves < 1 or >
  * reduced_dim + 1, key_bits * reduced_dim > 256; SFC_EUNSUPPORTED for a
- * subset with more than 518 elements (the exact-integer bound of the bf16
- * projection) or more than 2^32 voxels. */
+ * subset with more than 518 elements (the eigensolver's bound) or more
+ * than 2^32 voxels. */
 sfc_status sfc_index_build(const float *volume, const uint8_t *mask, const sfc_geometry *g,
                            int32_t K, int32_t reduced_dim, int32_t n_curves,
                            const sfc_options *opt, sfc_index **out);

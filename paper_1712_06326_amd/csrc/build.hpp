@@ -7,9 +7,11 @@
 namespace sfc {
 
 // ---- byte quantisation (vmin/vmax over known voxels, FP32 scale)
-// params: float[3] = {vmin, scale, vmax} on the device
+// params: float[3] = {vmin, scale, vmax} on the device; part: device
+// scratch of 2 * kQuantBlocks uint32 (per-block partial ranges)
+constexpr int kQuantBlocks = 1024;
 sfc_status launch_quantize(const float* vol, const uint8_t* mask, const Grid& g, uint8_t* xq,
-                           float* params, uint32_t* tmp2, hipStream_t st);
+                           float* params, uint32_t* part, hipStream_t st);
 // Order-free u64 checksum of the byte codes of the known voxels into *out
 // (device), which it clears first.
 sfc_status launch_code_checksum(const uint8_t* xq, const uint8_t* mask, int64_t nvox, int C,

@@ -25,13 +25,32 @@ __device__ inline float fdec(uint32_t e) {
     return __uint_as_float((e & 0x80000000u) ? (e & 0x7fffffffu) : ~e);
 }
 
-__global__ void minmax_init_kernel(uint32_t* mm) {
-    mm[0] = 0xffffffffu;
-    mm[1] = 0u;
+// min / max of the ordered encodings over a 256-thread block (results in
+// thread 0)
+__device__ inline void block_minmax(uint32_t& lo, uint32_t& hi) {
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+    }
+    __shared__ uint32_t wl[4], wh[4];
+    if ((threadIdx.x & 63) == 0) {
+        wl[threadIdx.x >> 6] = lo;
+        wh[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < 4; w++) {
+            lo = min(lo, wl[w]);
+            hi = max(hi, wh[w]);
+        }
 }
 
-__global__ void minmax_kernel(const float* __restrict__ vol, const uint8_t* __restrict__ mask,
-                              int64_t nvox, int C, uint32_t* __restrict__ mm) {
+// per-block partial range of the known voxels: part[2b] = min, part[2b+1] =
+// max of the ordered encodings (identity values for a block with none)
+__global__ __launch_bounds__(256) void minmax_kernel(const float* __restrict__ vol,
+                                                     const uint8_t* __restrict__ mask,
+                                                     int64_t nvox, int C,
+                                                     uint32_t* __restrict__ part) {
     uint32_t lo = 0xffffffffu, hi = 0u;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -42,23 +61,29 @@ __global__ void minmax_kernel(const float* __restrict__ vol, const uint8_t* __re
             hi = max(hi, e);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMin(&mm[0], lo);
-        atomicMax(&mm[1], hi);
+    block_minmax(lo, hi);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = lo;
+        part[2 * blockIdx.x + 1] = hi;
     }
 }
 
 // params = {vmin, scale = 255 / (vmax - vmin) in float32 (0 when the range is
-// empty), vmax}
-__global__ void scale_kernel(const uint32_t* __restrict__ mm, float* __restrict__ params) {
-    const float lo = fdec(mm[0]), hi = fdec(mm[1]);
-    params[0] = lo;
-    params[1] = (hi > lo) ? 255.0f / (hi - lo) : 0.0f;
-    params[2] = hi;
+// empty), vmax}, from the nb partial ranges (one 256-thread block)
+__global__ __launch_bounds__(256) void scale_kernel(const uint32_t* __restrict__ part, int nb,
+                                                    float* __restrict__ params) {
+    uint32_t lo = 0xffffffffu, hi = 0u;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        lo = min(lo, part[2 * b]);
+        hi = max(hi, part[2 * b + 1]);
+    }
+    block_minmax(lo, hi);
+    if (threadIdx.x == 0) {
+        const float vlo = fdec(lo), vhi = fdec(hi);
+        params[0] = vlo;
+        params[1] = (vhi > vlo) ? 255.0f / (vhi - vlo) : 0.0f;
+        params[2] = vhi;
+    }
 }
 
 __global__ void quantize_kernel(const float* __restrict__ vol, int64_t n,
@@ -124,23 +149,28 @@ __global__ void gather_samples_kernel(const uint8_t* __restrict__ xq,
     Xt[i] = w;
 }
 
-// sum[e] = sum of all sample bytes of element e (one block per element)
-__global__ void sample_sum_kernel(const uint32_t* __restrict__ Xt, int64_t nsp4,
-                                  uint64_t* __restrict__ sum) {
+// sum[e] += the sample bytes of element e in chunk blockIdx.y of kSumChunk
+// dwords (sum pre-zeroed; integer adds, so the order does not matter)
+constexpr int kSumChunk = 4096;
+__global__ __launch_bounds__(256) void sample_sum_kernel(const uint32_t* __restrict__ Xt,
+                                                         int64_t nsp4,
+                                                         unsigned long long* __restrict__ sum) {
     const int e = blockIdx.x;
-    uint64_t acc = 0;
-    for (int64_t k = threadIdx.x; k < nsp4; k += blockDim.x) {
+    const int64_t k0 = (int64_t)blockIdx.y * kSumChunk;
+    const int64_t k1 = k0 + kSumChunk < nsp4 ? k0 + kSumChunk : nsp4;
+    uint32_t acc = 0;   // at most 16 dwords of 4 bytes per thread
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
         const uint32_t w = Xt[(int64_t)e * nsp4 + k];
         acc += (w & 0xff) + ((w >> 8) & 0xff) + ((w >> 16) & 0xff) + (w >> 24);
     }
-    __shared__ uint64_t red[256];
+    __shared__ uint32_t red[256];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sum[e] = red[0];
+    if (threadIdx.x == 0) atomicAdd(&sum[e], (unsigned long long)red[0]);
 }
 
 constexpr int kGT = 64;        // gram tile (elements)
@@ -608,12 +638,11 @@ __global__ __launch_bounds__(256) void basis_kernel(const double* __restrict__ A
 
 sfc_status launch_quantize(const float* vol, const uint8_t* mask, const Grid& g, uint8_t* xq,
                            float* params, uint32_t* mm, hipStream_t st) {
-    minmax_init_kernel<<<1, 1, 0, st>>>(mm);
-    SFC_TRY(launched("minmax_init_kernel"));
-    const unsigned nb = (unsigned)std::min<int64_t>(4096, (g.nvox + 255) / 256);
+    const unsigned nb =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>(kQuantBlocks, (g.nvox + 255) / 256));
     minmax_kernel<<<nb, 256, 0, st>>>(vol, mask, g.nvox, g.C, mm);
     SFC_TRY(launched("minmax_kernel"));
-    scale_kernel<<<1, 1, 0, st>>>(mm, params);
+    scale_kernel<<<1, 256, 0, st>>>(mm, (int)nb, params);
     SFC_TRY(launched("scale_kernel"));
     const int64_t n = g.nvox * g.C;
     quantize_kernel<<<blocks_for(n), 256, 0, st>>>(vol, n, params, xq);
@@ -640,12 +669,14 @@ sfc_status launch_gather_samples(const uint8_t* xq, const uint32_t* dict, int64_
 
 sfc_status launch_gram(const uint32_t* Xt, int P, int64_t nsp4, uint64_t* sum, uint64_t* gram,
                        hipStream_t st) {
-    sample_sum_kernel<<<P, 256, 0, st>>>(Xt, nsp4, sum);
-    SFC_TRY(launched("sample_sum_kernel"));
     const int nt = (P + kGT - 1) / kGT;
     const int pairs = nt * (nt + 1) / 2;
     const int64_t chunks = (nsp4 + kGChunk - 1) / kGChunk;
     if (chunks > 65535) return fail(SFC_EUNSUPPORTED, "gram: too many samples");
+    const int64_t schunks = (nsp4 + kSumChunk - 1) / kSumChunk;
+    sample_sum_kernel<<<dim3(P, (unsigned)std::max<int64_t>(1, schunks)), 256, 0, st>>>(
+        Xt, nsp4, reinterpret_cast<unsigned long long*>(sum));
+    SFC_TRY(launched("sample_sum_kernel"));
     gram_kernel<<<dim3(pairs, (unsigned)chunks), 256, 0, st>>>(Xt, P, nsp4, nt, gram);
     return launched("gram_kernel");
 }

@@ -5,10 +5,10 @@
 // Projection: Y[n, S*D] = X[n, P] * Wcat[P, S*D], where row c of X is the
 // byte-coded patch of dictionary entry c (an implicit im2col gathered from
 // the quantised volume into LDS) and Wcat holds every subset's int8 basis in
-// its own D columns (zero outside the subset's elements). Bytes and int8
-// weights are exact in bf16 and every partial sum stays below 2^24
-// (|S_s|*C <= 518), so v_mfma_f32_32x32x16_bf16 with float32 accumulation
-// returns the exact integers.
+// its own D columns (zero outside the subset's elements). The GEMM runs on
+// v_mfma_i32_32x32x32_i8 over (x - 128) (a byte XOR 0x80 is that value as
+// int8) and adds 128 * (column sum of W) afterwards: integer arithmetic
+// throughout, so the coordinates are exact for any patch size.
 #include "build.hpp"
 #include "keys.hpp"
 #include "proj.hpp"
@@ -17,8 +17,8 @@ namespace sfc {
 
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
 inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
@@ -29,52 +29,50 @@ sfc_status launched(const char* what) {
 
 constexpr int kProjRows = 128;   // patches per workgroup (32 per wave)
 
-__device__ inline uint32_t bf16_of_byte_pair(uint32_t w, int k) {
-    // bytes k and k+1 of w -> two bf16 (upper halves of the exact floats)
-    const uint32_t lo = __float_as_uint((float)((w >> (8 * k)) & 0xffu)) >> 16;
-    const uint32_t hi = __float_as_uint((float)((w >> (8 * (k + 1))) & 0xffu)) >> 16;
-    return lo | (hi << 16);
-}
-
 template <int NT>
 __global__ __launch_bounds__(256) void proj_kernel(ProjArgs a) {
-    extern __shared__ uint8_t As[];   // [kProjRows][Pp + 8]
+    extern __shared__ __align__(16) uint8_t As[];   // [kProjRows][Pk + 16]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int stride = a.Pp + 8;
+    const int stride = a.Pk + 16;
     const int64_t base = (int64_t)blockIdx.x * kProjRows;
-    for (int i = tid; i < kProjRows * a.Pp; i += 256) {
-        const int r = i / a.Pp, e = i - r * a.Pp;
-        uint8_t v = 0;
+    // gather by runs: a patch is P / run runs of `run` contiguous bytes
+    const int nruns = a.P / a.run;
+    for (int i = tid; i < kProjRows * nruns; i += 256) {
+        const int r = i / nruns, j = i - r * nruns;
         const int64_t c = base + r;
-        if (e < a.P && c < a.cnt) {
-            const int64_t ctr = a.dict[a.r0 + c];
-            v = a.xq[ctr * a.C + a.elem_off[e]];
-        }
-        As[r * stride + e] = v;
+        if (c >= a.cnt) continue;
+        const uint8_t* src = a.xq + (int64_t)a.dict[a.r0 + c] * a.C + a.elem_off[j * a.run];
+        uint8_t* dst = As + r * stride + j * a.run;
+        for (int e = 0; e < a.run; e++) dst[e] = src[e];
+    }
+    // the padding elements meet zero weights; cleared so no stale bytes enter
+    const int npad = a.Pk - a.P;
+    for (int i = tid; i < kProjRows * npad; i += 256) {
+        const int r = i / npad;
+        As[r * stride + a.P + (i - r * npad)] = 0;
     }
     __syncthreads();
-    f32x16 acc[NT];
+    i32x16 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; t++)
 #pragma unroll
-        for (int i = 0; i < 16; i++) acc[t][i] = 0.0f;
+        for (int i = 0; i < 16; i++) acc[t][i] = 0;
     const int row = wave * 32 + (lane & 31);
-    const int kh = (lane >> 5) * 8;
-    for (int k0 = 0; k0 < a.Pp; k0 += 16) {
-        const uint8_t* ap = As + row * stride + k0 + kh;
-        const uint32_t w0 = *reinterpret_cast<const uint32_t*>(ap);
-        const uint32_t w1 = *reinterpret_cast<const uint32_t*>(ap + 4);
-        union { uint32_t u[4]; bf16x8 v; } A;
-        A.u[0] = bf16_of_byte_pair(w0, 0);
-        A.u[1] = bf16_of_byte_pair(w0, 2);
-        A.u[2] = bf16_of_byte_pair(w1, 0);
-        A.u[3] = bf16_of_byte_pair(w1, 2);
+    // each half-wave supplies 16 of the 32 depth positions of a step, the
+    // same positions for the patch row and the weight column
+    const int kh = (lane >> 5) * 16;
+    const bool live = base + wave * 32 < a.cnt;
+    if (live) {
+        for (int k0 = 0; k0 < a.Pk; k0 += 32) {
+            i32x4 A = *reinterpret_cast<const i32x4*>(As + row * stride + k0 + kh);
 #pragma unroll
-        for (int t = 0; t < NT; t++) {
-            const uint16_t* bp = a.Wt + (int64_t)(t * 32 + (lane & 31)) * a.Pp + k0 + kh;
-            union { uint4 u; bf16x8 v; } B;
-            B.u = *reinterpret_cast<const uint4*>(bp);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A.v, B.v, acc[t], 0, 0, 0);
+            for (int v = 0; v < 4; v++) A[v] ^= (int)0x80808080u;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int8_t* bp = a.Wt + (int64_t)(t * 32 + (lane & 31)) * a.Pk + k0 + kh;
+                const i32x4 B = *reinterpret_cast<const i32x4*>(bp);
+                acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B, acc[t], 0, 0, 0);
+            }
         }
     }
     // epilogue: lane holds column (lane & 31) of each tile, rows
@@ -82,12 +80,13 @@ __global__ __launch_bounds__(256) void proj_kernel(ProjArgs a) {
 #pragma unroll
     for (int t = 0; t < NT; t++) {
         const int col = t * 32 + (lane & 31);
+        const int ws = a.wsum[col];
         int mn = 0x7fffffff, mx = (int)0x80000000;
 #pragma unroll
         for (int i = 0; i < 16; i++) {
             const int r = (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
             const int64_t c = base + wave * 32 + r;
-            const int yv = (int)acc[t][i];
+            const int yv = acc[t][i] + ws;
             if (c < a.cnt && col < a.ncols) {
                 if (a.y) a.y[c * a.ystride + col] = yv;
                 mn = min(mn, yv);
@@ -164,18 +163,27 @@ __global__ void span_kernel(const int32_t* __restrict__ mn, const int32_t* __res
     span[s] = sp;
 }
 
-// Wt[col][e] (bf16 bits) = w_s[i][d] for col = s*D+d and e = elems_s[i]
+// Wt[col][e] = w_s[i][d] for col = s*D+d and e = elems_s[i]
 __global__ void weights_kernel(const int8_t* __restrict__ basis, const int32_t* __restrict__ elems,
-                               const int32_t* __restrict__ msz, int S, int mmax, int D, int Pp,
-                               uint16_t* __restrict__ Wt) {
+                               const int32_t* __restrict__ msz, int S, int mmax, int D, int Pk,
+                               int8_t* __restrict__ Wt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)S * mmax * D) return;
     const int s = (int)(i / ((int64_t)mmax * D));
     const int rem = (int)(i - (int64_t)s * mmax * D);
     const int r = rem / D, d = rem % D;
     if (r >= msz[s]) return;
-    const float w = (float)basis[(int64_t)s * mmax * D + r * D + d];
-    Wt[(int64_t)(s * D + d) * Pp + elems[s * mmax + r]] = (uint16_t)(__float_as_uint(w) >> 16);
+    Wt[(int64_t)(s * D + d) * Pk + elems[s * mmax + r]] = basis[(int64_t)s * mmax * D + r * D + d];
+}
+
+// wsum[col] = 128 * sum_e Wt[col][e] (the offset the byte XOR takes away)
+__global__ void weight_sums_kernel(const int8_t* __restrict__ Wt, int Pk, int cols,
+                                   int32_t* __restrict__ wsum) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= cols) return;
+    int sum = 0;
+    for (int e = 0; e < Pk; e++) sum += Wt[(int64_t)col * Pk + e];
+    wsum[col] = 128 * sum;
 }
 
 using ProjFn = void (*)(ProjArgs);
@@ -190,11 +198,22 @@ const ProjFn kProj[] = {nullptr, proj_fn<1>(), proj_fn<2>(), proj_fn<3>(), proj_
 
 int proj_tiles(int ncols) { return (ncols + 31) / 32; }
 
+int proj_depth(int P) { return (P + 31) / 32 * 32; }
+
+size_t proj_weight_bytes(int ncols, int P) {
+    const size_t cols = (size_t)proj_tiles(ncols) * 32;
+    return cols * proj_depth(P) + cols * sizeof(int32_t);
+}
+
 sfc_status launch_weights(const int8_t* basis, const int32_t* elems, const int32_t* msz, int S,
-                          int mmax, int D, int Pp, uint16_t* Wt, hipStream_t st) {
+                          int mmax, int D, int P, int ncols, int8_t* Wt, int32_t* wsum,
+                          hipStream_t st) {
+    const int Pk = proj_depth(P), cols = proj_tiles(ncols) * 32;
     weights_kernel<<<blocks_for((int64_t)S * mmax * D), 256, 0, st>>>(basis, elems, msz, S, mmax,
-                                                                      D, Pp, Wt);
-    return launched("weights_kernel");
+                                                                      D, Pk, Wt);
+    SFC_TRY(launched("weights_kernel"));
+    weight_sums_kernel<<<blocks_for(cols), 256, 0, st>>>(Wt, Pk, cols, wsum);
+    return launched("weight_sums_kernel");
 }
 
 sfc_status launch_init_minmax(int32_t* mn, int32_t* mx, int n, hipStream_t st) {
@@ -206,7 +225,9 @@ sfc_status launch_projection(const ProjArgs& a, hipStream_t st) {
     if (a.cnt == 0) return SFC_OK;
     const int nt = proj_tiles(a.ncols);
     if (nt < 1 || nt > 16) return fail(SFC_EUNSUPPORTED, "projection: S*D above 512 columns");
-    const size_t lds = (size_t)kProjRows * (a.Pp + 8);
+    if (a.Pk != proj_depth(a.P) || a.run < 1 || a.P % a.run != 0)
+        return fail(SFC_EINVAL, "projection: inconsistent patch layout");
+    const size_t lds = (size_t)kProjRows * (a.Pk + 16);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kProj[nt],
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

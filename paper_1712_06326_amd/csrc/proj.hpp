@@ -10,9 +10,11 @@ struct ProjArgs {
     const uint32_t* dict;     // dictionary centres by rank
     int64_t r0;               // first rank of this chunk
     int64_t cnt;              // patches in this chunk
-    const int32_t* elem_off;  // [Pp] element offset relative to centre*C (padding: any)
-    int P, Pp, C;             // elements, padded to 16
-    const uint16_t* Wt;       // [proj_tiles(ncols)*32][Pp] bf16 bits, zero padded
+    const int32_t* elem_off;  // [P] element offset relative to centre*C
+    int P, Pk, C;             // elements; Pk = proj_depth(P)
+    int run;                  // K*C: contiguous bytes along a patch's innermost axis
+    const int8_t* Wt;         // [proj_tiles(ncols)*32][Pk] int8 weights, zero padded
+    const int32_t* wsum;      // [proj_tiles(ncols)*32] 128 * (sum of the column's weights)
     int ncols;                // S*D
     int32_t* y;               // [cnt][ystride] or null
     int ystride;
@@ -34,8 +36,14 @@ struct KeyArgs {
 };
 
 int proj_tiles(int ncols);
+// element count padded to the MFMA depth (32)
+int proj_depth(int P);
+// bytes of the projection weights: int8 [tiles*32][Pk], then int32 [tiles*32]
+size_t proj_weight_bytes(int ncols, int P);
+// Wt (zeroed beforehand) and its column sums, from the int8 bases
 sfc_status launch_weights(const int8_t* basis, const int32_t* elems, const int32_t* msz, int S,
-                          int mmax, int D, int Pp, uint16_t* Wt, hipStream_t st);
+                          int mmax, int D, int P, int ncols, int8_t* Wt, int32_t* wsum,
+                          hipStream_t st);
 sfc_status launch_init_minmax(int32_t* mn, int32_t* mx, int n, hipStream_t st);
 sfc_status launch_projection(const ProjArgs& a, hipStream_t st);
 sfc_status launch_span(const int32_t* mn, const int32_t* mx, int S, int D, int64_t* lo,

@@ -221,7 +221,7 @@ sfc_status ensure_quantized(sfc_index* ix, const uint8_t* mask) {
     SFC_TRY(dev_alloc((void**)&ix->xq, (size_t)g.nvox * g.C, "quantised volume"));
     SFC_TRY(dev_alloc((void**)&ix->qparams, 4 * sizeof(float), "quantisation parameters"));
     uint32_t* mm = nullptr;
-    SFC_TRY(dev_alloc((void**)&mm, 2 * sizeof(uint32_t), "min/max"));
+    SFC_TRY(dev_alloc((void**)&mm, 2 * kQuantBlocks * sizeof(uint32_t), "min/max"));
     sfc_status s = launch_quantize(ix->vol, mask, g, ix->xq, ix->qparams, mm, ix->st);
     hipError_t e = hipStreamSynchronize(ix->st);
     dev_free(mm);
@@ -273,24 +273,37 @@ void release_sfc(sfc_index* ix) {
     ix->ids = nullptr;
 }
 
-// W^T W of every basis (the query's least-squares imputation) and the bf16
-// projection weights, from the int8 bases already on the device.
+// W^T W of every basis (the query's least-squares imputation) and the int8
+// projection weights with their column sums, from the bases on the device.
 sfc_status basis_products(sfc_index* ix, hipStream_t st) {
-    const int S = ix->S, D = ix->D, mmax = ix->mmax, Pp = ix->Pp;
+    const int S = ix->S, D = ix->D, mmax = ix->mmax, P = ix->g.Kd * ix->g.C;
     SFC_TRY(dev_alloc((void**)&ix->wtw, (size_t)S * D * D * 8, "basis gram"));
     wtw_kernel<<<(S * D * D + 255) / 256, 256, 0, st>>>(ix->basis, ix->msz, S, mmax, D, ix->wtw);
     SFC_HIP(hipGetLastError());
 
-    // projection weights (bf16)
+    // projection weights (int8) and their column sums
     const int ncols = S * D;
     const int nt = proj_tiles(ncols);
     if (nt > 16) return fail(SFC_EUNSUPPORTED, "subsets * reduced_dim above 512");
-    const size_t wbytes = (size_t)nt * 32 * Pp * 2;
+    const size_t wbytes = proj_weight_bytes(ncols, P);
     SFC_TRY(dev_alloc(&ix->proj_w, wbytes, "projection weights"));
     SFC_TRY(zero(ix->proj_w, wbytes, st));
-    SFC_TRY(launch_weights(ix->basis, ix->elems, ix->msz, S, mmax, D, Pp,
-                           static_cast<uint16_t*>(ix->proj_w), st));
+    int8_t* W = static_cast<int8_t*>(ix->proj_w);
+    SFC_TRY(launch_weights(ix->basis, ix->elems, ix->msz, S, mmax, D, P, ncols, W,
+                           reinterpret_cast<int32_t*>(W + (size_t)nt * 32 * proj_depth(P)), st));
     return SFC_OK;
+}
+
+// The patch layout and weights of the projection kernel.
+void set_proj_weights(const sfc_index* ix, ProjArgs& pa) {
+    const int P = ix->g.Kd * ix->g.C;
+    pa.P = P;
+    pa.Pk = proj_depth(P);
+    pa.C = ix->g.C;
+    pa.run = ix->g.K * ix->g.C;
+    const int8_t* W = static_cast<const int8_t*>(ix->proj_w);
+    pa.Wt = W;
+    pa.wsum = reinterpret_cast<const int32_t*>(W + (size_t)proj_tiles(ix->S * ix->D) * 32 * pa.Pk);
 }
 
 // Host copies of the small parameters; marks the handle as an SFC index.
@@ -331,7 +344,7 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
     int mmax = 0;
     for (int s = 0; s < S; s++) mmax = std::max(mmax, ix->h_npix[s] * C);
     if (mmax > kMaxSubsetElems)
-        return fail(SFC_EUNSUPPORTED, "a subset has more than 518 elements (exact bf16 bound)");
+        return fail(SFC_EUNSUPPORTED, "a subset has more than 518 elements (eigensolver bound)");
     ix->mmax = mmax;
     std::vector<int32_t> elems((size_t)S * mmax, 0), msz(S);
     for (int s = 0; s < S; s++) {
@@ -388,6 +401,7 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
         uint64_t* gram = nullptr;
         SFC_TRY(tmp.alloc((void**)&Xt, (size_t)P * nsp4 * 4, "sample matrix"));
         SFC_TRY(dev_alloc((void**)&ix->sum, (size_t)P * 8, "sample sums"));
+        SFC_TRY(zero(ix->sum, (size_t)P * 8, st));
         SFC_TRY(tmp.alloc((void**)&gram, (size_t)P * P * 8, "gram matrix"));
         SFC_TRY(zero(gram, (size_t)P * P * 8, st));
         SFC_TRY(launch_gather_samples(ix->xq, ix->dict, st1, ix->nsub, ix->elem_off, P, C, Xt, nsp4, st));
@@ -427,8 +441,6 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
 // coordinates of every dictionary patch, grid origin and span, keys of
 // every (subset, curve), the sort.
 sfc_status curves_from_basis(sfc_index* ix, hipStream_t st) {
-    const Grid& g = ix->g;
-    const int C = g.C, P = g.Kd * C, Pp = ix->Pp;
     const int S = ix->S, D = ix->D, L = ix->L;
     Temp tmp;
     SFC_TRY(basis_products(ix, st));
@@ -444,10 +456,7 @@ sfc_status curves_from_basis(sfc_index* ix, hipStream_t st) {
     pa.xq = ix->xq;
     pa.dict = ix->dict;
     pa.elem_off = ix->elem_off;
-    pa.P = P;
-    pa.Pp = Pp;
-    pa.C = C;
-    pa.Wt = static_cast<const uint16_t*>(ix->proj_w);
+    set_proj_weights(ix, pa);
     pa.ncols = ncols;
     pa.ystride = ncols;
     pa.colmin = cmin;
@@ -636,10 +645,7 @@ sfc_status sfc_index_projection(const sfc_index* ix, int32_t subset, int64_t* y)
     pa.xq = ix->xq;
     pa.dict = ix->dict;
     pa.elem_off = ix->elem_off;
-    pa.P = ix->g.Kd * ix->g.C;
-    pa.Pp = ix->Pp;
-    pa.C = ix->g.C;
-    pa.Wt = static_cast<const uint16_t*>(ix->proj_w);
+    set_proj_weights(ix, pa);
     pa.ncols = ncols;
     pa.ystride = ncols;
     pa.y = buf;
