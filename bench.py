@@ -359,6 +359,27 @@ def main():
                       f"float32 full scan (n={n}), single thread, {cpu_s:.1f}s; index build "
                       f"and index queries excluded (under 0.1% of the oracle's per-query time)"}
         forms["fp32_vs_oracle_agreement_pct"] = round(100 * agree, 2)
+        # the same oracle with the query list split over the host cores (ctypes
+        # releases the GIL, so the threads run the C scan in parallel)
+        cores = min(16, len(os.sched_getaffinity(0)))
+        k2 = min(12 * cores, Qs)
+        sel2 = np.sort(np.random.default_rng(8).choice(Qs, k2, replace=False))
+        t2_h, m2_h = res["t"].cpu().numpy()[sel2], m_h[sel2]
+        parts = np.array_split(np.arange(k2), cores)
+        from concurrent.futures import ThreadPoolExecutor
+        tc = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            outs = list(ex.map(lambda ix: oracle.brute(w.vol_h, w.mask_h.shape, K, d_h, t2_h[ix],
+                                                       m2_h[ix]), parts))
+        par_s = time.perf_counter() - tc
+        ob2 = np.concatenate([o[0] for o in outs])
+        oc2 = np.concatenate([o[1] for o in outs])
+        agree2 = float(np.mean((ob2 == bi_s[sel2]) & (oc2.view(np.uint32) == bc_s[sel2].view(np.uint32))))
+        forms["cpu_oracle_all_cores"] = {
+            "value": round(k2 / par_s, 3), "unit": "queries/s", "cores": cores,
+            "sample": f"{k2} seeded front queries split over {cores} threads, {par_s:.1f}s",
+            "agreement_with_fp32_scan_pct": round(100 * agree2, 2)}
+        log(f"oracle on {cores} threads: {k2} queries in {par_s:.1f}s")
         # the L1 scan's answers against the oracle's L1 scan on 4 of them
         s4 = sel[:4]
         ob1, oc1 = oracle.brute(w.vol_h, w.mask_h.shape, K, d_h, t_h[:4], m_h[s4], norm="l1")
