@@ -123,6 +123,11 @@ const char *sfc_last_error(void);
 /* Fill the defaults documented in sfc_options. */
 void sfc_options_default(sfc_options *opt);
 
+/* Error-path testing: the n-th device allocation the library makes from now
+ * on (any thread) fails with SFC_ENOMEM and the message "...: injected
+ * allocation failure"; n <= 0 turns this off. Not for production use. */
+void sfc_debug_fail_alloc(int64_t n);
+
 /* Fill front (Fig. 1a: known pixels adjacent to unknown ones; adjacency =
  * shared face). Writes the front's voxel ids in ascending order to
  * centres[0 .. min(count, capacity)), and the total to *count_host.

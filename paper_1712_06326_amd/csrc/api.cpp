@@ -1,6 +1,7 @@
 // C ABI: argument checks, handle lifetime and orchestration of the kernels.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -34,8 +35,17 @@ sfc_status check_hip(hipError_t e, const char* what) {
 }
 
 // Allocation with an optional injected failure: SFC_FAULT_INJECT=alloc:<n>
-// makes the n-th device allocation of the process fail (for error-path tests).
+// makes the n-th device allocation of the process fail, and
+// sfc_debug_fail_alloc(n) the n-th one from the call on (error-path tests).
 static long g_alloc_count = 0;
+static std::atomic<long> g_fail_in{0};   // > 0: allocations until one fails
+static bool injected_failure(long at) {
+    if (at >= 0 && g_alloc_count == at) return true;
+    long v = g_fail_in.load();
+    while (v > 0)
+        if (g_fail_in.compare_exchange_weak(v, v - 1)) return v == 1;
+    return false;
+}
 static long fault_alloc_at() {
     static long at = -2;
     if (at == -2) {
@@ -50,7 +60,7 @@ sfc_status dev_alloc(void** p, size_t bytes, const char* what) {
     *p = nullptr;
     long at = fault_alloc_at();
     g_alloc_count++;
-    if (at >= 0 && g_alloc_count == at)
+    if (injected_failure(at))
         return fail(SFC_ENOMEM, std::string(what) + ": injected allocation failure");
     if (bytes == 0) bytes = 1;
     hipError_t e = hipMalloc(p, bytes);
@@ -64,6 +74,69 @@ sfc_status dev_alloc(void** p, size_t bytes, const char* what) {
 
 void dev_free(void* p) {
     if (p) (void)hipFree(p);
+}
+
+// Temporaries come from a stream-ordered pool of the library (one per
+// device): hipFree waits for every stream of the device, which would make an
+// index build on one stream wait for a scan running on another; hipFreeAsync
+// does not. Freed memory up to kPoolKeep bytes stays in the pool for reuse.
+// If the pool cannot be created the temporaries fall back to hipMalloc /
+// hipFree (the same choice for every temporary of that device).
+namespace {
+constexpr uint64_t kPoolKeep = uint64_t(8) << 30;
+std::mutex g_pool_mu;
+std::map<int, hipMemPool_t> g_pools;   // device -> pool (nullptr: none)
+
+hipMemPool_t library_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pools.find(dev);
+    if (it != g_pools.end()) return it->second;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+        (void)hipGetLastError();
+        pool = nullptr;
+    } else {
+        uint64_t keep = kPoolKeep;
+        if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    g_pools[dev] = pool;
+    return pool;
+}
+}  // namespace
+
+sfc_status tmp_alloc(void** p, size_t bytes, const char* what, hipStream_t st) {
+    hipMemPool_t pool = library_pool();
+    if (!pool) return dev_alloc(p, bytes, what);
+    *p = nullptr;
+    long at = fault_alloc_at();
+    g_alloc_count++;
+    if (injected_failure(at))
+        return fail(SFC_ENOMEM, std::string(what) + ": injected allocation failure");
+    if (bytes == 0) bytes = 1;
+    hipError_t e = hipMallocFromPoolAsync(p, bytes, pool, st);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SFC_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    return SFC_OK;
+}
+
+void tmp_free(void* p, hipStream_t st) {
+    if (!p) return;
+    if (library_pool()) (void)hipFreeAsync(p, st);
+    else (void)hipFree(p);
 }
 
 sfc_status Scratch::reserve(size_t bytes, const char* what) {
@@ -172,8 +245,8 @@ sfc_status build_dictionary(sfc_index* ix, const uint8_t* mask) {
     const Grid& g = ix->g;
     hipStream_t st = ix->st;
     SFC_TRY(dev_alloc((void**)&ix->valid, (size_t)g.nvox, "dictionary validity map"));
-    Scratch tmp;
-    SFC_TRY(tmp.reserve((size_t)g.nvox + compact_scratch_bytes(g.nvox) + 64, "dictionary scratch"));
+    TmpBuf tmp(st);
+    SFC_TRY(tmp.alloc((size_t)g.nvox + compact_scratch_bytes(g.nvox) + 64, "dictionary scratch"));
     uint8_t* t8 = static_cast<uint8_t*>(tmp.ptr);
     SFC_TRY(launch_valid_centres(mask, g, ix->valid, t8, st));
     // count, allocate, compact
@@ -248,6 +321,8 @@ using namespace sfc;
 extern "C" {
 
 int32_t sfc_abi_version(void) { return SFC_ABI_VERSION; }
+
+void sfc_debug_fail_alloc(int64_t n) { g_fail_in.store(n > 0 ? (long)n : 0); }
 
 const char* sfc_last_error(void) { return g_last_error.c_str(); }
 

@@ -10,6 +10,20 @@ namespace sfc {
 
 sfc_status dev_alloc(void** p, size_t bytes, const char* what);
 void dev_free(void* p);
+// stream-ordered temporaries (freeing one does not wait for other streams)
+sfc_status tmp_alloc(void** p, size_t bytes, const char* what, hipStream_t st);
+void tmp_free(void* p, hipStream_t st);
+
+// One stream-ordered temporary, freed on its stream at scope exit.
+struct TmpBuf {
+    hipStream_t st;
+    void* ptr = nullptr;
+    explicit TmpBuf(hipStream_t s) : st(s) {}
+    sfc_status alloc(size_t bytes, const char* what) { return tmp_alloc(&ptr, bytes, what, st); }
+    ~TmpBuf() { tmp_free(ptr, st); }
+    TmpBuf(const TmpBuf&) = delete;
+    TmpBuf& operator=(const TmpBuf&) = delete;
+};
 
 // Grow-only device scratch buffer owned by a handle.
 struct Scratch {

@@ -70,16 +70,22 @@ sfc_status upload(T** dst, const std::vector<T>& src, const char* what, hipStrea
     return SFC_OK;
 }
 
+// Stream-ordered temporaries of one build step, freed on the stream at
+// scope exit (no wait for other streams).
 struct Temp {
+    hipStream_t st;
     std::vector<void*> ptrs;
+    explicit Temp(hipStream_t s) : st(s) {}
     sfc_status alloc(void** p, size_t bytes, const char* what) {
-        SFC_TRY(dev_alloc(p, bytes, what));
+        SFC_TRY(tmp_alloc(p, bytes, what, st));
         ptrs.push_back(*p);
         return SFC_OK;
     }
     ~Temp() {
-        for (void* p : ptrs) dev_free(p);
+        for (void* p : ptrs) tmp_free(p, st);
     }
+    Temp(const Temp&) = delete;
+    Temp& operator=(const Temp&) = delete;
 };
 
 __global__ void wtw_kernel(const int8_t* __restrict__ basis, const int32_t* __restrict__ msz,
@@ -168,7 +174,7 @@ QueryIndexView view_of(const sfc_index* ix) {
 sfc_status sort_key_arrays(uint64_t* keys, uint32_t* ids, int64_t n, int W64, int narr,
                            int nbits, hipStream_t st) {
     if (n <= 1 || narr <= 0) return SFC_OK;
-    Temp tmp;
+    Temp tmp(st);
     uint64_t* varying = nullptr;
     SFC_TRY(tmp.alloc((void**)&varying, (size_t)narr * W64 * 8, "varying bits"));
     SFC_TRY(zero(varying, (size_t)narr * W64 * 8, st));
@@ -220,15 +226,15 @@ sfc_status ensure_quantized(sfc_index* ix, const uint8_t* mask) {
     const Grid& g = ix->g;
     SFC_TRY(dev_alloc((void**)&ix->xq, (size_t)g.nvox * g.C, "quantised volume"));
     SFC_TRY(dev_alloc((void**)&ix->qparams, 4 * sizeof(float), "quantisation parameters"));
-    uint32_t* mm = nullptr;
-    SFC_TRY(dev_alloc((void**)&mm, 2 * kQuantBlocks * sizeof(uint32_t), "min/max"));
-    sfc_status s = launch_quantize(ix->vol, mask, g, ix->xq, ix->qparams, mm, ix->st);
-    hipError_t e = hipStreamSynchronize(ix->st);
-    dev_free(mm);
-    if (s != SFC_OK) return s;
-    if (e != hipSuccess) return check_hip(e, "quantisation");
     float qp[2];
-    SFC_HIP(hipMemcpy(qp, ix->qparams, sizeof(qp), hipMemcpyDeviceToHost));
+    {
+        TmpBuf mm(ix->st);
+        SFC_TRY(mm.alloc(2 * kQuantBlocks * sizeof(uint32_t), "min/max"));
+        SFC_TRY(launch_quantize(ix->vol, mask, g, ix->xq, ix->qparams,
+                                static_cast<uint32_t*>(mm.ptr), ix->st));
+        SFC_HIP(hipMemcpyAsync(qp, ix->qparams, sizeof(qp), hipMemcpyDeviceToHost, ix->st));
+        SFC_HIP(hipStreamSynchronize(ix->st));
+    }
     ix->vmin = qp[0];
     ix->qscale = qp[1];
     return SFC_OK;
@@ -390,7 +396,7 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
     {
         // the statistics and the eigensolver's matrices are freed before
         // the curves are built
-        Temp tmp;
+        Temp tmp(st);
 
         // integer statistics over the strided subsample
         const int64_t stride = (ix->n + (1 << 20) - 1) >> 20;
@@ -442,7 +448,7 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
 // every (subset, curve), the sort.
 sfc_status curves_from_basis(sfc_index* ix, hipStream_t st) {
     const int S = ix->S, D = ix->D, L = ix->L;
-    Temp tmp;
+    Temp tmp(st);
     SFC_TRY(basis_products(ix, st));
     const int ncols = S * D;
     int32_t *cmin = nullptr, *cmax = nullptr;

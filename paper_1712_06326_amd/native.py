@@ -99,6 +99,7 @@ _SIG = {
     "sfc_index_load": (ST, [P, P, C.POINTER(Geometry), I32, C.POINTER(Options), C.c_char_p,
                             C.POINTER(P)]),
     "sfc_sort_pairs": (ST, [P, P, I64, I32, I32, P]),
+    "sfc_debug_fail_alloc": (None, [I64]),
     "sfc_batch_create": (ST, [I32, P, P, P, I32, C.POINTER(Options), C.POINTER(P)]),
     "sfc_batch_query": (ST, [P, P, P, P, P, P]),
     "sfc_batch_autotune": (ST, [P, P, P, P, P, P, C.POINTER(C.c_int32)]),
@@ -170,6 +171,11 @@ def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
     o.timing = 1 if timing else 0
     o.norm = NORMS[norm] if isinstance(norm, str) else int(norm)
     return o
+
+
+def debug_fail_alloc(n: int) -> None:
+    """Makes the library's n-th device allocation from now fail (0: off)."""
+    _L.sfc_debug_fail_alloc(n)
 
 
 def fill_front(mask: torch.Tensor) -> torch.Tensor:
