@@ -62,6 +62,7 @@ class OrcIndex(C.Structure):
 def _declare(L):
     sig = {
         "orc_front": (I64, [P, I32, P, P, I64]),
+        "orc_priority": (None, [P, P, P, I32, P, I32, I32, I64, P, P]),
         "orc_extract": (None, [P, P, I32, P, I32, I32, P, I64, P, P]),
         "orc_dictionary": (I64, [P, I32, P, I32, P, I64]),
         "orc_cost_one": (C.c_float, [P, I32, P, I32, I32, I64, P, P]),
@@ -109,6 +110,19 @@ def _shape(shape):
 
 
 # ---------------------------------------------------------------- basics
+def priority(volume, mask, K, p, conf=None):
+    """(P, C_p) of front voxel p (flat id) in the fill order's reading;
+    conf defaults to 1 on known voxels and 0 elsewhere (the first step)."""
+    volume, mask = _c(volume, np.float32), _c(mask, np.uint8)
+    if conf is None:
+        conf = (mask != 0).astype(np.float64)
+    conf = _c(conf, np.float64)
+    P_, C_ = C.c_double(), C.c_double()
+    lib().orc_priority(_p(volume), _p(mask), _p(conf), mask.ndim, _p(_shape(mask.shape)),
+                       volume.shape[-1], K, int(p), C.byref(P_), C.byref(C_))
+    return P_.value, C_.value
+
+
 def front(mask):
     mask = _c(mask, np.uint8)
     out = np.empty(mask.size, dtype=np.int64)

@@ -1111,8 +1111,9 @@ static double mean_intensity(const float *vol, int64_t v, int C)
  *       known-indicator (out of bounds counts as known) across p, normalised
  *       (Dp = 0 if it vanishes).
  * The paper only cites Criminisi et al. for this heuristic; the formulas here
- * are the reading documented with the oracle (parity unpinned beyond the
- * loop invariants). */
+ * are a reading of it, pinned by closed forms on linear ramps (half-plane,
+ * half-space and corner holes, borders, several channels, confidence below
+ * one). */
 static void priority_of(const float *vol, const uint8_t *mask, const double *conf,
                         const grid_t *g, int C, int K, int64_t p, double *Pout, double *Cout)
 {
@@ -1153,6 +1154,16 @@ static void priority_of(const float *vol, const uint8_t *mask, const double *con
     }
     *Pout = Cp * Dp;
     *Cout = Cp;
+}
+
+/* The priority and confidence term of one front voxel p as the fill loop
+ * computes them (the reading above), given the confidence map conf
+ * (float64 per voxel). */
+void orc_priority(const float *vol, const uint8_t *mask, const double *conf, int nd,
+                  const int64_t *shape, int C, int K, int64_t p, double *P, double *Cp)
+{
+    grid_t g = make_grid(nd, shape);
+    priority_of(vol, mask, conf, &g, C, K, p, P, Cp);
 }
 
 /* The fill loop: until no voxel is unknown, take the front voxel with the

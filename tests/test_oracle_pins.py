@@ -670,3 +670,133 @@ def test_inpaint_single_pixel_hole_is_one_query(orc):
     t, m = orc.extract(vol, mask, 5, [c])
     bi, bc = orc.brute(vol, mask.shape, 5, orc.dictionary(mask, 5), t, m)
     assert log["centre"][0] == c and log["source"][0] == bi[0] and log["cost"][0] == bc[0]
+
+
+# ------------------------------------------------------------------ fill-order priority
+# Closed forms on linear ramps, where the gradient by differences is exact:
+# with the hole a half-plane, a front voxel's data term is the isophote's
+# component along the boundary normal, and its confidence (first step) is the
+# known fraction of its box.
+def _ramp(shape, slopes, C=1, ch_scale=(1.0,)):
+    grids = np.meshgrid(*[np.arange(s, dtype=np.float64) for s in shape], indexing="ij")
+    base = sum(sl * g for sl, g in zip(slopes, grids))
+    vol = np.stack([base * ch_scale[c % len(ch_scale)] for c in range(C)], -1)
+    return vol.astype(np.float32)
+
+
+@pytest.mark.parametrize("K", [5, 7, 9])
+def test_priority_vertical_boundary(orc, K):
+    # I = a x + b y, hole = columns right of x0: D = |b| (isophote (-b, a)
+    # against the normal (0, -1)), C_p = (h + 1) / K away from the borders
+    a, b = 0.25, -0.375
+    h = K // 2
+    H, W, x0 = 31, 29, 14
+    vol = _ramp((H, W), (b, a))
+    mask = np.ones((H, W), np.uint8)
+    mask[:, x0 + 1:] = 0
+    y = 15
+    P, Cp = orc.priority(vol, mask, K, y * W + x0)
+    assert Cp == (h + 1) / K
+    assert P == ((h + 1) / K) * abs(b)
+    # on the top row the box loses h rows; the normal ignores the border
+    # (out of bounds counts as known) and the y-difference becomes one-sided
+    P0, C0 = orc.priority(vol, mask, K, 0 * W + x0)
+    assert C0 == (h + 1) ** 2 / K ** 2
+    assert P0 == ((h + 1) ** 2 / K ** 2) * abs(b)
+
+
+def test_priority_horizontal_boundary_multichannel(orc):
+    # hole = rows below y0: D = |a| with a the x-slope of the channel mean
+    K, h = 7, 3
+    H, W, y0 = 25, 27, 11
+    vol = _ramp((H, W), (0.5, 1.0), C=3, ch_scale=(0.25, 0.5, 0.75))   # mean scale 0.5
+    mask = np.ones((H, W), np.uint8)
+    mask[y0 + 1:, :] = 0
+    P, Cp = orc.priority(vol, mask, K, y0 * W + 13)
+    assert Cp == (h + 1) / K
+    assert P == ((h + 1) / K) * 0.5
+
+
+def test_priority_3d_half_space(orc):
+    # I = c z + b y + a x, hole = x > x0: |grad I x n| with n = (0, 0, -1)
+    # is sqrt(b^2 + c^2) = 5/8 for b = 3/8, c = 1/2
+    K, h = 5, 2
+    shape, x0 = (13, 12, 14), 6
+    vol = _ramp(shape, (0.5, 0.375, 0.125))
+    mask = np.ones(shape, np.uint8)
+    mask[:, :, x0 + 1:] = 0
+    p = (6 * shape[1] + 5) * shape[2] + x0
+    P, Cp = orc.priority(vol, mask, K, p)
+    assert Cp == (h + 1) / K
+    assert P == ((h + 1) / K) * 0.625
+
+
+def test_priority_confidence_is_box_sum_over_k_to_the_d(orc):
+    # a later step: confidence values below 1 on some known voxels; C_p sums
+    # the known in-bounds ones of the box and divides by K^d (not by the
+    # known count), and unknown voxels contribute nothing
+    K = 5
+    H, W, x0 = 20, 20, 9
+    vol = _ramp((H, W), (0.0, 1.0))
+    mask = np.ones((H, W), np.uint8)
+    mask[:, x0 + 1:] = 0
+    conf = np.where(mask == 1, 1.0, 0.0)
+    conf[8:13, x0 - 2:x0 + 1] = 0.5       # the known part of the box of (10, x0)
+    conf[8:13, x0 + 1:x0 + 3] = 7.0       # unknown: must not count
+    _, Cp = orc.priority(vol, mask, K, 10 * W + x0, conf=conf)
+    assert Cp == (15 * 0.5) / 25
+    # the data term does not see the confidence: the ramp's y-slope is 0
+    P, _ = orc.priority(vol, mask, K, 10 * W + x0, conf=conf)
+    assert P == 0.0
+
+
+def test_priority_corner_uses_known_neighbours_only(orc):
+    # known region = the quadrant y <= y0, x <= x0; the hole holds values far
+    # off the ramp, so a difference that used an unknown neighbour would show.
+    # At (y0, x0) both differences are one-sided (b and a) and the normal is
+    # (-1, -1)/sqrt(2): D = |a - b| / sqrt(2); the box holds (h+1)^2 known
+    K, h = 5, 2
+    H, W, y0, x0 = 21, 23, 10, 12
+    a, b = 0.75, -0.25
+    vol = _ramp((H, W), (b, a))
+    mask = np.zeros((H, W), np.uint8)
+    mask[:y0 + 1, :x0 + 1] = 1
+    vol[mask == 0] = 100.0
+    P, Cp = orc.priority(vol, mask, K, y0 * W + x0)
+    assert Cp == (h + 1) ** 2 / K ** 2
+    assert P == pytest.approx(Cp * abs(a - b) / np.sqrt(2.0), rel=1e-15)
+
+
+def test_query_imputation_is_the_ridge_least_squares_fit(orc):
+    # the imputation solves (W_k^T W_k + I) a = W_k^T (x_k - mu_k); the same
+    # fit is the plain least-squares solution of the stacked system
+    # [W_k; I] a = [x_k - mu_k; 0], which numpy solves independently (SVD)
+    import ctypes
+    vol, mask = _img(h=44, w=42, c=3, seed=21)
+    K = 5
+    ix = orc.Index(vol, mask, K, D=6, L=2, key_bits=12, window=16)
+    L = orc.lib()
+    L.orc_query_point.restype = ctypes.c_int
+    L.orc_query_point.argtypes = [ctypes.POINTER(orc.OrcIndex), ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]
+    rng = np.random.default_rng(4)
+    cen = ix.dict[rng.choice(ix.n, 6, replace=False)]
+    t, m = orc.extract(vol, mask, K, cen)
+    C = vol.shape[-1]
+    for q in range(len(cen)):
+        mh = m[q].copy()
+        mh[rng.random(mh.size) < 0.35] = 0
+        yq = np.zeros(64)
+        s = L.orc_query_point(ctypes.byref(ix.struct()), t[q].ctypes.data, mh.ctypes.data,
+                              yq.ctypes.data)
+        els = np.array([p * C + c for p in ix.pix[s] for c in range(C)])
+        W = ix.bases[s].astype(np.float64)
+        kn = np.repeat(mh[ix.pix[s]].astype(bool), C)
+        x = np.clip(np.rint((t[q].reshape(-1)[els] - ix.vmin) * ix.qscale), 0, 255)
+        mu = ix.sum[els] / ix.nsub
+        D = W.shape[1]
+        A = np.vstack([W[kn], np.eye(D)])
+        rhs = np.concatenate([x[kn] - mu[kn], np.zeros(D)])
+        a = np.linalg.lstsq(A, rhs, rcond=None)[0]
+        ref = W[kn].T @ x[kn] + W[~kn].T @ (mu[~kn] + W[~kn] @ a)
+        assert np.allclose(yq[:D], ref, rtol=1e-9, atol=1e-7), (q, yq[:D], ref)
