@@ -114,12 +114,28 @@ __global__ __launch_bounds__(256) void key_kernel(KeyArgs a) {
     const int64_t r = i - (int64_t)s * a.cnt;
     uint32_t u[MD], v[MD];
     const uint64_t sp = (uint64_t)a.span[s];
+    // floor(rel (R-1) / sp) through a float64 reciprocal when the numerator
+    // stays below 2^53 (rel <= sp, so the quotient is below 2^21 and off by
+    // at most one, which the two integer checks correct); else the 64-bit
+    // division
+    const bool fdiv = a.R - 1 < (int64_t(1) << 21) && sp < (uint64_t(1) << 32);
+    const double inv = 1.0 / (double)sp;
 #pragma unroll
     for (int d = 0; d < MD; d++) {
         u[d] = 0;
         if (d < a.D) {
             const int64_t rel = (int64_t)a.y[r * a.ystride + s * a.D + d] - a.lo[s * a.D + d];
-            uint64_t q = rel > 0 ? ((uint64_t)rel * (uint64_t)(a.R - 1)) / sp : 0;
+            uint64_t q = 0;
+            if (rel > 0) {
+                const uint64_t num = (uint64_t)rel * (uint64_t)(a.R - 1);
+                if (fdiv && (uint64_t)rel <= sp) {
+                    q = (uint64_t)((double)num * inv);
+                    if (q * sp > num) q--;
+                    else if ((q + 1) * sp <= num) q++;
+                } else {
+                    q = num / sp;
+                }
+            }
             if (q > (uint64_t)(a.R - 1)) q = a.R - 1;
             u[d] = (uint32_t)q;
         }

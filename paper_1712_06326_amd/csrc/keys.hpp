@@ -42,11 +42,43 @@ __device__ __forceinline__ void hilbert_axes_to_transpose(uint32_t* X, int D, in
 
 // Bit l of coordinate d lands at bit l*D + (D-1-d) of the D*b-bit key:
 // level by level from the top, dim 0 first. Word 0 is the most significant.
+// 8 x 8 bit-matrix transpose of a 64-bit word, bit 8r + c <-> bit 8c + r
+// (swaps of 1x1, 2x2 and 4x4 blocks across the diagonal).
+__device__ __forceinline__ uint64_t transpose8x8(uint64_t x) {
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x ^= t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x ^= t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x ^= t ^ (t << 28);
+    return x;
+}
+
 // The levels enter a 256-bit accumulator from the top level down: each
 // shifts it left by D and puts its D bits (dim 0 highest) at the bottom.
+// For D = 8 a level is one byte, so the 64-bit word of levels 8j..8j+7 is
+// the transpose of the 8 x 8 bit matrix whose row 7 - d is byte j of v[d].
 template <int MD>
 __device__ __forceinline__ void interleave_words(const uint32_t* v, int D, int b, int W64, uint64_t* w) {
     static_assert(kMaxKeyWords == 4, "the accumulator holds four words");
+    if (MD >= 8 && D == 8) {
+        const uint32_t keep = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
+        uint64_t a[4];   // a[3] least significant: levels 0..7
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            uint64_t x = 0;
+#pragma unroll
+            for (int d = 0; d < 8; d++)
+                x |= (uint64_t)(((v[d] & keep) >> (8 * j)) & 0xffu) << (8 * (7 - d));
+            a[3 - j] = transpose8x8(x);
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxKeyWords; k++) {
+            const int src = kMaxKeyWords - W64 + k;
+            w[k] = src == 0 ? a[0] : src == 1 ? a[1] : src == 2 ? a[2] : a[3];
+        }
+        return;
+    }
     uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;   // a0 most significant
     const int rs = 64 - D;                     // 1 <= D <= 32
     for (int l = b - 1; l >= 0; l--) {

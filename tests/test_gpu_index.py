@@ -55,6 +55,10 @@ def _check(vol, mask, K, D, L, b, curve, W, queries=None, with_basis=False):
     (50, 70, 3, 9, 8, 4, 21, "morton", 32, 3),
     (45, 52, 2, 7, 6, 4, 10, "hilbert", 16, 4),
     (64, 80, 1, 9, 10, 6, 8, "hilbert", 32, 5),
+    # eight dimensions: one key byte per level (2 and 4 words, one curve)
+    (46, 58, 3, 7, 8, 3, 16, "hilbert", 16, 6),
+    (44, 50, 1, 7, 8, 2, 31, "morton", 16, 7),
+    (42, 48, 2, 5, 8, 1, 12, "morton", 8, 8),
 ])
 def test_index_small_images(h, w, c, K, D, L, b, curve, W, seed):
     d = synth.small_image(h, w, c, seed)
