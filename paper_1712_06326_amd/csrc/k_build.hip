@@ -129,24 +129,33 @@ __global__ __launch_bounds__(256) void code_checksum_kernel(const uint8_t* __res
 
 // ------------------------------------------------------------ covariance
 // Xt[e][s4] packs the bytes of samples 4*s4 .. 4*s4+3 of element e.
+// One thread per (4-sample group s4, block of kSampleEls elements): the four
+// centres are read once and serve every element of the block.
+constexpr int kSampleEls = 8;
 __global__ void gather_samples_kernel(const uint8_t* __restrict__ xq,
                                       const uint32_t* __restrict__ dict, int64_t stride,
                                       int64_t nsub, const int32_t* __restrict__ elem_off, int P,
                                       int C, uint32_t* __restrict__ Xt, int64_t nsp4) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)P * nsp4) return;
-    const int e = (int)(i / nsp4);
-    const int64_t s4 = i - (int64_t)e * nsp4;
-    const int64_t off = elem_off[e];
-    uint32_t w = 0;
+    const int64_t s4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s4 >= nsp4) return;
+    int64_t base[4];
+#pragma unroll
     for (int k = 0; k < 4; k++) {
         const int64_t s = s4 * 4 + k;
-        if (s < nsub) {
-            const int64_t c = dict[s * stride];
-            w |= (uint32_t)xq[c * C + off] << (8 * k);
-        }
+        base[k] = s < nsub ? (int64_t)dict[s * stride] * C : -1;
     }
-    Xt[i] = w;
+    const int e0 = (int)blockIdx.y * kSampleEls;
+#pragma unroll
+    for (int j = 0; j < kSampleEls; j++) {
+        const int e = e0 + j;
+        if (e >= P) break;
+        const int64_t off = elem_off[e];
+        uint32_t w = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (base[k] >= 0) w |= (uint32_t)xq[base[k] + off] << (8 * k);
+        Xt[(int64_t)e * nsp4 + s4] = w;
+    }
 }
 
 // sum[e] += the sample bytes of element e in chunk blockIdx.y of kSumChunk
@@ -174,11 +183,21 @@ __global__ __launch_bounds__(256) void sample_sum_kernel(const uint32_t* __restr
 }
 
 constexpr int kGT = 64;        // gram tile (elements)
-constexpr int kGK = 32;        // dwords per LDS stage
-constexpr int kGChunk = 4096;  // dwords (16384 samples) per block: u32 partials cannot overflow
+constexpr int kGChunk = 1024;  // dwords (4096 samples) per block: int32 partials cannot overflow
 
-// gram[e][f] += sum over samples of x_e * x_f, for tiles E <= F, with
-// v_dot4_u32_u8 on 4 packed samples at a time.
+typedef int gram_i32x4 __attribute__((ext_vector_type(4)));
+typedef int gram_i32x16 __attribute__((ext_vector_type(16)));
+// 16-byte loads at dword alignment (global loads of this width need only
+// dword alignment)
+typedef gram_i32x4 gram_i32x4u __attribute__((aligned(4)));
+
+// Centred Gram sums on the matrix cores: gram[e][f] += sum over the chunk of
+// x'_e x'_f with x' = x - 128 as int8 (a byte XOR 0x80), for the 64 x 64
+// tile pairs E <= F; each wave takes a 32 x 32 quarter of the pair on
+// v_mfma_i32_32x32x32_i8. A chunk's int32 sums stay below 2^28 (16384
+// samples of at most 2^14). Dwords past the chunk end enter as x' = 0; the
+// zero bytes that pad the last dword are samples x = 0 and are counted by
+// gram_offset_kernel, which adds 128 (S_e + S_f) - 2^14 N afterwards.
 __global__ __launch_bounds__(256) void gram_kernel(const uint32_t* __restrict__ Xt, int P,
                                                    int64_t nsp4, int ntiles,
                                                    uint64_t* __restrict__ gram) {
@@ -191,43 +210,56 @@ __global__ __launch_bounds__(256) void gram_kernel(const uint32_t* __restrict__ 
     const int F = E + pair;
     const int64_t k0 = (int64_t)blockIdx.y * kGChunk;
     const int64_t k1 = min(nsp4, k0 + kGChunk);
-    __shared__ uint32_t As[kGT][kGK + 1];
-    __shared__ uint32_t Bs[kGT][kGK + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    uint32_t acc[4][4] = {};
-    for (int64_t kk = k0; kk < k1; kk += kGK) {
-        for (int i = threadIdx.x; i < kGT * kGK; i += 256) {
-            const int r = i / kGK, c = i % kGK;
-            const int64_t k = kk + c;
-            const int e = E * kGT + r, f = F * kGT + r;
-            As[r][c] = (e < P && k < k1) ? Xt[(int64_t)e * nsp4 + k] : 0u;
-            Bs[r][c] = (f < P && k < k1) ? Xt[(int64_t)f * nsp4 + k] : 0u;
-        }
-        __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = E * kGT + (wave >> 1) * 32 + (lane & 31);
+    const int f = F * kGT + (wave & 1) * 32 + (lane & 31);
+    const int kh = (lane >> 5) * 4;   // this half-wave's 4 dwords of a step
+    const uint32_t* ra = Xt + (int64_t)min(e, P - 1) * nsp4;
+    const uint32_t* rb = Xt + (int64_t)min(f, P - 1) * nsp4;
+    gram_i32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; i++) acc[i] = 0;
+    const gram_i32x4 centre = {(int)0x80808080u, (int)0x80808080u, (int)0x80808080u,
+                               (int)0x80808080u};
+    // whole steps (unrolled so that loads of later steps are in flight),
+    // then the ragged last step with guarded loads
+    const int64_t kfull = k0 + (k1 - k0) / 8 * 8;
+    int64_t kd = k0;
 #pragma unroll 4
-        for (int c = 0; c < kGK; c++) {
-            uint32_t a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                a[u] = As[ty * 4 + u][c];
-                b[u] = Bs[tx * 4 + u][c];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) acc[u][v] = __builtin_amdgcn_udot4(a[u], b[v], acc[u][v], false);
-        }
-        __syncthreads();
+    for (; kd < kfull; kd += 8) {
+        const gram_i32x4 A = *reinterpret_cast<const gram_i32x4u*>(ra + kd + kh);
+        const gram_i32x4 B = *reinterpret_cast<const gram_i32x4u*>(rb + kd + kh);
+        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A ^ centre, B ^ centre, acc, 0, 0, 0);
     }
+    if (kd < k1) {
+        const int64_t k = kd + kh;
+        gram_i32x4 A, B;
 #pragma unroll
-    for (int u = 0; u < 4; u++)
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int e = E * kGT + ty * 4 + u, f = F * kGT + tx * 4 + v;
-            if (e < P && f < P && acc[u][v])
-                atomicAdd((unsigned long long*)&gram[(int64_t)e * P + f],
-                          (unsigned long long)acc[u][v]);
+        for (int j = 0; j < 4; j++) {
+            A[j] = k + j < k1 ? (int)ra[k + j] : (int)0x80808080u;
+            B[j] = k + j < k1 ? (int)rb[k + j] : (int)0x80808080u;
         }
+        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A ^ centre, B ^ centre, acc, 0, 0, 0);
+    }
+    // lane holds column (lane & 31) of the quarter, rows (i/4)*8 + (lane/32)*4 + i%4
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const int r = E * kGT + (wave >> 1) * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+        if (r < P && f < P && acc[i])
+            atomicAdd((unsigned long long*)&gram[(int64_t)r * P + f],
+                      (unsigned long long)(long long)acc[i]);
+    }
+}
+
+// gram[e][f] (e <= f) from the centred sums: + 128 (S_e + S_f) - 2^14 N,
+// N = the sample slots of every dword (the padding zeros included)
+__global__ void gram_offset_kernel(uint64_t* __restrict__ gram, const uint64_t* __restrict__ sum,
+                                   int P, int64_t nslots) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)P * P) return;
+    const int e = (int)(i / P), f = (int)(i % P);
+    if (e > f) return;
+    gram[i] += 128ull * (sum[e] + sum[f]) - 16384ull * (uint64_t)nslots;
 }
 
 // A_s[i][j] = n_sub * Sxx[e_i][e_j] - Sx[e_i] * Sx[e_j], exact in int64, then
@@ -662,8 +694,10 @@ sfc_status launch_code_checksum(const uint8_t* xq, const uint8_t* mask, int64_t 
 sfc_status launch_gather_samples(const uint8_t* xq, const uint32_t* dict, int64_t stride,
                                  int64_t nsub, const int32_t* elem_off, int P, int C,
                                  uint32_t* Xt, int64_t nsp4, hipStream_t st) {
-    gather_samples_kernel<<<blocks_for((int64_t)P * nsp4), 256, 0, st>>>(xq, dict, stride, nsub,
-                                                                         elem_off, P, C, Xt, nsp4);
+    const unsigned eblocks = (unsigned)((P + kSampleEls - 1) / kSampleEls);
+    gather_samples_kernel<<<dim3(blocks_for(nsp4), eblocks), 256, 0, st>>>(xq, dict, stride, nsub,
+                                                                           elem_off, P, C, Xt,
+                                                                           nsp4);
     return launched("gather_samples_kernel");
 }
 
@@ -678,7 +712,9 @@ sfc_status launch_gram(const uint32_t* Xt, int P, int64_t nsp4, uint64_t* sum, u
         Xt, nsp4, reinterpret_cast<unsigned long long*>(sum));
     SFC_TRY(launched("sample_sum_kernel"));
     gram_kernel<<<dim3(pairs, (unsigned)chunks), 256, 0, st>>>(Xt, P, nsp4, nt, gram);
-    return launched("gram_kernel");
+    SFC_TRY(launched("gram_kernel"));
+    gram_offset_kernel<<<blocks_for((int64_t)P * P), 256, 0, st>>>(gram, sum, P, 4 * nsp4);
+    return launched("gram_offset_kernel");
 }
 
 sfc_status launch_cov_matrix(const uint64_t* sum, const uint64_t* gram, int64_t nsub, int P,

@@ -115,6 +115,20 @@ __device__ __forceinline__ void morton_decode(const uint64_t* w, int D, int b, i
     }
 #pragma unroll
     for (int d = 0; d < MD; d++) v[d] = 0;
+    if (MD >= 8 && D == 8) {
+        // the transpose is its own inverse: word j's matrix has row 7 - d
+        // = byte j of coordinate d
+        const uint32_t keep = b >= 32 ? 0xffffffffu : ((1u << b) - 1u);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint64_t x = transpose8x8(a[3 - j]);
+#pragma unroll
+            for (int d = 0; d < 8; d++) v[d] |= (uint32_t)((x >> (8 * (7 - d))) & 0xffu) << (8 * j);
+        }
+#pragma unroll
+        for (int d = 0; d < 8; d++) v[d] &= keep;
+        return;
+    }
     const int ls = 64 - D;   // 1 <= D <= 32
     const uint64_t low = (D == 64) ? ~0ull : ((1ull << D) - 1);
     for (int l = 0; l < b; l++) {
