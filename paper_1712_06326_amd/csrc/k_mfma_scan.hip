@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256) void dict_operand_kernel(
     int rho = k0 / cols, j = k0 - rho * cols;
     const uint8_t* base = c < n ? xq + (int64_t)dict[c] * C : nullptr;
     uint32_t w[4];
+    int sq = -1;   // sum of squares of the current pixel, once its first norm column needs it
 #pragma unroll
     for (int e = 0; e < 8; e++) {
         int v = 0;
@@ -79,10 +80,12 @@ __global__ __launch_bounds__(256) void dict_operand_kernel(
             if (j < C) {
                 v = (int)base[elem_off[rho * C + j]] - 128;
             } else {
-                int sq = 0;
-                for (int ch = 0; ch < C; ch++) {
-                    const int x = (int)base[elem_off[rho * C + ch]] - 128;
-                    sq += x * x;
+                if (sq < 0) {
+                    sq = 0;
+                    for (int ch = 0; ch < C; ch++) {
+                        const int x = (int)base[elem_off[rho * C + ch]] - 128;
+                        sq += x * x;
+                    }
                 }
                 v = (j == C) ? (sq >> 8) : (sq & 255);
             }
@@ -93,6 +96,7 @@ __global__ __launch_bounds__(256) void dict_operand_kernel(
         if (++j == cols) {
             j = 0;
             rho++;
+            sq = -1;
         }
     }
     *reinterpret_cast<u32x4*>(B + blocked_index(c, k0, npad)) = u32x4{w[0], w[1], w[2], w[3]};
