@@ -567,7 +567,11 @@ sfc_status sfc_index_load(const float* volume, const uint8_t* mask, const sfc_ge
     o.window = h.window;
     SFC_TRY(validate_options(o));
     SFC_TRY(check_sfc_args(g, K, h.D, h.L, o));
-    if (h.n < 1 || h.S < 1 || h.mmax < 1 || h.W64 != (h.D * h.b + 63) / 64)
+    // bounds before any array is sized from the header: at most 3^nd - 1
+    // subsets of at most kMaxSubsetElems elements
+    const int max_subsets = h.nd == 2 ? 8 : 26;
+    if (h.n < 1 || h.S < 1 || h.S > max_subsets || h.mmax < 1 || h.mmax > kMaxSubsetElems ||
+        h.W64 != (h.D * h.b + 63) / 64)
         return fail(SFC_EINVAL, "sfc_index_load: inconsistent header");
     SavedIndex sv;
     sv.nsub = h.nsub;

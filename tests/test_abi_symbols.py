@@ -88,11 +88,12 @@ class _Geometry(ctypes.Structure):
                 ("shape", ctypes.c_int64 * 3)]
 
 
-def _index_header(magic=b"SFCINDEX", nd=2, C=1, K=5, D=4, L=2, b=16, shape=(40, 44, 0), n=100):
+def _index_header(magic=b"SFCINDEX", nd=2, C=1, K=5, D=4, L=2, b=16, shape=(40, 44, 0), n=100,
+                  S=5, mmax=10):
     # the header sfc_index_save writes: magic, version, 13 int32 (the last two
     # zero), 6 int64, 2 float, 2 uint64 (136 bytes, no padding)
     W64 = (D * b + 63) // 64
-    ints = (nd, C, K, D, L, b, 0, 16, W64, 5, 10, 0, 0)
+    ints = (nd, C, K, D, L, b, 0, 16, W64, S, mmax, 0, 0)
     return struct.pack("<8sI13i6q2f2Q", magic, 1, *ints, *shape, n, n, 1 << (b - 1),
                        0.0, 1.0, 0, 0)
 
@@ -133,6 +134,8 @@ def test_index_file_errors(tmp_path):
     assert b"another geometry" in run(_index_header(shape=(40, 45, 0)))
     assert b"another geometry" in run(_index_header(C=3))
     assert b"inconsistent" in run(_index_header(n=0))
+    assert b"inconsistent" in run(_index_header(S=9))       # 2D has at most 8 subsets
+    assert b"inconsistent" in run(_index_header(mmax=519))  # above the subset bound
     assert b"reduced_dim" in run(_index_header(D=30))
     assert b"truncated" in run(_index_header())
     # sums 25 * 8, bases 5 * 10 * 4, grid 5 * 4 * 8 + 5 * 8 bytes
