@@ -123,7 +123,13 @@ const char *sfc_last_error(void);
 /* Fill the defaults documented in sfc_options. */
 void sfc_options_default(sfc_options *opt);
 
-/* Error-path testing: the n-th device allocation the library makes from now
+/* Temporaries of the index build (and of the dictionary build) come from a
+ * stream-ordered memory pool of the library, one per device, which keeps up
+ * to 8 GiB of freed memory for reuse; freeing them never waits for work on
+ * other streams. The environment variable SFC_TMP_POOL=0, read at the first
+ * temporary on a device, makes them plain hipMalloc / hipFree allocations.
+ *
+ * Error-path testing: the n-th device allocation the library makes from now
  * on (any thread) fails with SFC_ENOMEM and the message "...: injected
  * allocation failure"; n <= 0 turns this off. Not for production use. */
 void sfc_debug_fail_alloc(int64_t n);

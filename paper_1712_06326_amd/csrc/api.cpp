@@ -96,6 +96,11 @@ hipMemPool_t library_pool() {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     auto it = g_pools.find(dev);
     if (it != g_pools.end()) return it->second;
+    const char* env = std::getenv("SFC_TMP_POOL");
+    if (env && std::strcmp(env, "0") == 0) {   // temporaries through hipMalloc / hipFree
+        g_pools[dev] = nullptr;
+        return nullptr;
+    }
     hipMemPoolProps props{};
     props.allocType = hipMemAllocationTypePinned;
     props.handleTypes = hipMemHandleTypeNone;
