@@ -73,10 +73,24 @@ __global__ __launch_bounds__(256) void dict_operand_kernel(
     const uint8_t* base = c < n ? xq + (int64_t)dict[c] * C : nullptr;
     uint32_t w[4];
     int sq = -1;   // sum of squares of the current pixel, once its first norm column needs it
+    // up to four channels: the pixel's codes are loaded once, in registers
+    int px0 = 0, px1 = 0, px2 = 0, px3 = 0, prho = -1;
 #pragma unroll
     for (int e = 0; e < 8; e++) {
         int v = 0;
-        if (base && rho < Kd) {
+        if (base && rho < Kd && C <= 4) {
+            if (rho != prho) {
+                const uint8_t* pp = base + elem_off[rho * C];   // channels are contiguous
+                px0 = (int)pp[0] - 128;
+                px1 = C > 1 ? (int)pp[1] - 128 : 0;
+                px2 = C > 2 ? (int)pp[2] - 128 : 0;
+                px3 = C > 3 ? (int)pp[3] - 128 : 0;
+                sq = px0 * px0 + px1 * px1 + px2 * px2 + px3 * px3;
+                prho = rho;
+            }
+            v = j == 0 ? px0 : j == 1 ? px1 : j == 2 ? px2 : j == 3 ? px3 : 0;
+            if (j >= C) v = (j == C) ? (sq >> 8) : (sq & 255);
+        } else if (base && rho < Kd) {
             if (j < C) {
                 v = (int)base[elem_off[rho * C + j]] - 128;
             } else {
