@@ -85,6 +85,8 @@ def _declare(L):
         "orc_knn": (I32, [C.POINTER(OrcIndex), P, P, P, I64, I32, P, P, P, P]),
         "orc_morton_decode": (None, [P, I32, I32, P]),
         "orc_query_point": (I32, [C.POINTER(OrcIndex), P, P, P]),
+        "orc_choose_subset": (I32, [P, P, I32, I64, P]),
+        "orc_window": (I64, [P, I64, I32, P, I32, P]),
         "orc_inpaint": (I64, [P, P, I32, P, I32, I32, I32, I32, P, I64,
                               C.POINTER(OrcIndex), I64, P, P, P]),
     }
@@ -291,6 +293,31 @@ def sort(keys_, ids):
     ids = np.array(ids, dtype=np.int64, order="C", copy=True)
     lib().orc_sort(_p(keys_), _p(ids), ids.size, keys_.shape[1] if keys_.ndim == 2 else 1)
     return keys_, ids
+
+
+def choose_subset(pix, m):
+    """The query's subset (Fig. 1b) for target pixel mask m [K^nd]: pix is the
+    list of subsets (pixel offsets), as subsets() returns it."""
+    m = _c(m, np.uint8)
+    Kd = m.size
+    npix = np.array([p.size for p in pix], dtype=np.int32)
+    pixa = np.full((len(pix), Kd), -1, dtype=np.int32)
+    for s, p in enumerate(pix):
+        pixa[s, :p.size] = p
+    return int(lib().orc_choose_subset(_p(npix), _p(pixa), len(pix), Kd, _p(m)))
+
+
+def window(sorted_keys, qkey, W):
+    """(p, lo) of the candidate window of width W on one sorted curve for the
+    query key qkey (uint64 words, word 0 most significant)."""
+    k = _c(sorted_keys, np.uint64)
+    if k.ndim == 1:
+        k = k.reshape(-1, 1)
+    qk = _c(np.atleast_1d(np.asarray(qkey, dtype=np.uint64)), np.uint64)
+    assert qk.size == k.shape[1]
+    p = C.c_int64()
+    lo = lib().orc_window(_p(k), k.shape[0], k.shape[1], _p(qk), int(W), C.byref(p))
+    return int(p.value), int(lo)
 
 
 CURVES = {"morton": 0, "hilbert": 1}

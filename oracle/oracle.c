@@ -692,8 +692,6 @@ void orc_key_of(const uint32_t *v, int D, int b, int curve, uint64_t *key)
     interleave(X, D, b, W64, key);
 }
 
-/* Grid cell of one principal vector: u_d = clamp(floor((y_d - lo_d)*(R-1) /
- * span), 0, R-1); shifted copy j of L adds floor(j*R/L) to every dim. */
 /* Shift of curve j: the same offset floor(j*R/(D+1)) on every dim, the
  * diagonal shifts of shifted-curve kNN search (Liao, Lopez and Leutenegger,
  * 2001). A divisor of D+1 rather than L keeps the offsets off the powers of two,
@@ -703,6 +701,8 @@ static int64_t shift_of(int j, int64_t R, int D)
     return ((int64_t)j * R) / (D + 1);
 }
 
+/* Grid cell of one principal vector: u_d = clamp(floor((y_d - lo_d)*(R-1) /
+ * span), 0, R-1), plus the shift of curve j on every dim. */
 static void cell_of(const int64_t *y, int D, const int64_t *lo, int64_t span, int64_t R,
                     int j, int L, uint32_t *v)
 {
@@ -886,17 +886,51 @@ static void cell_of_real(const double *y, int D, const int64_t *lo, int64_t span
     }
 }
 
+/* The query's subset (Fig. 1b: the index whose pixels best cover the search
+ * area): the subset with the largest fraction k_s / n_s of its pixels known
+ * in the target mask m, compared exactly as k_s * n_b > k_b * n_s; on equal
+ * fractions the lower subset is kept. pix is [S][Kd], npix[S]. */
+int orc_choose_subset(const int32_t *npix, const int32_t *pix, int S, int64_t Kd,
+                      const uint8_t *m)
+{
+    int sb = 0;
+    int64_t kb = -1, nb = 1;
+    for (int s = 0; s < S; s++) {
+        int64_t k = 0, ns = npix[s];
+        for (int i = 0; i < ns; i++) k += m[pix[s * Kd + i]];
+        if (kb < 0 || k * nb > kb * ns) { sb = s; kb = k; nb = ns; }
+    }
+    return sb;
+}
+
+/* The candidate window on one sorted curve: p = the first position whose key
+ * is >= the query key qk (lower bound; n if none), then the W positions
+ * starting at lo = p - floor(W/2), moved inside the array:
+ * lo = clamp(lo, 0, max(n - W, 0)). Returns lo; the window is
+ * [lo, min(lo + W, n)). keys is [n][W64], sorted; *p_out receives p. */
+int64_t orc_window(const uint64_t *keys, int64_t n, int W64, const uint64_t *qk, int W,
+                   int64_t *p_out)
+{
+    int64_t a = 0, z = n;
+    while (a < z) {
+        int64_t mid = a + (z - a) / 2;
+        if (key_cmp(keys + mid * W64, qk, W64) < 0) a = mid + 1;
+        else z = mid;
+    }
+    if (p_out) *p_out = a;
+    int64_t lo = a - W / 2;
+    int64_t lmax = n - W;
+    if (lmax < 0) lmax = 0;
+    if (lo > lmax) lo = lmax;
+    if (lo < 0) lo = 0;
+    return lo;
+}
+
 /* Exposed for tests: subset choice and real principal coordinates. */
 int orc_query_point(const orc_index *ix, const float *t, const uint8_t *m, double *yq)
 {
     int64_t Kd = ipow(ix->K, ix->nd);
-    int sb = 0;
-    int64_t kb = -1, nb = 1;
-    for (int s = 0; s < ix->S; s++) {
-        int64_t k = 0, ns = ix->npix[s];
-        for (int i = 0; i < ns; i++) k += m[ix->pix[s * Kd + i]];
-        if (kb < 0 || k * nb > kb * ns) { sb = s; kb = k; nb = ns; }
-    }
+    int sb = orc_choose_subset(ix->npix, ix->pix, ix->S, Kd, m);
     query_coords(ix, t, m, sb, yq);
     return sb;
 }
@@ -922,13 +956,7 @@ int64_t orc_query_one(const orc_index *ix, const float *vol, const float *t,
     int W64 = (ix->D * ix->b + 63) / 64;
     int64_t R = (ix->L > 1) ? ((int64_t)1 << (ix->b - 1)) : ((int64_t)1 << ix->b);
     /* 1 */
-    int sb = 0;
-    int64_t kb = -1, nb = 1;
-    for (int s = 0; s < ix->S; s++) {
-        int64_t k = 0, ns = ix->npix[s];
-        for (int i = 0; i < ns; i++) k += m[ix->pix[s * Kd + i]];
-        if (kb < 0 || k * nb > kb * ns) { sb = s; kb = k; nb = ns; }
-    }
+    int sb = orc_choose_subset(ix->npix, ix->pix, ix->S, Kd, m);
     if (subset_out) *subset_out = sb;
     /* 2, 3 */
     double yq[64];
@@ -943,17 +971,7 @@ int64_t orc_query_one(const orc_index *ix, const float *vol, const float *t,
         orc_key_of(v, ix->D, ix->b, ix->curve, qk);
         const uint64_t *keys = ix->keys + ((int64_t)(sb * ix->L + j) * ix->n) * W64;
         const int64_t *ids = ix->ids + (int64_t)(sb * ix->L + j) * ix->n;
-        int64_t a = 0, z = ix->n;
-        while (a < z) {
-            int64_t mid = a + (z - a) / 2;
-            if (key_cmp(keys + mid * W64, qk, W64) < 0) a = mid + 1;
-            else z = mid;
-        }
-        int64_t lo = a - ix->window / 2;
-        int64_t lmax = ix->n - ix->window;
-        if (lmax < 0) lmax = 0;
-        if (lo > lmax) lo = lmax;
-        if (lo < 0) lo = 0;
+        int64_t lo = orc_window(keys, ix->n, W64, qk, ix->window, NULL);
         int64_t hi = lo + ix->window;
         if (hi > ix->n) hi = ix->n;
         for (int64_t i = lo; i < hi; i++) cand[nc++] = ids[i];
@@ -1034,13 +1052,7 @@ int64_t orc_knn_one(const orc_index *ix, const float *vol, const float *t, const
     int64_t Kd = ipow(ix->K, ix->nd);
     int W64 = (ix->D * ix->b + 63) / 64;
     int64_t R = (ix->L > 1) ? ((int64_t)1 << (ix->b - 1)) : ((int64_t)1 << ix->b);
-    int sb = 0;
-    int64_t kb = -1, nb = 1;
-    for (int s = 0; s < ix->S; s++) {
-        int64_t kk = 0, ns = ix->npix[s];
-        for (int i = 0; i < ns; i++) kk += m[ix->pix[s * Kd + i]];
-        if (kb < 0 || kk * nb > kb * ns) { sb = s; kb = kk; nb = ns; }
-    }
+    int sb = orc_choose_subset(ix->npix, ix->pix, ix->S, Kd, m);
     double yq[64];
     query_coords(ix, t, m, sb, yq);
     uint32_t u[64], v[64];

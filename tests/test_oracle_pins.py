@@ -345,6 +345,71 @@ def test_basis_orders_signs_and_scales(orc):
     assert np.all(np.diff(np.diag(Ad)[order]) <= 0)
 
 
+def _eigh_basis(A, D):
+    """rint(127 U / g) from numpy's eigh: U the D leading eigenvectors
+    (eigenvalue descending), each signed positive at its largest-magnitude
+    entry, g the largest magnitude over them; also the distance of every
+    scaled entry from a rounding tie."""
+    lam, U = np.linalg.eigh(A)
+    U = U[:, ::-1][:, :D]
+    U = U * np.sign(U[np.abs(U).argmax(0), np.arange(D)])
+    z = U * 127 / np.abs(U).max()
+    tie = np.abs(np.abs(z - np.floor(z)) - 0.5)
+    return np.rint(z), tie, lam[::-1]
+
+
+def _real_cov(orc, nd, K, C, seed, subset):
+    if nd == 2:
+        d = synth.small_image(48, 52, C, seed, holes=2, frac=0.08)
+    else:
+        d = synth.small_volume(22, seed)
+    vol, mask = d["volume"], d["mask"]
+    xq, _, _ = orc.quantize(vol, mask)
+    dd = orc.dictionary(mask, K)
+    s, ss, ns = orc.cov_sums(xq, mask.shape, K, dd)
+    el = orc.subset_elems(orc.subsets(nd, K)[subset], vol.shape[-1])
+    return orc.cov_matrix(s, ss, ns, el)
+
+
+@pytest.mark.parametrize("case", ["rand7", "rand12", "rand50", "mixed20",
+                                  "img2d_k9_c3_s0", "img2d_k9_c3_s5", "img2d_k7_c1_s2",
+                                  "vol3d_k5_s0", "vol3d_k5_s13", "vol3d_k7_s4"])
+def test_basis_equals_rounded_eigh(orc, case):
+    # The int8 basis depends only on the eigenvectors, not on the Jacobi
+    # solver's rounding order (its round-robin pairing, its mirroring of the
+    # upper triangle): every entry equals rint(127 U / g) computed from
+    # numpy's eigh, except entries within 1e-9 of a rounding tie.
+    D = 8
+    if case.startswith("rand"):
+        m = int(case[4:])
+        rng = np.random.default_rng(m)
+        X = rng.integers(0, 256, size=(400, m)).astype(np.float64)
+        X[:, 1] = X[:, 0]
+        A = 400 * X.T @ X - np.outer(X.sum(0), X.sum(0))
+        D = min(D, m - 2)
+    elif case == "mixed20":
+        rng = np.random.default_rng(2)
+        X = rng.integers(0, 256, size=(300, 20)).astype(np.float64) @ rng.normal(size=(20, 20))
+        A = X.T @ X
+        D = 6
+    elif case.startswith("img2d"):
+        _, k, c, s = case.split("_")
+        A = _real_cov(orc, 2, int(k[1:]), int(c[1:]), 3, int(s[1:]))
+    else:
+        _, k, s = case.split("_")
+        A = _real_cov(orc, 3, int(k[1:]), 1, 4, int(s[1:]))
+    Ad, V, _ = orc.jacobi(A)
+    w, order = orc.basis_from(Ad, V, D)
+    want, tie, lam = _eigh_basis(A, D)
+    # the eigenvectors must be well defined: distinct leading eigenvalues
+    gaps = np.abs(np.diff(lam[:D + 1]))
+    assert gaps.min() > 1e-6 * lam[0]
+    ok = tie > 1e-9
+    assert ok.mean() > 0.99
+    assert np.array_equal(w.astype(np.float64)[ok], want[ok])
+    assert np.all(np.abs(w.astype(np.float64) - want) <= 1)
+
+
 def test_projection_matches_numpy(orc):
     vol, mask = _img(h=26, w=29, c=3, seed=8)
     K = 5
@@ -602,6 +667,163 @@ def test_query_coords_full_mask_exact_and_partial_least_squares(orc):
         a = np.linalg.lstsq(W[kn], x[kn] - mu[kn], rcond=None)[0]
         ref = W[kn].T @ x[kn] + W[~kn].T @ (mu[~kn] + W[~kn] @ a)
         assert np.allclose(yq[:5], ref, rtol=1e-4, atol=1.0)
+
+
+def _mask_3d_k5(unknown):
+    """A 5x5x5 target pixel mask with the pixels whose (i, j, k) satisfies
+    unknown(i, j, k) set to 0 (rho = 25 i + 5 j + k)."""
+    m = np.ones(125, np.uint8)
+    for r in range(125):
+        if unknown(r // 25, (r // 5) % 5, r % 5):
+            m[r] = 0
+    return m
+
+
+def _fraction_rule(pix, m):
+    """The reading of Fig. 1b: the subset with the largest known fraction,
+    ties to the lower subset, in exact rationals."""
+    from fractions import Fraction
+    fr = [Fraction(int(m[p].sum()), p.size) for p in pix]
+    return fr.index(max(fr)), fr
+
+
+def test_subset_choice_is_largest_known_fraction_not_count(orc):
+    # 3D, K = 5: anchors {0, 2, 4}^3 minus the centre in lexicographic order,
+    # so subset 18 is anchored at (4, 0, 2) (an edge midpoint, 83 pixels) and
+    # subset 21 at (4, 2, 2) (the face centre, 76 pixels). With the plane
+    # i = 0 unknown, the face-centre subset opposite it is fully known (76 of
+    # 76) while the edge subset keeps the most known pixels (79 of 83): the
+    # largest known fraction picks 21, the largest known count would pick 18.
+    pix = orc.subsets(3, 5)
+    m = _mask_3d_k5(lambda i, j, k: i == 0)
+    counts = [int(m[p].sum()) for p in pix]
+    assert (pix[21].size, counts[21]) == (76, 76) and (pix[18].size, counts[18]) == (83, 79)
+    assert int(np.argmax(counts)) == 18
+    assert _fraction_rule(pix, m)[0] == 21
+    assert orc.choose_subset(pix, m) == 21
+    # the fraction-rule winner is unique here, so taking the smallest fraction
+    # or the last subset would differ too
+    assert orc.choose_subset(pix, 1 - m) != 21
+
+
+def test_subset_choice_ties_go_to_the_lower_subset(orc):
+    # The line (i, 2, 2), i = 0..4, through the centre unknown: eight edge
+    # subsets (1, 3, 5, 7, 18, 20, 22, 24) each lose four of their 83 pixels
+    # and tie at 79/83, the largest fraction (no subset is fully known); the
+    # lowest of them, 1, is chosen (the highest would be 24).
+    pix = orc.subsets(3, 5)
+    m = _mask_3d_k5(lambda i, j, k: j == 2 and k == 2)
+    best, fr = _fraction_rule(pix, m)
+    from fractions import Fraction
+    tied = [s for s, f in enumerate(fr) if f == max(fr)]
+    assert tied == [1, 3, 5, 7, 18, 20, 22, 24] and max(fr) == Fraction(79, 83)
+    assert orc.choose_subset(pix, m) == 1
+    # a full mask ties every subset at 1: subset 0
+    assert orc.choose_subset(pix, np.ones(125, np.uint8)) == 0
+
+
+def test_subset_choice_seeded_masks_follow_the_fraction_rule(orc):
+    # seeded partial masks in 3D (unequal subset sizes) and 2D (equal sizes)
+    rng = np.random.default_rng(11)
+    for nd, K in [(3, 5), (3, 7), (2, 9)]:
+        pix = orc.subsets(nd, K)
+        disagree = 0
+        for _ in range(300):
+            m = (rng.random(K ** nd) > rng.uniform(0.02, 0.5)).astype(np.uint8)
+            want, fr = _fraction_rule(pix, m)
+            assert orc.choose_subset(pix, m) == want
+            disagree += int(np.argmax([int(m[p].sum()) for p in pix])) != want
+        if nd == 3:
+            assert disagree > 0   # the count rule would have failed here
+
+
+def test_query_uses_the_subset_choice(orc):
+    # The index query picks its subset by the same rule (query_point returns
+    # the subset the query searched).
+    rng = np.random.default_rng(5)
+    vol = rng.random((12, 13, 11, 1)).astype(np.float32)
+    mask = np.ones((12, 13, 11), np.uint8)
+    mask[5:8, 5:8, 4:7] = 0
+    ix = orc.Index(vol, mask, 5, 4, 2, key_bits=8)
+    ms = [_mask_3d_k5(lambda i, j, k: i == 0), _mask_3d_k5(lambda i, j, k: j == 2 and k == 2)]
+    ms += [(rng.random(125) > 0.3).astype(np.uint8) for _ in range(20)]
+    m = np.stack(ms)
+    t = rng.random((m.shape[0], 125, 1)).astype(np.float32)
+    sub, _ = ix.query_point(t, m)
+    _, _, _, _, sub2 = ix.query(vol, t, m)
+    want = [_fraction_rule(ix.pix, mm)[0] for mm in m]
+    assert sub[0] == 21 and sub[1] == 1
+    assert list(sub) == want and list(sub2) == want
+
+
+# Windows written out by hand from the reading of Section II.C's search: p is
+# the first position whose key is >= the query key, lo = p - floor(W/2)
+# clamped to [0, max(n - W, 0)], the window is [lo, min(lo + W, n)).
+_KEYS1 = [3, 5, 5, 5, 9, 12, 12, 20, 31, 40]          # n = 10, one word
+
+
+@pytest.mark.parametrize("q,W,p,lo", [
+    (1, 4, 0, 0),      # below the first key: p = 0, window at the start
+    (3, 4, 0, 0),      # equal to the first key
+    (50, 4, 10, 6),    # above the last key: p = n, window at the end
+    (40, 4, 9, 6),     # equal to the last key: lo = 7 clamped to n - W = 6
+    (5, 4, 1, 0),      # a run of duplicates 5, 5, 5: p is its first position
+    (5, 2, 1, 0),      # p - 1 = 0
+    (6, 2, 4, 3),      # between the run and 9: p = 4
+    (10, 4, 5, 3),     # mid-array between 9 and 12
+    (12, 4, 5, 3),     # first of the run 12, 12
+    (13, 4, 7, 5),     # after the run: p = 7 (key 20)
+    (20, 5, 7, 5),     # odd W: floor(5/2) = 2
+    (9, 1, 4, 4),      # W = 1: the lower-bound position itself
+    (31, 3, 8, 7),     # odd W near the end: lo = 7 = n - W
+    (9, 10, 4, 0),     # W = n: the whole array
+    (9, 16, 4, 0),     # W > n: lo = 0, window [0, n)
+])
+def test_window_placement_hand_cases(orc, q, W, p, lo):
+    keys = np.array(_KEYS1, np.uint64)
+    assert orc.window(keys, q, W) == (p, lo)
+
+
+def test_window_placement_two_word_keys(orc):
+    # word 0 most significant: (1, 7) < (2, 0) < (2, 0) < (2, 5) < (3, 1)
+    keys = np.array([[1, 7], [2, 0], [2, 0], [2, 5], [3, 1]], np.uint64)
+    assert orc.window(keys, [2, 0], 2) == (1, 0)
+    assert orc.window(keys, [2, 1], 2) == (3, 2)
+    assert orc.window(keys, [1, 8], 2) == (1, 0)     # the low word decides within (1, .)
+    assert orc.window(keys, [3, 2], 2) == (5, 3)
+    assert orc.window(keys, [0, 2**64 - 1], 3) == (0, 0)
+    # a high word of 2^63 and above compares unsigned
+    keys = np.array([[5, 0], [2**63, 0], [2**64 - 1, 3]], np.uint64)
+    assert orc.window(keys, [2**63 + 1, 0], 1) == (2, 2)
+
+
+def test_index_query_windows_are_the_hand_rule(orc):
+    # The index query's candidates are the union of the windows on its
+    # curves: with L = 1 and W = 8 on a small index, every query's candidate
+    # set is exactly 8 consecutive entries of the curve (or n of them), and
+    # the query's own key, re-derived from query_point through key_of, has
+    # its lower-bound position inside the window at offset floor(W/2) unless
+    # the window was clamped at an end.
+    vol, mask = _img(h=40, w=42, c=1, seed=9)
+    K, W = 5, 8
+    ix = orc.Index(vol, mask, K, 3, 1, key_bits=8, window=W)
+    f = orc.front(mask)[::7]
+    t, m = orc.extract(vol, mask, K, f)
+    _, _, cand, nc, sub = ix.query(vol, t, m)
+    _, ys = ix.query_point(t, m)
+    R = 1 << ix.b
+    for q in range(len(f)):
+        s = sub[q]
+        ids = ix.ids[s, 0]
+        u = np.floor((ys[q] - ix.lo[s]) * (R - 1) / ix.span[s])
+        v = np.clip(u, 0, R - 1).astype(np.uint32)
+        qk = orc.key_of(v, ix.b, ix.curve)
+        keys = ix.keys[s, 0]
+        kint = [int(k[0]) for k in keys]
+        p = int(np.searchsorted(np.array(kint, dtype=np.uint64), np.uint64(qk[0]), side="left"))
+        lo = min(max(p - W // 2, 0), max(ix.n - W, 0))
+        assert nc[q] == min(W, ix.n)
+        assert np.array_equal(np.sort(cand[q, :nc[q]]), np.sort(ids[lo:lo + W]))
 
 
 def test_more_curves_lower_acceleration_error(orc):
