@@ -151,6 +151,31 @@ def dictionary(mask, K):
     return out[:n].copy()
 
 
+def dictionary_pooled(mask, K, threads):
+    """dictionary() computed over slabs of the slowest axis in a thread pool:
+    the slab of centre rows [a, b) with h = (K-1)/2 rows of halo on each side
+    (clipped to the volume) holds every box of those centres, so the oracle's
+    dictionary of the slab, restricted to rows [a, b) and offset back, is the
+    full dictionary's part for those rows."""
+    mask = _c(mask, np.uint8)
+    if threads <= 1 or mask.shape[0] < 4 * threads:
+        return dictionary(mask, K)
+    h = (K - 1) // 2
+    row = int(np.prod(mask.shape[1:]))
+    cuts = np.linspace(0, mask.shape[0], 2 * threads + 1).astype(int)
+
+    def part(ab):
+        a, b = ab
+        lo, hi = max(0, a - h), min(mask.shape[0], b + h)
+        ids = dictionary(mask[lo:hi], K)
+        r = ids // row + lo
+        return ids[(r >= a) & (r < b)] + lo * row
+
+    parts = _pool_map(part, [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a],
+                      threads)
+    return np.concatenate(parts)
+
+
 NORMS = {"l2": 0, "l1": 1}
 
 
@@ -181,6 +206,21 @@ def brute(volume, shape, K, dict_ids, t, m, norm="l2"):
     bc = np.empty(Q, dtype=np.float32)
     lib().orc_brute(_p(volume), len(shape), _p(_shape(shape)), volume.shape[-1], K,
                     _p(dict_ids), dict_ids.size, _p(t), _p(m), Q, _p(bi), _p(bc), NORMS[norm])
+    return bi, bc
+
+
+def brute_pooled(volume, shape, K, dict_ids, t, m, threads, norm="l2"):
+    """brute() over slices of the dictionary in a thread pool, merged by
+    (cost, id): slices ascend, so on equal costs the earlier slice's (lower)
+    id stays, as in one full scan."""
+    dict_ids = _c(dict_ids, np.int64)
+    parts = _pool_map(lambda d: brute(volume, shape, K, d, t, m, norm),
+                      [x for x in np.array_split(dict_ids, max(1, 2 * threads)) if x.size],
+                      threads)
+    bi, bc = parts[0][0].copy(), parts[0][1].copy()
+    for pi, pc in parts[1:]:
+        take = pc < bc
+        bi[take], bc[take] = pi[take], pc[take]
     return bi, bc
 
 
@@ -220,6 +260,29 @@ def cov_sums(xq, shape, K, dict_ids):
     nsub = lib().orc_cov_sums(_p(xq), len(shape), _p(_shape(shape)), Cc, K,
                               _p(dict_ids), dict_ids.size, _p(s), _p(ss))
     return s, ss, int(nsub)
+
+
+def _pool_map(fn, items, threads):
+    if threads <= 1:
+        return [fn(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:   # ctypes releases the GIL during each call
+        return list(ex.map(fn, items))
+
+
+def cov_sums_pooled(xq, shape, K, dict_ids, threads):
+    """cov_sums over the same strided subsample, computed as exact integer
+    sums over slices of it in a thread pool (each slice holds under 2^20
+    ranks, so orc_cov_sums takes every rank of a slice)."""
+    dict_ids = _c(dict_ids, np.int64)
+    stride = max(1, -(-dict_ids.size // (1 << 20)))
+    sub = dict_ids[::stride]
+    parts = _pool_map(lambda d: cov_sums(xq, shape, K, d),
+                      [x for x in np.array_split(sub, max(1, 2 * threads)) if x.size], threads)
+    s = sum(p[0] for p in parts)
+    ss = sum(p[1] for p in parts)
+    assert sum(p[2] for p in parts) == sub.size
+    return s, ss, int(sub.size)
 
 
 def cov_matrix(s, ss, nsub, elems):
@@ -329,7 +392,11 @@ class Index:
     curves, sort by curve position (Sections II, II.A-C)."""
 
     def __init__(self, volume, mask, K, D, L, key_bits=8, curve="morton", window=32,
-                 bases=None, keep_y=False, norm="l2"):
+                 bases=None, keep_y=False, norm="l2", threads=1, build_curves=True):
+        """threads > 1 runs independent oracle calls (slices of the covariance
+        subsample, separate subsets) in a thread pool; the result is the same.
+        build_curves=False stops after the statistics and bases: curves are
+        then attached one by one with attach_curve()."""
         self.volume = _c(volume, np.float32)
         self.mask = _c(mask, np.uint8)
         self.shape = tuple(self.mask.shape)
@@ -339,39 +406,74 @@ class Index:
         self.norm = NORMS[norm]   # the rescoring cost (the index itself is norm-free)
         self.curve = CURVES[curve] if isinstance(curve, str) else int(curve)
         self.xq, self.vmin, self.qscale = quantize(self.volume, self.mask)
-        self.dict = dictionary(self.mask, K)
+        self.dict = dictionary_pooled(self.mask, K, threads)
         self.n = self.dict.size
         if self.n == 0:
             raise ValueError("empty dictionary")
         self.pix = subsets(self.nd, K)
         self.S = len(self.pix)
         self.elems = [subset_elems(p, self.C) for p in self.pix]
-        self.sum, self.sumsq, self.nsub = cov_sums(self.xq, self.shape, K, self.dict)
+        if threads > 1:
+            self.sum, self.sumsq, self.nsub = cov_sums_pooled(self.xq, self.shape, K, self.dict,
+                                                              threads)
+        else:
+            self.sum, self.sumsq, self.nsub = cov_sums(self.xq, self.shape, K, self.dict)
         self.W64 = key_words(D, key_bits)
-        self.bases, self.lo, self.span, self.sweeps = [], [], [], []
+        self.y = [None] * self.S if keep_y else None
+        self.sweeps = [None] * self.S
+
+        def basis_of(s):
+            if bases is not None:
+                return _c(bases[s], np.int8)
+            A = cov_matrix(self.sum, self.sumsq, self.nsub, self.elems[s])
+            Ad, V, sw = jacobi(A)
+            self.sweeps[s] = sw
+            return basis_from(Ad, V, D)[0]
+
+        self.bases = _pool_map(basis_of, range(self.S), threads)
+        self.lo, self.span = [None] * self.S, [None] * self.S
+        self._curves = {}
+        if not build_curves:
+            self.keys = self.ids = None
+            self._struct = None
+            return
         self.keys = np.empty((self.S, L, self.n, self.W64), dtype=np.uint64)
         self.ids = np.empty((self.S, L, self.n), dtype=np.int64)
-        self.y = [] if keep_y else None
-        for s in range(self.S):
-            if bases is None:
-                A = cov_matrix(self.sum, self.sumsq, self.nsub, self.elems[s])
-                Ad, V, sw = jacobi(A)
-                w, _ = basis_from(Ad, V, D)
-                self.sweeps.append(sw)
-            else:
-                w = _c(bases[s], np.int8)
-            self.bases.append(w)
-            y = project(self.xq, self.shape, K, self.dict, self.elems[s], w)
+
+        def subset_curves(s):
+            y = project(self.xq, self.shape, K, self.dict, self.elems[s], self.bases[s])
             if keep_y:
-                self.y.append(y)
+                self.y[s] = y
             lo, span = key_params(y)
-            self.lo.append(lo)
-            self.span.append(span)
+            self.lo[s], self.span[s] = lo, span
             for j in range(L):
                 k = keys(y, lo, span, key_bits, j, L, self.curve)
                 k, i = sort(k, self.dict)
                 self.keys[s, j] = k
                 self.ids[s, j] = i
+
+        _pool_map(subset_curves, range(self.S), threads)
+        for s in range(self.S):
+            for j in range(L):
+                self._curves[(s, j)] = (self.keys[s, j], self.ids[s, j])
+        self._struct = None
+
+    def attach_curve(self, s, j, lo, span, sorted_keys, sorted_ids):
+        """Attach one sorted curve of subset s (grid origin lo, span) to an
+        index built with build_curves=False. The caller must have shown the
+        arrays to be this index's own: strictly increasing in (key, id), a
+        permutation of the dictionary, and every key equal to the key this
+        oracle computes for that id; sorting is then unique, so they equal
+        what sort() would return."""
+        k = _c(sorted_keys, np.uint64).reshape(self.n, self.W64)
+        i = _c(sorted_ids, np.int64)
+        assert i.size == self.n
+        self.lo[s], self.span[s] = _c(lo, np.int64), int(span)
+        self._curves[(s, j)] = (k, i)
+        self._struct = None
+
+    def drop_curves(self):
+        self._curves = {}
         self._struct = None
 
     def struct(self):
@@ -383,8 +485,18 @@ class Index:
                 self._pixa[s, :p.size] = p
             self._basis = np.concatenate([w.ravel() for w in self.bases]).astype(np.int8)
             self._boff = np.cumsum([0] + [w.size for w in self.bases[:-1]]).astype(np.int64)
-            self._lo = np.ascontiguousarray(np.stack(self.lo), dtype=np.int64)
-            self._span = np.array(self.span, dtype=np.int64)
+            self._lo = np.zeros((self.S, self.D), dtype=np.int64)
+            self._span = np.ones(self.S, dtype=np.int64)
+            for s_ in range(self.S):
+                if self.lo[s_] is not None:
+                    self._lo[s_] = self.lo[s_]
+                    self._span[s_] = self.span[s_]
+            nc = self.S * self.L
+            self._kp = (C.c_void_p * nc)()
+            self._ip = (C.c_void_p * nc)()
+            for (s_, j), (k, i) in self._curves.items():
+                self._kp[s_ * self.L + j] = k.ctypes.data
+                self._ip[s_ * self.L + j] = i.ctypes.data
             st = OrcIndex()
             st.nd = self.nd
             for i, v in enumerate(self.shape):
@@ -397,7 +509,8 @@ class Index:
             st.basis, st.basis_off = _p(self._basis), _p(self._boff)
             st.lo, st.span = _p(self._lo), _p(self._span)
             st.sum, st.nsub = _p(self.sum), self.nsub
-            st.keys, st.ids = _p(self.keys), _p(self.ids)
+            st.keys = C.cast(self._kp, C.c_void_p)
+            st.ids = C.cast(self._ip, C.c_void_p)
             st.norm = self.norm
             self._struct = st
         return self._struct
@@ -415,11 +528,22 @@ class Index:
             ys[q] = buf[:self.D]
         return sub, ys
 
+    def _check_curves(self, m, curves):
+        """Every query's subset must have the curves the query reads."""
+        if len(self._curves) == self.S * self.L:
+            return
+        for q in range(m.shape[0]):
+            s = choose_subset(self.pix, m[q])
+            for j in curves:
+                if (s, j) not in self._curves:
+                    raise ValueError(f"query {q} needs curve ({s}, {j}), which is not attached")
+
     def query(self, volume, t, m):
         """Returns (best_id, best_cost, candidates [Q, L*W] padded -1,
         ncand [Q], subset [Q])."""
         volume = _c(volume, np.float32)
         t, m = _c(t, np.float32), _c(m, np.uint8)
+        self._check_curves(m, range(self.L))
         Q = m.shape[0]
         cap = self.L * self.window
         bi = np.empty(Q, dtype=np.int64)
@@ -437,6 +561,7 @@ class Index:
         -1, ncand [Q])."""
         volume = _c(volume, np.float32)
         t, m = _c(t, np.float32), _c(m, np.uint8)
+        self._check_curves(m, [0])
         Q = m.shape[0]
         bi = np.empty(Q, dtype=np.int64)
         bc = np.empty(Q, dtype=np.float32)

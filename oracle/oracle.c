@@ -22,6 +22,7 @@
  *
  * Parity status per function is stated in each header comment.
  */
+#define _GNU_SOURCE   /* qsort_r */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -730,32 +731,34 @@ void orc_keys(const int64_t *y, int64_t n, int D, const int64_t *lo, int64_t spa
     }
 }
 
-static int g_sort_w64;
-static const uint64_t *g_sort_keys;
-static const int64_t *g_sort_ids;
+typedef struct {
+    int w64;
+    const uint64_t *keys;
+    const int64_t *ids;
+} sort_ctx;
 
-static int cmp_entry(const void *pa, const void *pb)
+static int cmp_entry(const void *pa, const void *pb, void *arg)
 {
+    const sort_ctx *cx = (const sort_ctx *)arg;
     int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
-    for (int w = 0; w < g_sort_w64; w++) {
-        uint64_t ka = g_sort_keys[a * g_sort_w64 + w], kb = g_sort_keys[b * g_sort_w64 + w];
+    for (int w = 0; w < cx->w64; w++) {
+        uint64_t ka = cx->keys[a * cx->w64 + w], kb = cx->keys[b * cx->w64 + w];
         if (ka != kb) return ka < kb ? -1 : 1;
     }
-    if (g_sort_ids[a] != g_sort_ids[b]) return g_sort_ids[a] < g_sort_ids[b] ? -1 : 1;
+    if (cx->ids[a] != cx->ids[b]) return cx->ids[a] < cx->ids[b] ? -1 : 1;
     return 0;
 }
 
 /* Sort a curve's entries by (key, id) ascending (Section II.C sorts the
  * dictionary by curve position; ids are unique, so the order is total).
- * keys [n][W64] and ids [n] are permuted in place. */
+ * keys [n][W64] and ids [n] are permuted in place. Reentrant: independent
+ * curves may be sorted from several threads at once. */
 void orc_sort(uint64_t *keys, int64_t *ids, int64_t n, int W64)
 {
     int64_t *perm = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
     for (int64_t i = 0; i < n; i++) perm[i] = i;
-    g_sort_w64 = W64;
-    g_sort_keys = keys;
-    g_sort_ids = ids;
-    qsort(perm, (size_t)n, sizeof(int64_t), cmp_entry);
+    sort_ctx cx = { W64, keys, ids };
+    qsort_r(perm, (size_t)n, sizeof(int64_t), cmp_entry, &cx);
     uint64_t *k2 = malloc(sizeof(uint64_t) * (n > 0 ? n : 1) * W64);
     int64_t *i2 = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
     for (int64_t i = 0; i < n; i++) {
@@ -787,8 +790,8 @@ typedef struct {
     const int64_t *span;          /* [S] */
     const int64_t *sum;           /* [P] subsample sums (for the mean) */
     int64_t nsub;
-    const uint64_t *keys;         /* [S][L][n][W64] */
-    const int64_t *ids;           /* [S][L][n] */
+    const uint64_t *const *keys;  /* [S*L] pointers, curve (s, j) at s*L + j: [n][W64] sorted */
+    const int64_t *const *ids;    /* [S*L] pointers, curve (s, j): [n] ids in the same order */
     int norm;                     /* cost of the rescoring: 0 L2, 1 L1 */
 } orc_index;
 
@@ -969,8 +972,8 @@ int64_t orc_query_one(const orc_index *ix, const float *vol, const float *t,
     for (int j = 0; j < ix->L; j++) {
         cell_of_real(yq, ix->D, ix->lo + sb * ix->D, ix->span[sb], R, j, v);
         orc_key_of(v, ix->D, ix->b, ix->curve, qk);
-        const uint64_t *keys = ix->keys + ((int64_t)(sb * ix->L + j) * ix->n) * W64;
-        const int64_t *ids = ix->ids + (int64_t)(sb * ix->L + j) * ix->n;
+        const uint64_t *keys = ix->keys[sb * ix->L + j];
+        const int64_t *ids = ix->ids[sb * ix->L + j];
         int64_t lo = orc_window(keys, ix->n, W64, qk, ix->window, NULL);
         int64_t hi = lo + ix->window;
         if (hi > ix->n) hi = ix->n;
@@ -1057,8 +1060,8 @@ int64_t orc_knn_one(const orc_index *ix, const float *vol, const float *t, const
     query_coords(ix, t, m, sb, yq);
     uint32_t u[64], v[64];
     cell_of_real(yq, ix->D, ix->lo + sb * ix->D, ix->span[sb], R, 0, u);
-    const uint64_t *keys = ix->keys + ((int64_t)(sb * ix->L) * ix->n) * W64;
-    const int64_t *ids = ix->ids + (int64_t)(sb * ix->L) * ix->n;
+    const uint64_t *keys = ix->keys[sb * ix->L];
+    const int64_t *ids = ix->ids[sb * ix->L];
     dist_id *all = malloc(sizeof(dist_id) * (size_t)ix->n);
     for (int64_t i = 0; i < ix->n; i++) {
         orc_morton_decode(keys + i * W64, ix->D, ix->b, v);

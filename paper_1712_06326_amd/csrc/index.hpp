@@ -86,6 +86,8 @@ struct sfc_index {
     int32_t* elem_off = nullptr;     // [Pp] element offset relative to centre*C
     int8_t* basis = nullptr;         // [S][mmax][D] int8
     int64_t* wtw = nullptr;          // [S][D][D] W^T W
+    int64_t* ws = nullptr;           // [S][D] W^T S (subsample sums)
+    uint64_t* smask = nullptr;       // [S][ceil(Kd/64)] subset pixel bit masks
     int64_t* lo = nullptr;           // [S][D]
     int64_t* span = nullptr;         // [S]
     uint64_t* keys = nullptr;        // [S][L][W64][n] sorted key words (one array per word)

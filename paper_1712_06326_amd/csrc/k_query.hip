@@ -24,85 +24,144 @@ sfc_status launched(const char* what) {
 }
 
 // ------------------------------------------------------------ prologue
-// One thread per query. Subset: the largest known fraction k_s/n_s, compared
-// exactly as k_a*n_b > k_b*n_a, ties to the lower subset. Coordinates: the
-// known elements enter exactly (A = W_k^T x_k); unknown ones are imputed from
-// the principal-component model fitted to the known ones by least squares:
-//   G = W^T W - W_u^T W_u + I,  r = W_k^T (n_sub x_k - S_k)   (integers)
-//   G z = r by Gaussian elimination without pivoting (float64, column by
-//   column, then back substitution),
-//   y_d = A_d + (B_d + sum_e H_de z_e) / n_sub,  B = W_u^T S_u,  H = W_u^T W_u.
-template <int D>
-__global__ __launch_bounds__(64) void prologue_kernel(QueryIndexView v, const float* __restrict__ t,
-                                                      const uint8_t* __restrict__ m, int64_t Q,
-                                                      int32_t* __restrict__ qsub,
-                                                      double* __restrict__ qcoords,
-                                                      uint64_t* __restrict__ qkeys) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= Q) return;
-    const uint8_t* mq = m + q * v.Kd;
-    const float* tq = t + q * v.Kd * v.C;
+// G lanes per query, 256/G queries per workgroup.
+//  1. The target's known pixels as a bit set (Kd <= 1024 bits), built with
+//     ballots, G pixels per step.
+//  2. Subset: the largest known fraction k_s/n_s, compared exactly as
+//     k_a*n_b > k_b*n_a, ties to the lower subset; k_s is the popcount of the
+//     known bits under the subset's pixel mask.
+//  3. Over the subset's known elements, spread across the lanes: the exact
+//     integer sums A = W_k^T x_k, T = W_k^T S_k and G_k = W_k^T W_k (upper
+//     triangle), reduced across the group (integer sums: any order).
+//  4. The least-squares imputation of the unknown elements, from
+//       G z = r,  G = G_k + I,  r = n_sub A - T           (integers)
+//     by Gaussian elimination without pivoting in float64 (column by
+//     column, then back substitution), and
+//       y_d = A_d + (B_d + sum_e H_de z_e) / n_sub,
+//       B = W^T S - T = W_u^T S_u,  H = W^T W - G_k = W_u^T W_u.
+//     Every lane of the group computes this in the same order (no lane
+//     exchanges in float64).
+//  5. The grid cell, then one key per shifted curve (lane j: curve j).
+constexpr int kPrologueLanes = 16;
+constexpr int kMaxKnownWords = 16;   // K^nd <= 1024
+constexpr int kMaxSubsets = 26;      // 3^3 - 1
+
+template <int D, int G>
+__global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const float* __restrict__ t,
+                                                       const uint8_t* __restrict__ m, int64_t Q,
+                                                       int32_t* __restrict__ qsub,
+                                                       double* __restrict__ qcoords,
+                                                       uint64_t* __restrict__ qkeys) {
+    static_assert(64 % G == 0 && G >= 4, "a group of lanes lies inside one wave");
+    constexpr int NG = 256 / G;
+    constexpr int NT = D * (D + 1) / 2;
+    __shared__ uint64_t known_bits[NG][kMaxKnownWords];
+    __shared__ int32_t known_cnt[NG][kMaxSubsets];
+    const int lane = threadIdx.x & 63;
+    const int grp = threadIdx.x / G;
+    const int gl = threadIdx.x % G;
+    const int64_t q = (int64_t)blockIdx.x * NG + grp;
+    const bool live = q < Q;
+    // a group past the end shadows the last query (every lane takes part in
+    // the ballots) and stores nothing
+    const int64_t qq = live ? q : Q - 1;
+    const uint8_t* mq = m + qq * v.Kd;
+    const float* tq = t + qq * (int64_t)v.Kd * v.C;
+    const int KW = (v.Kd + 63) >> 6;
+    const int gshift = (lane / G) * G;
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+
+    // 1. known bits
+    for (int w = 0; w < KW; w++) {
+        uint64_t word = 0;
+        for (int sub = 0; sub < 64; sub += G) {
+            const int p = w * 64 + sub + gl;
+            const bool k = p < v.Kd && mq[p] != 0;
+            word |= ((__ballot(k) >> gshift) & gmask) << sub;
+        }
+        if (gl == 0) known_bits[grp][w] = word;
+    }
+    __syncthreads();
+
+    // 2. subset choice
+    for (int s = gl; s < v.S; s += G) {
+        int k = 0;
+        for (int w = 0; w < KW; w++) k += __popcll(known_bits[grp][w] & v.smask[s * KW + w]);
+        known_cnt[grp][s] = k;
+    }
+    __syncthreads();
     int sb = 0;
     int64_t kb = -1, nbest = 1;
     for (int s = 0; s < v.S; s++) {
-        const int ns = v.npix[s];
-        int64_t k = 0;
-        for (int i = 0; i < ns; i++) k += mq[v.pix[s * v.Kd + i]] ? 1 : 0;
+        const int64_t k = known_cnt[grp][s], ns = v.npix[s];
         if (kb < 0 || k * nbest > kb * ns) {
             sb = s;
             kb = k;
             nbest = ns;
         }
     }
-    const float vmin = v.qparams[0], sc = v.qparams[1];
-    int64_t A[D], B[D], r[D], H[D][D];
+
+    // 3. exact sums over the known elements
+    int32_t A[D], Gk[NT];
+    int64_t T[D];
 #pragma unroll
     for (int d = 0; d < D; d++) {
         A[d] = 0;
-        B[d] = 0;
-        r[d] = 0;
-#pragma unroll
-        for (int f = 0; f < D; f++) H[d][f] = 0;
+        T[d] = 0;
     }
+#pragma unroll
+    for (int i = 0; i < NT; i++) Gk[i] = 0;
+    const float vmin = v.qparams[0], sc = v.qparams[1];
     const int8_t* wb = v.basis + (int64_t)sb * v.mmax * D;
-    int row = 0;
-    for (int i = 0; i < v.npix[sb]; i++) {
+    const int np = v.npix[sb];
+    for (int i = gl; i < np; i += G) {
         const int rho = v.pix[sb * v.Kd + i];
-        const bool known = mq[rho] != 0;
-        for (int ch = 0; ch < v.C; ch++, row++) {
+        if (!((known_bits[grp][rho >> 6] >> (rho & 63)) & 1ull)) continue;
+        for (int ch = 0; ch < v.C; ch++) {
             const int e = rho * v.C + ch;
-            int64_t w[D];
+            float rr = __builtin_rintf((tq[e] - vmin) * sc);
+            if (!(rr >= 0.0f)) rr = 0.0f;
+            if (rr > 255.0f) rr = 255.0f;
+            const int32_t x = (int32_t)rr;
+            const int64_t se = (int64_t)v.sum[e];
+            const int8_t* wr = wb + (int64_t)(i * v.C + ch) * D;
+            int32_t w[D];
 #pragma unroll
-            for (int d = 0; d < D; d++) w[d] = wb[row * D + d];
-            if (known) {
-                float rr = __builtin_rintf((tq[e] - vmin) * sc);
-                if (!(rr >= 0.0f)) rr = 0.0f;
-                if (rr > 255.0f) rr = 255.0f;
-                const int64_t x = (int64_t)rr;
-                const int64_t c = v.nsub * x - (int64_t)v.sum[e];
+            for (int d = 0; d < D; d++) w[d] = wr[d];
+            int k = 0;
 #pragma unroll
-                for (int d = 0; d < D; d++) {
-                    A[d] += w[d] * x;
-                    r[d] += w[d] * c;
-                }
-            } else {
-                const int64_t se = (int64_t)v.sum[e];
+            for (int d = 0; d < D; d++) {
+                A[d] += w[d] * x;
+                T[d] += (int64_t)w[d] * se;
 #pragma unroll
-                for (int d = 0; d < D; d++) {
-                    B[d] += w[d] * se;
-#pragma unroll
-                    for (int f = 0; f < D; f++) H[d][f] += w[d] * w[f];
-                }
+                for (int f = d; f < D; f++) Gk[k++] += w[d] * w[f];
             }
         }
     }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            A[d] += __shfl_xor(A[d], off, 64);
+            T[d] += (int64_t)__shfl_xor((long long)T[d], off, 64);
+        }
+#pragma unroll
+        for (int i = 0; i < NT; i++) Gk[i] += __shfl_xor(Gk[i], off, 64);
+    }
+
+    // 4. imputation in float64, the oracle's order
     const int64_t* wtw = v.wtw + (int64_t)sb * D * D;
+    const int64_t* ws = v.ws + (int64_t)sb * D;
     double a[D][D], rr[D], z[D];
 #pragma unroll
     for (int d = 0; d < D; d++) {
 #pragma unroll
-        for (int f = 0; f < D; f++) a[d][f] = (double)(wtw[d * D + f] - H[d][f] + (d == f ? 1 : 0));
-        rr[d] = (double)r[d];
+        for (int f = 0; f < D; f++) {
+            const int lo = d < f ? d : f, hi = d < f ? f : d;
+            const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+            a[d][f] = (double)((int64_t)Gk[k] + (d == f ? 1 : 0));
+        }
+        rr[d] = (double)(v.nsub * (int64_t)A[d] - T[d]);
     }
 #pragma unroll
     for (int k = 0; k < D; k++)
@@ -123,14 +182,23 @@ __global__ __launch_bounds__(64) void prologue_kernel(QueryIndexView v, const fl
     double y[D];
 #pragma unroll
     for (int d = 0; d < D; d++) {
-        double f = (double)B[d];
+        double f = (double)(ws[d] - T[d]);
 #pragma unroll
-        for (int e = 0; e < D; e++) f = f + (double)H[d][e] * z[e];
+        for (int e = 0; e < D; e++) {
+            const int lo = d < e ? d : e, hi = d < e ? e : d;
+            const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+            f = f + (double)(wtw[d * D + e] - (int64_t)Gk[k]) * z[e];
+        }
         y[d] = (double)A[d] + f / (double)v.nsub;
-        qcoords[q * D + d] = y[d];
     }
-    qsub[q] = sb;
-    // grid cell and one key per shifted curve
+    if (!live) return;
+    if (gl == 0) {
+        qsub[q] = sb;
+#pragma unroll
+        for (int d = 0; d < D; d++) qcoords[q * D + d] = y[d];
+    }
+
+    // 5. grid cell and one key per shifted curve
     const double span = (double)v.span[sb];
     const double rm1 = (double)(v.R - 1);
     uint32_t u[D], cell[D];
@@ -141,7 +209,7 @@ __global__ __launch_bounds__(64) void prologue_kernel(QueryIndexView v, const fl
         if (uu > rm1) uu = rm1;
         u[d] = (uint32_t)(int64_t)uu;
     }
-    for (int j = 0; j < v.L; j++) {
+    for (int j = gl; j < v.L; j += G) {
         const uint32_t sh = (uint32_t)(((int64_t)j * v.R) / (D + 1));
 #pragma unroll
         for (int d = 0; d < D; d++) cell[d] = u[d] + sh;
@@ -694,7 +762,7 @@ using RescoreFn = void (*)(QueryIndexView, const float*, const float*, const uin
                            int64_t*, int32_t*);
 
 template <int D>
-PrologueFn prologue_fn() { return prologue_kernel<D>; }
+PrologueFn prologue_fn() { return prologue_kernel<D, kPrologueLanes>; }
 
 using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
                        const uint32_t*, const int32_t*, const int32_t*, int, int64_t, int64_t*,
@@ -743,8 +811,10 @@ sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const 
     case 16: fn = prologue_fn<16>(); break;
     default: return fail(SFC_EUNSUPPORTED, "index query: reduced dimension not in {1..12, 16}");
     }
-    hipLaunchKernelGGL(fn, dim3(blocks_for(Q, 64)), dim3(64), 0, st, v, t, m, Q, qsub, qcoords,
-                       qkeys);
+    if (v.Kd > 64 * kMaxKnownWords || v.S > kMaxSubsets)
+        return fail(SFC_EUNSUPPORTED, "index query: more than 1024 pixels or 26 subsets per patch");
+    hipLaunchKernelGGL(fn, dim3(blocks_for(Q, 256 / kPrologueLanes)), dim3(256), 0, st, v, t, m, Q,
+                       qsub, qcoords, qkeys);
     return launched("prologue_kernel");
 }
 

@@ -15,6 +15,8 @@ struct QueryIndexView {
     const int32_t* pix;        // [S][Kd]
     const int8_t* basis;       // [S][mmax][D]
     const int64_t* wtw;        // [S][D][D] = W^T W (exact)
+    const int64_t* ws;         // [S][D] = W^T S, S the subsample sums (exact)
+    const uint64_t* smask;     // [S][ceil(Kd/64)] pixel bit mask of each subset
     const uint64_t* sum;       // [P] subsample sums
     const int64_t* lo;         // [S][D]
     const int64_t* span;       // [S]

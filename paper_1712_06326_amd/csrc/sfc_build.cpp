@@ -99,6 +99,20 @@ __global__ void wtw_kernel(const int8_t* __restrict__ basis, const int32_t* __re
     wtw[i] = acc;
 }
 
+// ws[s][d] = sum over the subset's elements r of w[r][d] * sum[elem r]
+__global__ void basis_sums_kernel(const int8_t* __restrict__ basis, const int32_t* __restrict__ msz,
+                                  const int32_t* __restrict__ elems,
+                                  const uint64_t* __restrict__ sum, int S, int mmax, int D,
+                                  int64_t* __restrict__ ws) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * D) return;
+    const int s = i / D, d = i % D;
+    const int8_t* w = basis + (int64_t)s * mmax * D;
+    int64_t acc = 0;
+    for (int r = 0; r < msz[s]; r++) acc += (int64_t)w[r * D + d] * (int64_t)sum[elems[s * mmax + r]];
+    ws[i] = acc;
+}
+
 __global__ void zero_bytes_kernel(uint8_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -157,6 +171,8 @@ QueryIndexView view_of(const sfc_index* ix) {
     v.pix = ix->pix;
     v.basis = ix->basis;
     v.wtw = ix->wtw;
+    v.ws = ix->ws;
+    v.smask = ix->smask;
     v.sum = reinterpret_cast<const uint64_t*>(ix->sum);
     v.lo = ix->lo;
     v.span = ix->span;
@@ -271,8 +287,8 @@ sfc_status ensure_elem_offsets(sfc_index* ix) {
 
 void release_sfc(sfc_index* ix) {
     void* ps[] = {ix->xq, ix->sum, ix->npix, ix->pix, ix->basis, ix->lo, ix->span, ix->keys,
-                  ix->ids, ix->proj_w, ix->wtw, ix->qparams, ix->elems, ix->msz, ix->elem_off,
-                  ix->mfma_B, ix->mask_copy};
+                  ix->ids, ix->proj_w, ix->wtw, ix->ws, ix->smask, ix->qparams, ix->elems,
+                  ix->msz, ix->elem_off, ix->mfma_B, ix->mask_copy};
     for (void* p : ps) dev_free(p);
     ix->xq = nullptr;
     ix->keys = nullptr;
@@ -285,6 +301,10 @@ sfc_status basis_products(sfc_index* ix, hipStream_t st) {
     const int S = ix->S, D = ix->D, mmax = ix->mmax, P = ix->g.Kd * ix->g.C;
     SFC_TRY(dev_alloc((void**)&ix->wtw, (size_t)S * D * D * 8, "basis gram"));
     wtw_kernel<<<(S * D * D + 255) / 256, 256, 0, st>>>(ix->basis, ix->msz, S, mmax, D, ix->wtw);
+    SFC_HIP(hipGetLastError());
+    SFC_TRY(dev_alloc((void**)&ix->ws, (size_t)S * D * 8, "basis sums"));
+    basis_sums_kernel<<<(S * D + 255) / 256, 256, 0, st>>>(
+        ix->basis, ix->msz, ix->elems, reinterpret_cast<const uint64_t*>(ix->sum), S, mmax, D, ix->ws);
     SFC_HIP(hipGetLastError());
 
     // projection weights (int8) and their column sums
@@ -367,6 +387,14 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
         for (int i = g.nd - 1; i >= 0; i--, rho /= g.K) off += (int64_t)(rho % g.K - g.h) * g.stride[i];
         eoff[e] = (int32_t)(off * C + e % C);
     }
+    const int KW = (g.Kd + 63) / 64;
+    std::vector<uint64_t> smask((size_t)S * KW, 0);
+    for (int s = 0; s < S; s++)
+        for (int i = 0; i < ix->h_npix[s]; i++) {
+            const int rho = ix->h_pix[(size_t)s * g.Kd + i];
+            smask[(size_t)s * KW + rho / 64] |= 1ull << (rho % 64);
+        }
+    SFC_TRY(upload(&ix->smask, smask, "subset pixel masks", st));
     SFC_TRY(upload(&ix->npix, ix->h_npix, "subset sizes", st));
     SFC_TRY(upload(&ix->pix, ix->h_pix, "subset pixels", st));
     SFC_TRY(upload(&ix->elems, elems, "subset elements", st));

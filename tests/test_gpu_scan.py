@@ -116,23 +116,31 @@ def test_scan_determinism_over_tile_shapes(h, w, c, K):
 
 
 def test_scan_config2_sampled():
-    """Config 2 at full size (n ~ 1e6), all front queries scanned in one
-    launch; a seeded sample is checked against the oracle."""
+    """Config 2 at full size (n ~ 0.9e6), all front queries scanned in one
+    launch as the benchmark does; the front, every target and the dictionary
+    equal the oracle's, and 256 seeded queries equal the oracle's full scan."""
+    import os
     nat = need_gpu()
     say("scan config2: generating")
     d = synth.config2()
     vol, mask = d["volume"], d["mask"]
     vd, md = dev(vol), dev(mask)
     f = nat.fill_front(md)
+    fo = oracle.front(mask)
+    assert np.array_equal(host(f), fo)
     t, m = nat.extract_targets(vd, md, 9, f)
+    to, mo = oracle.extract(vol, mask, 9, fo)
+    assert np.array_equal(host(m), mo) and np.array_equal(host(t), to)
+    do = oracle.dictionary(mask, 9)
     ix = nat.Index(vd, md, 9)
+    assert np.array_equal(host(ix.dictionary()), do)
     say(f"scan config2: n={ix.info.n} Q={f.numel()}")
     bi, bc = ix.query(t, m)
     bi, bc = host(bi), host(bc)
     rng = np.random.default_rng(2)
-    sel = np.sort(rng.choice(f.numel(), 6, replace=False))
-    do = host(ix.dictionary())
-    to, mo = host(t)[sel], host(m)[sel]
-    boi, boc = oracle.brute(vol, mask.shape, 9, do, to, mo)
+    sel = np.sort(rng.choice(fo.size, 256, replace=False))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    boi, boc = oracle.brute_pooled(vol, mask.shape, 9, do, to[sel], mo[sel], threads)
     assert np.array_equal(bi[sel], boi)
     assert np.array_equal(bc[sel].view(np.uint32), boc.view(np.uint32))
+    say("scan config2: 256 sampled queries equal the oracle's full scan")
