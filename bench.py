@@ -53,6 +53,16 @@ WORKLOADS = {
 }
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -111,6 +121,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-n1e8", action="store_true", help="skip the n~1.25e8 pass")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-images pass")
+    ap.add_argument("--no-inpaint", action="store_true", help="skip the whole-inpainting runs")
     ap.add_argument("--cpu-sample", type=int, default=48, help="oracle full-scan queries timed")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 512 MiB device copy (HBM counter calibration)")
@@ -188,7 +199,7 @@ def main():
         kz = min(1024, w.Q)
         sz = torch.from_numpy(np.sort(np.random.default_rng(3).choice(w.Q, kz, replace=False))).cuda()
         iz = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], **w.opts)
-        wz, window_trials = iz.autotune_window(tz[sz].contiguous(), mz[sz].contiguous(), 0.9)
+        wz, window_trials = iz.autotune_window(tz[sz].contiguous(), mz[sz].contiguous(), 0.9, -1.0)
         iz.close()
         del fz, tz, mz
         log(f"window autotuner: W={wz} reaches recall 0.9 on the sample")
@@ -230,6 +241,8 @@ def main():
     bi_x, bc_x = bi_x.cpu().numpy(), bc_x.cpu().numpy()
     bi_s, bc_s = res["bi_s"].cpu().numpy(), res["bc_s"].cpu().numpy()
     recall = float(np.mean(bi_x == bi_s))
+    # equal cost counts too: flat or repeated texture has several optimal patches
+    cost_recall = float(np.mean(bc_x.view(np.uint32) == bc_s.view(np.uint32)))
     ok = bc_s > 0
     ae = float(np.mean(np.sqrt(bc_x[ok].astype(np.float64)) / np.sqrt(bc_s[ok]) - 1.0)) * 100
 
@@ -273,6 +286,7 @@ def main():
         "index_window_trials": window_trials,
         "scan_queries": Qs,
         "index_recall_at_1_pct": round(100 * recall, 3),
+        "index_optimal_cost_pct": round(100 * cost_recall, 3),
         "index_acceleration_error_pct": round(ae, 4),
         "rooflines": {k: v for k, v in roofs.items() if k != dom},
     }
@@ -292,7 +306,11 @@ def main():
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": cfg["label"], "n": n, "queries": Q, "K": K,
+        "config": {"workload": cfg["label"],
+                   "step": "front + target extraction, index build, index query, float32 scan"
+                           + (", bf16 scan" if cfg["bf16"] else "")
+                           + " of every front target (value = front targets / step time)",
+                   "n": n, "queries": Q, "K": K,
                    "reduced_dim": cfg["D"], "n_curves": cfg["L"], "key_bits": cfg["key_bits"],
                    "window": cfg["window"], "curve": cfg["curve"]},
         "forms": forms,
@@ -320,6 +338,44 @@ def main():
             "acceleration_error_pct": round(float(np.mean(
                 np.sqrt(ck[ok].astype(np.float64)) / np.sqrt(bc_s[ok]) - 1.0)) * 100, 4)}
         log(f"k-NN query: {k_ms:.2f} ms for {Qs} queries")
+
+    # the brute-force reduced-precision form without an index seed: the
+    # two-pass bf16 filter (tile minima, then the tiles that can reach them)
+    if cfg["bf16"]:
+        ixb = native.Index(w.vol, w.mask, K, timing=True)
+        for _ in range(2):
+            a_ = ev()
+            bu, cu = ixb.query(res["t"], res["m"], "bf16")
+            b_ = ev()
+            torch.cuda.synchronize()
+        kb = ixb.kernel_times()
+        p1, p2 = ixb.filter_tiles()
+        fbu = ixb.fallbacks()
+        ixb.close()
+        kd = K ** w.mask_h.ndim
+        gemm1 = 2.0 * kd * (C + 2) * n * Qs
+        f_ms = sum(v[1] for k_, v in kb.items() if k_.startswith("filter_kernel"))
+        gemm = gemm1 * (1.0 + (p2 / p1 if p1 else 0.0))
+        forms["bf16_two_pass"] = {
+            "qps": round(Qs / (a_.elapsed_time(b_) * 1e-3), 1),
+            "kernel_ms": {k_: round(v[1] / v[0], 3) for k_, v in kb.items()},
+            "filter_tiles": [p1, p2], "fallback_queries": int(fbu),
+            "filter_tflops": round(gemm / (f_ms * 1e-3) / 1e12, 1),
+            "filter_frac_of_bf16_peak": round(gemm / (f_ms * 1e-3) / 1e12 / PEAK_BF16_MFMA, 4),
+            "work": "2 x K^d(C+2) x n x Q x (1 + pass-2 tiles / pass-1 tiles) flop",
+            "agreement_with_fp32_pct": round(100 * float(np.mean(
+                (bu.cpu().numpy() == bi_s) &
+                (cu.cpu().numpy().view(np.uint32) == bc_s.view(np.uint32)))), 3)}
+        log(f"bf16 two-pass: {forms['bf16_two_pass']['qps']} q/s")
+
+    # the index forms at the paper's quality acceptance (AE < 1 %)
+    if cfg.get("D"):
+        fq = native.fill_front(w.mask)
+        tq, mq = native.extract_targets(w.vol, w.mask, K, fq)
+        forms["index_at_ae_below_1pct"] = quality_point(torch, native, w, tq, mq, ev)
+        del fq, tq, mq
+        log(f"quality point: {forms['index_at_ae_below_1pct']['windowed'].get('window')} / "
+            f"{forms['index_at_ae_below_1pct']['knn'].get('k')}")
 
     # the L1 cost variant (Section III.K): the float32 scan of the same
     # targets under L1 (second run timed; 2 flops per known element and
@@ -355,6 +411,7 @@ def main():
         agree = float(np.mean((ob == bi_s[sel]) & (oc.view(np.uint32) == bc_s[sel].view(np.uint32))))
         line["cpu_baseline"] = {
             "value": round(k / cpu_s, 4), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": len(os.sched_getaffinity(0)),
             "sample": f"{k} seeded front queries of the same workload through the oracle's "
                       f"float32 full scan (n={n}), single thread, {cpu_s:.1f}s; index build "
                       f"and index queries excluded (under 0.1% of the oracle's per-query time)"}
@@ -387,6 +444,11 @@ def main():
         forms["l1_vs_oracle_agreement_pct"] = round(
             100 * float(np.mean((ob1 == bl_h) & (oc1.view(np.uint32) == cl_h.view(np.uint32)))), 2)
 
+    if args.workload == "config2" and not args.no_inpaint:
+        del res
+        torch.cuda.empty_cache()
+        line["inpaint"] = inpaint_pass(torch, native, synth)
+        res = None
     if args.workload == "config2" and not args.no_n1e8:
         del w, res
         torch.cuda.empty_cache()
@@ -395,6 +457,118 @@ def main():
         torch.cuda.empty_cache()
         line["batch"] = batch_pass(torch, native, synth, ev, 16, (256, 1024), 3, 1)
     print(json.dumps(line), flush=True)
+
+
+KNN_KS = (4, 8, 12, 16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256)
+
+
+def _accel_error(ci, cs):
+    """Section III.C's acceleration error (mean of sqrt(cost_index /
+    cost_scan) - 1 over targets with a nonzero scan cost), as a fraction."""
+    ok = cs > 0
+    return float(np.mean(np.sqrt(ci[ok].astype(np.float64)) / np.sqrt(cs[ok].astype(np.float64))
+                         - 1.0)) if ok.any() else 0.0
+
+
+def quality_point(torch, native, w, t, m, ev, sample=1024):
+    """Section III.D accepts an acceleration error below 1 %. On a seeded
+    sample of front targets: the smallest window W of the windowed query
+    (sfc_autotune_window with a 1 % target) and the smallest k of the exact
+    k-NN query (mu = 256) whose error is below 1 %, each with its query rate
+    over every front target (second run timed)."""
+    cfg, K = w.cfg, w.K
+    Q = int(m.shape[0])
+    k = min(sample, Q)
+    sel = torch.from_numpy(np.sort(np.random.default_rng(11).choice(Q, k, replace=False))).cuda()
+    ts, ms = t[sel].contiguous(), m[sel].contiguous()
+    out = {"sample": k, "accel_error_limit_pct": 1.0}
+    ix = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], **w.opts)
+    ref_i, ref_c = (a.cpu().numpy() for a in ix.query(ts, ms, "fp32"))
+    W, trials = ix.autotune_window(ts, ms, 0.0, 0.01)
+    hit = next((x for x in trials if x["accel_error"] < 0.01), None)
+    win = {"trials": [{"window": x["window"], "recall_pct": round(100 * x["recall"], 2),
+                       "accel_error_pct": round(100 * x["accel_error"], 4)} for x in trials]}
+    if hit is not None:
+        for _ in range(2):
+            a = ev()
+            ix.query(t, m, "index")
+            b = ev()
+            torch.cuda.synchronize()
+        ms_ = a.elapsed_time(b)
+        win.update(reached=True, window=W, candidates_per_query=W * cfg["L"],
+                   recall_pct=round(100 * hit["recall"], 2),
+                   accel_error_pct=round(100 * hit["accel_error"], 4),
+                   qps=round(Q / (ms_ * 1e-3), 1))
+    else:
+        last = trials[-1]
+        win.update(reached=False, largest_window=last["window"],
+                   accel_error_pct_at_largest=round(100 * last["accel_error"], 4))
+    out["windowed"] = win
+    knn = {"mu": 256, "trials": []}
+    if cfg["curve"] == "morton":
+        for kk in KNN_KS:
+            bk, ck = (a.cpu().numpy() for a in ix.knn(ts, ms, k=kk, mu=256))
+            ae = _accel_error(ck, ref_c)
+            knn["trials"].append({"k": kk, "recall_pct": round(100 * float(np.mean(bk == ref_i)), 2),
+                                  "accel_error_pct": round(100 * ae, 4)})
+            if ae < 0.01:
+                for _ in range(2):
+                    a = ev()
+                    ix.knn(t, m, k=kk, mu=256)
+                    b = ev()
+                    torch.cuda.synchronize()
+                ms_ = a.elapsed_time(b)
+                knn.update(reached=True, k=kk, recall_pct=knn["trials"][-1]["recall_pct"],
+                           accel_error_pct=round(100 * ae, 4), qps=round(Q / (ms_ * 1e-3), 1))
+                break
+        else:
+            knn.update(reached=False)
+    out["knn"] = knn
+    ix.close()
+    return out
+
+
+def inpaint_pass(torch, native, synth, names=("config1", "config2")):
+    """Whole inpainting runs (Section I's fill loop in Criminisi order, the
+    analogue of the paper's Table 2 on synthetic images): the device-resident
+    loop with the float32 full scan and with the SFC index (its build timed
+    apart), each on a fresh copy of the image."""
+    out = {}
+    for name in names:
+        cfg = WORKLOADS[name]
+        d = getattr(synth, cfg["gen"])()
+        vol0 = torch.from_numpy(d["volume"]).cuda()
+        mask0 = torch.from_numpy(d["mask"]).cuda()
+        K = cfg["K"]
+        row = {"unknown_voxels": int((d["mask"] == 0).sum()), "K": K}
+        for mode in ("fp32", "index"):
+            vol, mask = vol0.clone(), mask0.clone()
+            torch.cuda.synchronize()
+            ix = None
+            build_ms = 0.0
+            if mode == "index":
+                tb = time.perf_counter()
+                ix = native.Index(vol, mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"],
+                                  key_bits=cfg["key_bits"], window=cfg["window"], curve=cfg["curve"])
+                torch.cuda.synchronize()
+                build_ms = 1e3 * (time.perf_counter() - tb)
+            tl = time.perf_counter()
+            it, _ = native.inpaint(vol, mask, K, order="criminisi", mode=mode, index=ix)
+            torch.cuda.synchronize()
+            loop_ms = 1e3 * (time.perf_counter() - tl)
+            if ix is not None:
+                ix.close()
+            row[mode] = {"iterations": it, "loop_ms": round(loop_ms, 1),
+                         "ms_per_iteration": round(loop_ms / max(it, 1), 4)}
+            if mode == "index":
+                row[mode]["index_build_ms"] = round(build_ms, 1)
+                row[mode]["total_ms"] = round(loop_ms + build_ms, 1)
+            log(f"inpaint {name} {mode}: {it} iterations in {loop_ms:.0f} ms")
+        row["index_speedup_over_fp32_scan"] = round(row["fp32"]["loop_ms"] / row["index"]["total_ms"], 2)
+        out[name] = row
+        del vol0, mask0
+        torch.cuda.empty_cache()
+    return out
 
 
 def batch_pass(torch, native, synth, ev, n_images, sides, steps, warmup):
@@ -493,6 +667,7 @@ def large_pass(torch, native, synth, ev):
     kk = ix.kernel_times()
     knn_ms = sum(v[1] for v in kk.values())
     ix.close()
+    quality = quality_point(torch, native, w, t, m, ev)
     bx, cx = bi_x[w.sel].cpu().numpy(), bc_x[w.sel].cpu().numpy()
     bs, cs = bi_s.cpu().numpy(), bc_s.cpu().numpy()
     ok = cs > 0
@@ -506,6 +681,7 @@ def large_pass(torch, native, synth, ev):
            "fp32_scan_frac_of_fp32_peak": round(scan_tf / PEAK_FP32_VALU, 4),
            "fp32_scan_shape": shape,
            "index_recall_at_1_pct": round(100 * float(np.mean(bx == bs)), 3),
+           "index_optimal_cost_pct": round(100 * float(np.mean(cx.view(np.uint32) == cs.view(np.uint32))), 3),
            "index_acceleration_error_pct": round(
                float(np.mean(np.sqrt(cx[ok].astype(np.float64)) / np.sqrt(cs[ok]) - 1)) * 100, 4),
            "index_cost_never_below_scan": bool(np.all(cx >= cs)),
@@ -513,7 +689,8 @@ def large_pass(torch, native, synth, ev):
                          "recall_at_1_pct": round(100 * float(np.mean(bk.cpu().numpy() == bs)), 3),
                          "acceleration_error_pct": round(float(np.mean(
                              np.sqrt(ck.cpu().numpy()[ok].astype(np.float64)) / np.sqrt(cs[ok])
-                             - 1)) * 100, 4)}}
+                             - 1)) * 100, 4)},
+           "index_at_ae_below_1pct": quality}
     del w, t, m, ts, ms
     torch.cuda.empty_cache()
     return out

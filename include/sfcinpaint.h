@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define SFC_ABI_VERSION 1
+#define SFC_ABI_VERSION 2
 
 typedef enum {
     SFC_OK = 0,
@@ -77,10 +77,6 @@ typedef struct {
     int32_t key_bits;      /* b, bits per principal coordinate (1..31), default 8 */
     int32_t window;        /* W, candidates taken from each curve, default 32 */
     int32_t curve;         /* sfc_curve, default SFC_CURVE_MORTON */
-    int32_t rescore_top;   /* T, candidates rescored per query by the
-                              reduced-precision scans, default 16 */
-    int32_t certify;       /* 1 (default): a reduced-precision answer whose
-                              certificate fails is recomputed by the float32 scan */
     int32_t query_block;   /* queries per float32-scan workgroup, 0 = library choice */
     int32_t scan_variant;  /* float32-scan tile shape: 0 = default or the one
                               sfc_autotune chose, k >= 1 = the k-th shape */
@@ -168,8 +164,8 @@ sfc_status sfc_dictionary_build(const float *volume, const uint8_t *mask,
  * as sfc_dictionary_build. Errors: SFC_EINVAL for K even, K > a side,
  * reduced_dim < 1 or > a subset's element count, n_curves < 1 or >
  * reduced_dim + 1, key_bits * reduced_dim > 256; SFC_EUNSUPPORTED for a
- * subset with more than 518 elements (the eigensolver's bound) or more
- * than 2^32 voxels. */
+ * subset with more than 518 elements (the eigensolver's bound), n_curves *
+ * window above 2048, or more than 2^32 voxels. */
 sfc_status sfc_index_build(const float *volume, const uint8_t *mask, const sfc_geometry *g,
                            int32_t K, int32_t reduced_dim, int32_t n_curves,
                            const sfc_options *opt, sfc_index **out);
@@ -243,15 +239,19 @@ typedef struct {
 } sfc_window_trial;
 
 /* Window autotuner for SFC_MODE_INDEX: answers the targets with the float32
- * full scan, then with the index at W = 2, 4, 6, 8, 12, ..., 256 (while
- * n_curves * W <= 512), and keeps on the handle the smallest W whose recall
- * reaches target_recall (in [0, 1]; the largest W tried if none does).
- * *window_host receives it; the trials (up to capacity) go to trials_host and
- * their number to *count_host. The window is a query-time parameter: the
- * index itself is not rebuilt. Synchronises. */
+ * full scan, then with the index at W = 2, 4, 6, 8, 12, ..., 1024 (while
+ * n_curves * W <= 2048), and keeps on the handle the smallest W whose recall
+ * reaches target_recall (in [0, 1]) and whose acceleration error (Section
+ * III.C, as in sfc_window_trial) is at most max_accel_error (a fraction, so
+ * 0.01 for the paper's 1 %; a negative value drops this condition); the
+ * largest W tried if none qualifies. *window_host receives it; the trials
+ * (up to capacity) go to trials_host and their number to *count_host. The
+ * window is a query-time parameter: the index itself is not rebuilt.
+ * Synchronises. SFC_EINVAL for a NaN max_accel_error. */
 sfc_status sfc_autotune_window(sfc_index *idx, const float *targets, const uint8_t *target_masks,
-                               int64_t Q, float target_recall, sfc_window_trial *trials_host,
-                               int32_t capacity, int32_t *count_host, int32_t *window_host);
+                               int64_t Q, float target_recall, float max_accel_error,
+                               sfc_window_trial *trials_host, int32_t capacity,
+                               int32_t *count_host, int32_t *window_host);
 
 /* Statistics of the last sfc_query call on this handle (host values):
  * n_fallback = queries a reduced-precision scan could not certify. */

@@ -224,7 +224,6 @@ sfc_status validate_options(const sfc_options& o) {
     if (o.window < 1) return fail(SFC_EINVAL, "window must be >= 1");
     if (o.curve != SFC_CURVE_MORTON && o.curve != SFC_CURVE_HILBERT)
         return fail(SFC_EINVAL, "unknown curve");
-    if (o.rescore_top < 1 || o.rescore_top > 64) return fail(SFC_EINVAL, "rescore_top must be 1..64");
     if (o.query_block < 0) return fail(SFC_EINVAL, "query_block must be >= 0");
     if (o.norm != SFC_NORM_L2 && o.norm != SFC_NORM_L1) return fail(SFC_EINVAL, "unknown norm");
     return SFC_OK;
@@ -296,27 +295,30 @@ sfc_index::~sfc_index() {
 
 namespace sfc {
 
-sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
-                            uint64_t* best_dev) {
+sfc_status scan_fp32_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, uint32_t* rm,
+                        float* tp, uint64_t* best) {
     const Grid& g = ix->g;
     const int64_t qpad = scan_qpad(Q);
-    SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
-    uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
     SFC_TRY(launch_pack_rowmask(m, g, Q, rm, ix->st));
     // targets padded with zero rows up to the scan's query block
-    const size_t tbytes = (size_t)Q * g.Kd * g.C * sizeof(float);
-    const size_t pbytes = (size_t)qpad * g.Kd * g.C * sizeof(float);
-    SFC_TRY(ix->tpad.reserve(pbytes, "padded targets"));
-    float* tp = static_cast<float*>(ix->tpad.ptr);
-    SFC_HIP(hipMemcpyAsync(tp, t, tbytes, hipMemcpyDeviceToDevice, ix->st));
-    SFC_TRY(launch_zero_f32(tp + (size_t)Q * g.Kd * g.C, (int64_t)(qpad - Q) * g.Kd * g.C, ix->st));
-    SFC_TRY(launch_fill_u64(best_dev, Q, ~0ull, ix->st));
-    ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best_dev, ix->opt.query_block,
+    SFC_TRY(launch_pad_f32(t, (int64_t)Q * g.Kd * g.C, (int64_t)qpad * g.Kd * g.C, tp, ix->st));
+    SFC_TRY(launch_fill_u64(best, Q, ~0ull, ix->st));
+    ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best, ix->opt.query_block,
                ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant,
                ix->spans, ix->n_spans, ix->opt.norm};
     SFC_TRY(ix->timer.begin("scan_fp32_kernel", ix->st));
     SFC_TRY(launch_scan_fp32(g, a, ix->st));
     return ix->timer.end(ix->st);
+}
+
+sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
+                            uint64_t* best_dev) {
+    const Grid& g = ix->g;
+    const int64_t qpad = scan_qpad(Q);
+    SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
+    SFC_TRY(ix->tpad.reserve((size_t)qpad * g.Kd * g.C * sizeof(float), "padded targets"));
+    return scan_fp32_on(ix, t, m, Q, static_cast<uint32_t*>(ix->rowmask.ptr),
+                        static_cast<float*>(ix->tpad.ptr), best_dev);
 }
 
 }  // namespace sfc
@@ -338,8 +340,6 @@ void sfc_options_default(sfc_options* o) {
     o->key_bits = 8;
     o->window = 32;
     o->curve = SFC_CURVE_MORTON;
-    o->rescore_top = 16;
-    o->certify = 1;
     o->query_block = 0;
     o->stream = nullptr;
 }
@@ -786,8 +786,9 @@ sfc_status sfc_sort_pairs(uint64_t* keys, uint32_t* ids, int64_t n, int32_t key_
 }
 
 sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_t* target_masks,
-                               int64_t Q, float target_recall, sfc_window_trial* trials,
-                               int32_t capacity, int32_t* count, int32_t* window) {
+                               int64_t Q, float target_recall, float max_accel_error,
+                               sfc_window_trial* trials, int32_t capacity, int32_t* count,
+                               int32_t* window) {
     clear_error();
     if (!ix || !targets || !target_masks || !count || !window || (capacity > 0 && !trials))
         return fail(SFC_EINVAL, "null pointer");
@@ -795,6 +796,7 @@ sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_
     if (Q < 1) return fail(SFC_EINVAL, "window autotuning needs Q >= 1");
     if (!(target_recall >= 0.0f && target_recall <= 1.0f))
         return fail(SFC_EINVAL, "target_recall must be in [0, 1]");
+    if (std::isnan(max_accel_error)) return fail(SFC_EINVAL, "max_accel_error is NaN");
     ix->timer.reset(false);
     const int saved = ix->opt.window;
     std::vector<int64_t> ref_id(Q), got_id(Q);
@@ -821,12 +823,13 @@ sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_
             if (he != hipSuccess) s = check_hip(he, "autotune reference");
         }
     }
-    static const int kWindows[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    static const int kWindows[] = {2,  4,  6,   8,   12,  16,  24,  32,  48,
+                                   64, 96, 128, 192, 256, 384, 512, 768, 1024};
     int best_w = -1, largest = -1, n_trials = 0;
     float best_recall = 0.0f, largest_recall = 0.0f;
     for (int w : kWindows) {
         if (s != SFC_OK) break;
-        if ((int64_t)ix->L * w > 512) break;
+        if ((int64_t)ix->L * w > 2048) break;
         ix->opt.window = w;
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && s == SFC_OK; rep++) {   // the first run warms up
@@ -859,12 +862,13 @@ sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_
             }
         }
         const float recall = (float)hits / (float)Q;
-        if (n_trials < capacity)
-            trials[n_trials] = sfc_window_trial{w, recall, nz ? (float)(ae / nz) : 0.0f, ms};
+        const float mean_ae = nz ? (float)(ae / nz) : 0.0f;
+        if (n_trials < capacity) trials[n_trials] = sfc_window_trial{w, recall, mean_ae, ms};
         n_trials++;
         largest = w;
         largest_recall = recall;
-        if (best_w < 0 && recall >= target_recall) {
+        if (best_w < 0 && recall >= target_recall &&
+            (max_accel_error < 0.0f || mean_ae <= max_accel_error)) {
             best_w = w;
             best_recall = recall;
         }
@@ -875,7 +879,7 @@ sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_
     dev_free(d_cost);
     if (s != SFC_OK || largest < 0) {
         ix->opt.window = saved;
-        return s != SFC_OK ? s : fail(SFC_EUNSUPPORTED, "no window fits n_curves * window <= 512");
+        return s != SFC_OK ? s : fail(SFC_EUNSUPPORTED, "no window fits n_curves * window <= 2048");
     }
     if (best_w < 0) {
         best_w = largest;

@@ -73,6 +73,8 @@ sfc_status launch_valid_centres(const uint8_t* mask, const Grid& g, uint8_t* val
                                 uint8_t* tmp, hipStream_t st);
 sfc_status launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 sfc_status launch_zero_f32(float* p, int64_t n, hipStream_t st);
+// out[i] = in[i] for i < n, 0 for n <= i < npad
+sfc_status launch_pad_f32(const float* in, int64_t n, int64_t npad, float* out, hipStream_t st);
 sfc_status launch_u32_to_i64(const uint32_t* in, int64_t* out, int64_t n, hipStream_t st);
 
 // float32 full scan: best[q] = min over valid centres of (cost bits << 32 | id)

@@ -134,10 +134,20 @@ void release_sfc(sfc_index* ix);
 sfc_status code_checksum(sfc_index* ix, uint64_t* out_host);
 sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                             uint64_t* best_dev);
+// The float32 scan on caller buffers: rm [scan_qpad(Q) * rows] u32 row masks,
+// tp [scan_qpad(Q) * Kd * C] padded targets, best [Q] packed results. Every
+// word of the three is written before it is read.
+sfc_status scan_fp32_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, uint32_t* rm,
+                        float* tp, uint64_t* best);
 sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                                sfc_mode mode, int64_t* best_id, float* best_cost);
 sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                        int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
+// The index query on a caller buffer of index_query_bytes(ix, Q) bytes
+// (kernel launches only: no allocation, no synchronisation).
+size_t index_query_bytes(const sfc_index* ix, int64_t Q);
+sfc_status query_index_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, void* buf,
+                          int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
 sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                         int32_t* subset, double* coords);
 sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int k, int mu,

@@ -41,6 +41,11 @@ __global__ void extract_kernel(const float* __restrict__ vol, const uint8_t* __r
     if (i >= Q * g.Kd) return;
     int64_t q = i / g.Kd;
     int rho = (int)(i - q * g.Kd);
+    if (centres[q] < 0) {   // no target (an empty fill front): an all-unknown patch
+        m[i] = 0;
+        for (int ch = 0; ch < g.C; ch++) t[i * g.C + ch] = 0.0f;
+        return;
+    }
     int64_t c[kMaxDims];
     coords_of(g, centres[q], c);
     int64_t v = 0;
@@ -164,6 +169,12 @@ __global__ void zero_f32_kernel(float* p, int64_t n) {
     if (i < n) p[i] = 0.0f;
 }
 
+__global__ void pad_f32_kernel(const float* __restrict__ in, int64_t n, int64_t npad,
+                               float* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npad) out[i] = i < n ? in[i] : 0.0f;
+}
+
 __global__ void u32_to_i64_kernel(const uint32_t* __restrict__ in, int64_t* __restrict__ out,
                                   int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -261,6 +272,12 @@ sfc_status launch_zero_f32(float* p, int64_t n, hipStream_t st) {
     if (n <= 0) return SFC_OK;
     zero_f32_kernel<<<blocks_for(n), kBlock, 0, st>>>(p, n);
     return launched("zero_f32_kernel");
+}
+
+sfc_status launch_pad_f32(const float* in, int64_t n, int64_t npad, float* out, hipStream_t st) {
+    if (npad <= 0) return SFC_OK;
+    pad_f32_kernel<<<blocks_for(npad), kBlock, 0, st>>>(in, n, npad, out);
+    return launched("pad_f32_kernel");
 }
 
 sfc_status launch_u32_to_i64(const uint32_t* in, int64_t* out, int64_t n, hipStream_t st) {

@@ -56,6 +56,82 @@ __device__ inline Cand shfl_cand(const Cand& x, int off) {
     return y;
 }
 
+// The fill-order candidate of voxel v: (P, C, id) for a front voxel under
+// order 0 (Criminisi), (-C, 0, id) under order 1 (raster: only the id ranks,
+// C is carried for the confidence update); {-1, -1, max} otherwise.
+__device__ inline Cand voxel_cand(const float* __restrict__ vol, const uint8_t* __restrict__ mask,
+                                  const double* __restrict__ conf, const Grid& g, int order,
+                                  int64_t v) {
+    Cand best{-1.0, -1.0, INT64_MAX};
+    if (mask[v]) {
+        int64_t c[kMaxDims];
+        coords_of(g, v, c);
+        bool front = false;
+        for (int i = 0; i < g.nd; i++) {
+            if (c[i] > 0 && !mask[v - g.stride[i]]) front = true;
+            if (c[i] + 1 < g.shape[i] && !mask[v + g.stride[i]]) front = true;
+        }
+        if (front) {
+            double cs = 0.0;
+            for (int rho = 0; rho < g.Kd; rho++) {
+                int64_t u = 0;
+                bool inb = true;
+                int r = rho;
+                for (int a = g.nd - 1; a >= 0; a--) {
+                    const int64_t x = c[a] + (r % g.K) - g.h;
+                    r /= g.K;
+                    if (x < 0 || x >= g.shape[a]) inb = false;
+                    u += x * g.stride[a];
+                }
+                if (inb && mask[u]) cs += conf[u];
+            }
+            const double Cp = cs / (double)g.Kd;
+            if (order == 0) {
+                double gr[kMaxDims], nr[kMaxDims], nn = 0.0;
+                const double I0 = mean_intensity(vol, v, g.C);
+                for (int i = 0; i < g.nd; i++) {
+                    const bool hasp = c[i] + 1 < g.shape[i], hasm = c[i] > 0;
+                    const int64_t vp = v + g.stride[i], vm = v - g.stride[i];
+                    const bool kp = hasp && mask[vp], km = hasm && mask[vm];
+                    if (kp && km)
+                        gr[i] = (mean_intensity(vol, vp, g.C) - mean_intensity(vol, vm, g.C)) / 2.0;
+                    else if (kp)
+                        gr[i] = mean_intensity(vol, vp, g.C) - I0;
+                    else if (km)
+                        gr[i] = I0 - mean_intensity(vol, vm, g.C);
+                    else
+                        gr[i] = 0.0;
+                    const int ip = hasp ? mask[vp] : 1, im = hasm ? mask[vm] : 1;
+                    nr[i] = (double)(ip - im);
+                    nn += nr[i] * nr[i];
+                }
+                double Dp = 0.0;
+                if (nn > 0.0) {
+                    const double len = sqrt(nn);
+                    for (int i = 0; i < g.nd; i++) nr[i] = nr[i] / len;
+                    if (g.nd == 2) {
+                        Dp = fabs(gr[0] * nr[1] - gr[1] * nr[0]);
+                    } else {
+                        const double c0 = gr[1] * nr[2] - gr[2] * nr[1];
+                        const double c1 = gr[2] * nr[0] - gr[0] * nr[2];
+                        const double c2 = gr[0] * nr[1] - gr[1] * nr[0];
+                        Dp = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+                    }
+                }
+                best = Cand{Cp * Dp, Cp, v};
+            } else {
+                // raster: only the id ranks; keep Cp for the confidence update
+                best = Cand{-Cp, 0.0, v};   // carried, not compared (see reduce with order 1)
+            }
+        }
+    }
+    return best;
+}
+
+__device__ inline bool ranks_before(const Cand& a, const Cand& b, int order) {
+    return order == 0 ? better(a, b) : (a.id < b.id);
+}
+
 // Per block: the best front voxel by (P, C, -id) (order 0) or the lowest
 // front id (order 1, with P and C of that voxel), and the unknown count.
 __global__ __launch_bounds__(256) void priority_kernel(const float* __restrict__ vol,
@@ -67,73 +143,8 @@ __global__ __launch_bounds__(256) void priority_kernel(const float* __restrict__
     Cand best{-1.0, -1.0, INT64_MAX};
     int unk = 0;
     if (v < g.nvox) {
-        if (!mask[v]) {
-            unk = 1;
-        } else {
-            int64_t c[kMaxDims];
-            coords_of(g, v, c);
-            bool front = false;
-            for (int i = 0; i < g.nd; i++) {
-                if (c[i] > 0 && !mask[v - g.stride[i]]) front = true;
-                if (c[i] + 1 < g.shape[i] && !mask[v + g.stride[i]]) front = true;
-            }
-            if (front) {
-                double cs = 0.0;
-                for (int rho = 0; rho < g.Kd; rho++) {
-                    int64_t u = 0;
-                    bool inb = true;
-                    int r = rho;
-                    for (int a = g.nd - 1; a >= 0; a--) {
-                        const int64_t x = c[a] + (r % g.K) - g.h;
-                        r /= g.K;
-                        if (x < 0 || x >= g.shape[a]) inb = false;
-                        u += x * g.stride[a];
-                    }
-                    if (inb && mask[u]) cs += conf[u];
-                }
-                const double Cp = cs / (double)g.Kd;
-                double Pp = 0.0;
-                if (order == 0) {
-                    double gr[kMaxDims], nr[kMaxDims], nn = 0.0;
-                    const double I0 = mean_intensity(vol, v, g.C);
-                    for (int i = 0; i < g.nd; i++) {
-                        const bool hasp = c[i] + 1 < g.shape[i], hasm = c[i] > 0;
-                        const int64_t vp = v + g.stride[i], vm = v - g.stride[i];
-                        const bool kp = hasp && mask[vp], km = hasm && mask[vm];
-                        if (kp && km)
-                            gr[i] = (mean_intensity(vol, vp, g.C) - mean_intensity(vol, vm, g.C)) / 2.0;
-                        else if (kp)
-                            gr[i] = mean_intensity(vol, vp, g.C) - I0;
-                        else if (km)
-                            gr[i] = I0 - mean_intensity(vol, vm, g.C);
-                        else
-                            gr[i] = 0.0;
-                        const int ip = hasp ? mask[vp] : 1, im = hasm ? mask[vm] : 1;
-                        nr[i] = (double)(ip - im);
-                        nn += nr[i] * nr[i];
-                    }
-                    double Dp = 0.0;
-                    if (nn > 0.0) {
-                        const double len = sqrt(nn);
-                        for (int i = 0; i < g.nd; i++) nr[i] = nr[i] / len;
-                        if (g.nd == 2) {
-                            Dp = fabs(gr[0] * nr[1] - gr[1] * nr[0]);
-                        } else {
-                            const double c0 = gr[1] * nr[2] - gr[2] * nr[1];
-                            const double c1 = gr[2] * nr[0] - gr[0] * nr[2];
-                            const double c2 = gr[0] * nr[1] - gr[1] * nr[0];
-                            Dp = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-                        }
-                    }
-                    Pp = Cp * Dp;
-                    best = Cand{Pp, Cp, v};
-                } else {
-                    // raster: only the id ranks; keep Cp for the confidence update
-                    best = Cand{0.0, 0.0, v};
-                    best.p = -Cp;   // carried, not compared (see reduce with order 1)
-                }
-            }
-        }
+        if (!mask[v]) unk = 1;
+        else best = voxel_cand(vol, mask, conf, g, order, v);
     }
     // block reduction
     for (int off = 32; off > 0; off >>= 1) {
@@ -219,6 +230,199 @@ __global__ void fill_kernel(float* __restrict__ vol, uint8_t* __restrict__ mask,
     conf[up] = *cpick;
 }
 
+// ---- the device-resident loop: priorities kept per voxel and updated only
+// around the last filled box, block partials in two levels, loop state on
+// the device.
+
+// Best candidate of a 256-thread block (x valid in every thread).
+__device__ inline Cand block_best(Cand x, int order) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const Cand o = shfl_cand(x, off);
+        if (ranks_before(o, x, order)) x = o;
+    }
+    __shared__ Cand sb[4];
+    if ((threadIdx.x & 63) == 0) sb[threadIdx.x >> 6] = x;
+    __syncthreads();
+    Cand b = sb[0];
+    for (int w = 1; w < 4; w++)
+        if (ranks_before(sb[w], b, order)) b = sb[w];
+    return b;
+}
+
+__global__ __launch_bounds__(256) void cand_all_kernel(const float* __restrict__ vol,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const double* __restrict__ conf, Grid g,
+                                                       int order, Cand* __restrict__ pv) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < g.nvox) pv[v] = voxel_cand(vol, mask, conf, g, order, v);
+}
+
+// part[b] = best of src[256 b .. 256 b + 255] (src has n entries)
+__global__ __launch_bounds__(256) void part_all_kernel(const Cand* __restrict__ src, int64_t n,
+                                                       int order, Cand* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const Cand x = i < n ? src[i] : Cand{-1.0, -1.0, INT64_MAX};
+    const Cand b = block_best(x, order);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ void count_unknown_kernel(const uint8_t* __restrict__ mask, int64_t n,
+                                     LoopState* __restrict__ ls) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int u = (i < n && !mask[i]) ? 1 : 0;
+    const unsigned long long b = __ballot(u);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&ls->unknown, (unsigned long long)__popcll(b));
+}
+
+__global__ void loop_init_kernel(LoopState* ls) {
+    ls->unknown = 0;
+    ls->centre = -1;
+    ls->cpick = 0.0;
+    ls->source = -1;
+    ls->cost = 0.0f;
+    ls->last = -1;
+    ls->it = 0;
+}
+
+// The region whose candidates a fill at centre p can change: the box of
+// half-width K-1 around p (the confidence box sum of a voxel reaches h
+// around it, the filled box h around p; front status and gradients reach one
+// voxel around the filled box, and h + 1 <= K - 1 for K >= 3), clipped.
+// Line l of the region: its coordinates along the slower axes, and the id
+// range of its clipped extent along the fastest axis; false if the line is
+// outside the volume.
+__device__ inline bool region_line(const Grid& g, int64_t p, int64_t l, int64_t* id0, int64_t* id1) {
+    const int R = g.K - 1, side = 2 * R + 1;
+    int64_t c[kMaxDims];
+    coords_of(g, p, c);
+    int64_t base = 0;
+    for (int a = g.nd - 2; a >= 0; a--) {
+        const int64_t x = c[a] + (l % side) - R;
+        l /= side;
+        if (x < 0 || x >= g.shape[a]) return false;
+        base += x * g.stride[a];
+    }
+    const int f = g.nd - 1;
+    const int64_t x0 = c[f] - R < 0 ? 0 : c[f] - R;
+    const int64_t x1 = c[f] + R >= g.shape[f] ? g.shape[f] - 1 : c[f] + R;
+    *id0 = base + x0;
+    *id1 = base + x1;
+    return true;
+}
+
+__device__ inline int64_t region_lines(const Grid& g) {
+    int64_t n = 1;
+    for (int a = 0; a < g.nd - 1; a++) n *= 2 * g.K - 1;
+    return n;
+}
+
+// candidates of the region around the last filled centre; one workgroup per
+// region line, a thread per voxel of it (2K - 1 <= 256 for K <= 127)
+__global__ __launch_bounds__(256) void region_cand_kernel(const float* __restrict__ vol,
+                                                          const uint8_t* __restrict__ mask,
+                                                          const double* __restrict__ conf, Grid g,
+                                                          int order, const LoopState* __restrict__ ls,
+                                                          Cand* __restrict__ pv) {
+    const int64_t p = ls->last;
+    if (p < 0) return;
+    int64_t id0, id1;
+    if (!region_line(g, p, blockIdx.x, &id0, &id1)) return;
+    const int64_t v = id0 + threadIdx.x;
+    if (v <= id1) pv[v] = voxel_cand(vol, mask, conf, g, order, v);
+}
+
+// level-1 partials of the blocks of 256 voxels that a region line touches
+// (at most two per line); lines sharing a block write the same value
+__global__ __launch_bounds__(256) void region_part1_kernel(const Cand* __restrict__ pv, Grid g,
+                                                           int order, const LoopState* __restrict__ ls,
+                                                           Cand* __restrict__ part1) {
+    const int64_t p = ls->last;
+    if (p < 0) return;
+    int64_t id0, id1;
+    if (!region_line(g, p, blockIdx.x >> 1, &id0, &id1)) return;
+    const int64_t b = id0 / 256 + (blockIdx.x & 1);
+    if (b > id1 / 256) return;
+    const int64_t i = b * 256 + threadIdx.x;
+    const Cand x = i < g.nvox ? pv[i] : Cand{-1.0, -1.0, INT64_MAX};
+    const Cand best = block_best(x, order);
+    if (threadIdx.x == 0) part1[b] = best;
+}
+
+// level-2 partials over the level-1 blocks that changed
+__global__ __launch_bounds__(256) void region_part2_kernel(const Cand* __restrict__ part1,
+                                                           int64_t nb1, Grid g, int order,
+                                                           const LoopState* __restrict__ ls,
+                                                           Cand* __restrict__ part2) {
+    const int64_t p = ls->last;
+    if (p < 0) return;
+    int64_t id0, id1;
+    if (!region_line(g, p, blockIdx.x >> 1, &id0, &id1)) return;
+    const int64_t b = id0 / 256 + (blockIdx.x & 1);
+    if (b > id1 / 256) return;
+    const int64_t c = b / 256;
+    const int64_t i = c * 256 + threadIdx.x;
+    const Cand x = i < nb1 ? part1[i] : Cand{-1.0, -1.0, INT64_MAX};
+    const Cand best = block_best(x, order);
+    if (threadIdx.x == 0) part2[c] = best;
+}
+
+// the next target from the level-2 partials; none when nothing is unknown
+__global__ __launch_bounds__(256) void loop_pick_kernel(const Cand* __restrict__ part2, int64_t nb2,
+                                                        int order, LoopState* __restrict__ ls) {
+    Cand best{-1.0, -1.0, INT64_MAX};
+    for (int64_t i = threadIdx.x; i < nb2; i += blockDim.x) {
+        const Cand o = part2[i];
+        if (ranks_before(o, best, order)) best = o;
+    }
+    const Cand b = block_best(best, order);
+    if (threadIdx.x == 0) {
+        const bool none = b.id == INT64_MAX || ls->unknown == 0;
+        ls->centre = none ? -1 : b.id;
+        ls->cpick = order == 0 ? b.c : -b.p;
+    }
+}
+
+// As fill_kernel, with the iteration count, the last centre and the unknown
+// count kept in the loop state.
+__global__ void loop_fill_kernel(float* __restrict__ vol, uint8_t* __restrict__ mask,
+                                 double* __restrict__ conf, Grid g, LoopState* __restrict__ ls,
+                                 int64_t cap, int64_t* __restrict__ lc, int64_t* __restrict__ ls_src,
+                                 float* __restrict__ lcost) {
+    const int rho = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = ls->centre, s = ls->source;
+    if (p < 0 || s < 0) return;
+    if (rho == 0) {
+        const int64_t it = ls->it;
+        if (it < cap) {
+            lc[it] = p;
+            ls_src[it] = s;
+            lcost[it] = ls->cost;
+        }
+        ls->it = it + 1;
+        ls->last = p;
+    }
+    if (rho >= g.Kd) return;
+    int64_t cp[kMaxDims], cs[kMaxDims];
+    coords_of(g, p, cp);
+    coords_of(g, s, cs);
+    int64_t up = 0, us = 0;
+    bool inb = true;
+    int r = rho;
+    for (int a = g.nd - 1; a >= 0; a--) {
+        const int64_t o = (r % g.K) - g.h;
+        r /= g.K;
+        const int64_t x = cp[a] + o;
+        if (x < 0 || x >= g.shape[a]) inb = false;
+        up += x * g.stride[a];
+        us += (cs[a] + o) * g.stride[a];
+    }
+    if (!inb || mask[up]) return;
+    for (int ch = 0; ch < g.C; ch++) vol[up * g.C + ch] = vol[us * g.C + ch];
+    mask[up] = 1;
+    conf[up] = ls->cpick;
+    atomicAdd(&ls->unknown, ~0ull);   // minus one
+}
+
 __global__ void conf_init_kernel(const uint8_t* __restrict__ mask, int64_t n, double* __restrict__ conf) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) conf[i] = mask[i] ? 1.0 : 0.0;
@@ -245,6 +449,58 @@ sfc_status launch_pick(const float* vol, const uint8_t* mask, const double* conf
     SFC_TRY(launched("priority_kernel"));
     pick_kernel<<<1, 256, 0, st>>>(static_cast<const Cand*>(part), nb, order, centre, cpick);
     return launched("pick_kernel");
+}
+
+size_t loop_part_entries(const Grid& g, int64_t* nb1, int64_t* nb2) {
+    *nb1 = (g.nvox + 255) / 256;
+    *nb2 = (*nb1 + 255) / 256;
+    return (size_t)(*nb1 + *nb2);
+}
+size_t loop_cand_bytes() { return sizeof(Cand); }
+
+sfc_status launch_loop_init(const float* vol, const uint8_t* mask, const double* conf, const Grid& g,
+                            int order, void* pv, void* part1, void* part2, LoopState* ls,
+                            hipStream_t st) {
+    int64_t nb1, nb2;
+    loop_part_entries(g, &nb1, &nb2);
+    loop_init_kernel<<<1, 1, 0, st>>>(ls);
+    SFC_TRY(launched("loop_init_kernel"));
+    count_unknown_kernel<<<blocks_for(g.nvox), 256, 0, st>>>(mask, g.nvox, ls);
+    SFC_TRY(launched("count_unknown_kernel"));
+    cand_all_kernel<<<blocks_for(g.nvox), 256, 0, st>>>(vol, mask, conf, g, order, static_cast<Cand*>(pv));
+    SFC_TRY(launched("cand_all_kernel"));
+    part_all_kernel<<<(unsigned)nb1, 256, 0, st>>>(static_cast<const Cand*>(pv), g.nvox, order,
+                                                   static_cast<Cand*>(part1));
+    SFC_TRY(launched("part_all_kernel"));
+    part_all_kernel<<<(unsigned)nb2, 256, 0, st>>>(static_cast<const Cand*>(part1), nb1, order,
+                                                   static_cast<Cand*>(part2));
+    return launched("part_all_kernel");
+}
+
+sfc_status launch_loop_pick(const float* vol, const uint8_t* mask, const double* conf, const Grid& g,
+                            int order, void* pv, void* part1, void* part2, LoopState* ls,
+                            hipStream_t st) {
+    int64_t nb1, nb2;
+    loop_part_entries(g, &nb1, &nb2);
+    int64_t lines = 1;
+    for (int a = 0; a < g.nd - 1; a++) lines *= 2 * g.K - 1;
+    region_cand_kernel<<<(unsigned)lines, 256, 0, st>>>(vol, mask, conf, g, order, ls,
+                                                        static_cast<Cand*>(pv));
+    SFC_TRY(launched("region_cand_kernel"));
+    region_part1_kernel<<<(unsigned)(2 * lines), 256, 0, st>>>(static_cast<const Cand*>(pv), g, order, ls,
+                                                              static_cast<Cand*>(part1));
+    SFC_TRY(launched("region_part1_kernel"));
+    region_part2_kernel<<<(unsigned)(2 * lines), 256, 0, st>>>(static_cast<const Cand*>(part1), nb1, g,
+                                                              order, ls, static_cast<Cand*>(part2));
+    SFC_TRY(launched("region_part2_kernel"));
+    loop_pick_kernel<<<1, 256, 0, st>>>(static_cast<const Cand*>(part2), nb2, order, ls);
+    return launched("loop_pick_kernel");
+}
+
+sfc_status launch_loop_fill(float* vol, uint8_t* mask, double* conf, const Grid& g, LoopState* ls,
+                            int64_t cap, int64_t* lc, int64_t* lsrc, float* lcost, hipStream_t st) {
+    loop_fill_kernel<<<blocks_for(g.Kd), 256, 0, st>>>(vol, mask, conf, g, ls, cap, lc, lsrc, lcost);
+    return launched("loop_fill_kernel");
 }
 
 sfc_status launch_fill(float* vol, uint8_t* mask, double* conf, const Grid& g, const int64_t* centre,

@@ -51,7 +51,9 @@ __global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const f
                                                        const uint8_t* __restrict__ m, int64_t Q,
                                                        int32_t* __restrict__ qsub,
                                                        double* __restrict__ qcoords,
-                                                       uint64_t* __restrict__ qkeys) {
+                                                       uint64_t* __restrict__ qkeys,
+                                                       uint32_t* __restrict__ rowmask,
+                                                       int64_t qpad) {
     static_assert(64 % G == 0 && G >= 4, "a group of lanes lies inside one wave");
     constexpr int NG = 256 / G;
     constexpr int NT = D * (D + 1) / 2;
@@ -82,6 +84,17 @@ __global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const f
         if (gl == 0) known_bits[grp][w] = word;
     }
     __syncthreads();
+
+    // the rescoring's row masks: bit dx of row r = pixel r*K + dx known
+    if (rowmask && live) {
+        for (int r = gl; r < v.rows; r += G) {
+            const int p0 = r * v.K;
+            const int w0 = p0 >> 6, b0 = p0 & 63;
+            uint64_t bits = known_bits[grp][w0] >> b0;
+            if (b0 + v.K > 64) bits |= known_bits[grp][w0 + 1] << (64 - b0);
+            rowmask[(int64_t)r * qpad + q] = (uint32_t)(bits & ((1ull << v.K) - 1ull));
+        }
+    }
 
     // 2. subset choice
     for (int s = gl; s < v.S; s += G) {
@@ -268,7 +281,7 @@ __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int
 }
 
 // ------------------------------------------------------------ rescore
-constexpr int kCap = 512;   // maximum L*W
+constexpr int kCap = 2048;   // maximum L*W
 
 template <int ND, int K, int C, int NORM>
 __device__ inline float cand_cost(const QueryIndexView& v, const float* __restrict__ vol,
@@ -317,14 +330,20 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
                                                       float* __restrict__ best_cost,
                                                       int64_t* __restrict__ cand,
                                                       int32_t* __restrict__ ncand) {
-    __shared__ uint32_t sa[4][kCap];
-    __shared__ uint32_t sb[4][kCap];
+    // per wave: cap ids to sort (A), then the unique ones (Bu); cap is the
+    // power of two >= L*W, so the launch sizes the LDS to 2 * 4 * cap words
+    extern __shared__ uint32_t rescore_lds[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t q = (int64_t)blockIdx.x * 4 + w;
+    // XCD-aware: workgroup b runs on XCD b % 8; each XCD takes one
+    // contiguous eighth of the queries, whose neighbouring targets share
+    // candidates, so the patches they gather stay in that XCD's L2
+    const int64_t nblk = gridDim.x, per_xcd = (nblk + 7) / 8;
+    const int64_t qb = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t q = qb * 4 + w;
     const bool live = q < Q;
     const int LW = v.L * v.window;
-    uint32_t* A = sa[w];
-    uint32_t* Bu = sb[w];
+    uint32_t* A = rescore_lds + (size_t)w * cap;
+    uint32_t* Bu = rescore_lds + (size_t)(4 + w) * cap;
     const int s = live ? qsub[q] : 0;
     for (int i = lane; i < cap; i += 64) {
         uint32_t id = 0xffffffffu;
@@ -425,7 +444,7 @@ __global__ __launch_bounds__(256) void list_rescore_kernel(QueryIndexView v, con
 }
 
 using PrologueFn = void (*)(QueryIndexView, const float*, const uint8_t*, int64_t, int32_t*,
-                            double*, uint64_t*);
+                            double*, uint64_t*, uint32_t*, int64_t);
 // ------------------------------------------------------------ exact k-NN
 // The k-NN query of Section II.D on the unshifted Morton curve (curve 0 of
 // the chosen subset), one wave per query. A region is a box of grid cells
@@ -792,7 +811,7 @@ const RescoreEntry kRescore[] = {
 
 sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const uint8_t* m,
                                  int64_t Q, int32_t* qsub, double* qcoords, uint64_t* qkeys,
-                                 hipStream_t st) {
+                                 uint32_t* rowmask, int64_t qpad, hipStream_t st) {
     if (Q == 0) return SFC_OK;
     PrologueFn fn = nullptr;
     switch (v.D) {
@@ -814,7 +833,7 @@ sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const 
     if (v.Kd > 64 * kMaxKnownWords || v.S > kMaxSubsets)
         return fail(SFC_EUNSUPPORTED, "index query: more than 1024 pixels or 26 subsets per patch");
     hipLaunchKernelGGL(fn, dim3(blocks_for(Q, 256 / kPrologueLanes)), dim3(256), 0, st, v, t, m, Q,
-                       qsub, qcoords, qkeys);
+                       qsub, qcoords, qkeys, rowmask, qpad);
     return launched("prologue_kernel");
 }
 
@@ -867,10 +886,18 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
     if (!ent) return fail(SFC_EUNSUPPORTED, "index rescoring: no kernel for this (ndim, K, C)");
     int cap = 64;
     while (cap < v.L * v.window) cap <<= 1;
-    if (cap > kCap) return fail(SFC_EUNSUPPORTED, "n_curves * window above 512");
-    hipLaunchKernelGGL(norm == 1 ? ent->fn_l1 : ent->fn, dim3(blocks_for(Q, 4)), dim3(256), 0, st,
-                       v, vol, t, rowmask, qpad, qsub, wstart, Q, cap, best_id, best_cost, cand,
-                       ncand);
+    if (cap > kCap) return fail(SFC_EUNSUPPORTED, "n_curves * window above 2048");
+    const size_t lds = (size_t)8 * cap * sizeof(uint32_t);
+    const void* fn = reinterpret_cast<const void*>(norm == 1 ? ent->fn_l1 : ent->fn);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return check_hip(e, "rescore LDS attribute");
+    }
+    // a multiple of 8 workgroups, so the XCD-aware query order is a bijection
+    const unsigned nblk = (blocks_for(Q, 4) + 7) / 8 * 8;
+    hipLaunchKernelGGL(norm == 1 ? ent->fn_l1 : ent->fn, dim3(nblk), dim3(256), lds,
+                       st, v, vol, t, rowmask, qpad, qsub, wstart, Q, cap, best_id, best_cost,
+                       cand, ncand);
     return launched("rescore_kernel");
 }
 

@@ -24,10 +24,12 @@ struct QueryIndexView {
     const uint32_t* ids;       // [S][L][n]
 };
 
-// subset, real coordinates [Q][D] and keys [Q][L][W64] of each query
+// subset, real coordinates [Q][D] and keys [Q][L][W64] of each query; with
+// rowmask non-null also the rescoring's row masks [rows][qpad] (bit dx of
+// row r: pixel r*K + dx known), written for queries < Q only
 sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const uint8_t* m,
                                  int64_t Q, int32_t* qsub, double* qcoords, uint64_t* qkeys,
-                                 hipStream_t st);
+                                 uint32_t* rowmask, int64_t qpad, hipStream_t st);
 // window start per (query, curve): wstart [Q][L]
 sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub,
                                const uint64_t* qkeys, int64_t Q, int64_t* wstart, hipStream_t st);

@@ -225,7 +225,7 @@ sfc_status check_sfc_args(const sfc_geometry* g, int K, int D, int L, const sfc_
     if (L > D + 1) return fail(SFC_EINVAL, "n_curves must be <= reduced_dim + 1 (shift headroom)");
     if ((int64_t)D * o.key_bits > 256) return fail(SFC_EINVAL, "reduced_dim * key_bits above 256");
     if (D > 12 && D != 16) return fail(SFC_EUNSUPPORTED, "reduced_dim must be 1..12 or 16");
-    if ((int64_t)L * o.window > 512) return fail(SFC_EUNSUPPORTED, "n_curves * window above 512");
+    if ((int64_t)L * o.window > 2048) return fail(SFC_EUNSUPPORTED, "n_curves * window above 2048");
     if (!scan_supported(g->ndim, K, g->channels) || !rescore_supported(g->ndim, K, g->channels))
         return fail(SFC_EUNSUPPORTED, "no kernels for this (ndim, K, channels)");
     int Kd = 1;
@@ -546,27 +546,51 @@ sfc_status curves_from_basis(sfc_index* ix, hipStream_t st) {
     return finish_sfc(ix, st);
 }
 
+namespace {
+// Layout of the index query's temporaries: row masks, coordinates, keys,
+// window starts, subsets (each at a 256-byte boundary).
+struct IndexQueryLayout {
+    size_t rm, co, k, w, s, total;
+    IndexQueryLayout(const sfc_index* ix, int64_t Q) {
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = off;
+            off += (bytes + 255) & ~size_t(255);
+            return at;
+        };
+        rm = take((size_t)scan_qpad(Q) * ix->g.rows * sizeof(uint32_t));
+        co = take((size_t)Q * 8 * ix->D);
+        k = take((size_t)Q * 8 * ix->L * ix->W64);
+        w = take((size_t)Q * 8 * ix->L);
+        s = take((size_t)Q * 4);
+        total = off;
+    }
+};
+}  // namespace
+
+size_t index_query_bytes(const sfc_index* ix, int64_t Q) { return IndexQueryLayout(ix, Q).total; }
+
 sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int64_t* best_id,
                        float* best_cost, int64_t* cand, int32_t* ncand) {
-    const Grid& g = ix->g;
+    // the handle's grow-only buffer: allocated on first use, reused after
+    SFC_TRY(ix->qtmp.reserve(index_query_bytes(ix, Q), "query scratch"));
+    return query_index_on(ix, t, m, Q, ix->qtmp.ptr, best_id, best_cost, cand, ncand);
+}
+
+sfc_status query_index_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, void* buf,
+                          int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand) {
     hipStream_t st = ix->st;
     const int64_t qpad = scan_qpad(Q);
-    SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
-    uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
-    SFC_TRY(launch_pack_rowmask(m, g, Q, rm, st));
-    const size_t need = (size_t)Q * (4 + 8 * ix->D + 8 * ix->L * ix->W64 + 8 * ix->L) + 256;
-    SFC_TRY(ix->qtmp.reserve(need, "query scratch"));
-    char* p = static_cast<char*>(ix->qtmp.ptr);
-    double* coords = reinterpret_cast<double*>(p);
-    p += (size_t)Q * 8 * ix->D;
-    uint64_t* qkeys = reinterpret_cast<uint64_t*>(p);
-    p += (size_t)Q * 8 * ix->L * ix->W64;
-    int64_t* wstart = reinterpret_cast<int64_t*>(p);
-    p += (size_t)Q * 8 * ix->L;
-    int32_t* qsub = reinterpret_cast<int32_t*>(p);
+    const IndexQueryLayout lay(ix, Q);
+    char* base = static_cast<char*>(buf);
+    uint32_t* rm = reinterpret_cast<uint32_t*>(base + lay.rm);
+    double* coords = reinterpret_cast<double*>(base + lay.co);
+    uint64_t* qkeys = reinterpret_cast<uint64_t*>(base + lay.k);
+    int64_t* wstart = reinterpret_cast<int64_t*>(base + lay.w);
+    int32_t* qsub = reinterpret_cast<int32_t*>(base + lay.s);
     const QueryIndexView v = view_of(ix);
     SFC_TRY(ix->timer.begin("prologue_kernel", st));
-    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, st));
+    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, rm, qpad, st));
     SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->timer.begin("search_kernel", st));
     SFC_TRY(launch_query_search(v, qsub, qkeys, Q, wstart, st));
@@ -582,10 +606,8 @@ sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
     const Grid& g = ix->g;
     hipStream_t st = ix->st;
     const int64_t qpad = scan_qpad(Q);
-    SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
-    uint32_t* rm = static_cast<uint32_t*>(ix->rowmask.ptr);
-    SFC_TRY(launch_pack_rowmask(m, g, Q, rm, st));
-    const size_t need = (size_t)Q * (4 + 8 * ix->D + 8 * ix->L * ix->W64 + 4 * k + 4 + 4 + 1) + 1024;
+    const size_t need = (size_t)qpad * g.rows * 4 + 64 +
+                        (size_t)Q * (4 + 8 * ix->D + 8 * ix->L * ix->W64 + 4 * k + 4 + 4 + 1) + 1024;
     SFC_TRY(ix->qtmp.reserve(need, "k-NN query scratch"));
     char* p = static_cast<char*>(ix->qtmp.ptr);
     auto take = [&](size_t bytes) {
@@ -593,6 +615,7 @@ sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
         p += (bytes + 63) & ~size_t(63);
         return r;
     };
+    uint32_t* rm = reinterpret_cast<uint32_t*>(take((size_t)qpad * g.rows * 4));
     double* coords = reinterpret_cast<double*>(take((size_t)Q * 8 * ix->D));
     uint64_t* qkeys = reinterpret_cast<uint64_t*>(take((size_t)Q * 8 * ix->L * ix->W64));
     int32_t* qsub = reinterpret_cast<int32_t*>(take((size_t)Q * 4));
@@ -604,7 +627,7 @@ sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
     SFC_TRY(launch_fill_u64(flag, 1, 0ull, st));
     const QueryIndexView v = view_of(ix);
     SFC_TRY(ix->timer.begin("prologue_kernel", st));
-    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, st));
+    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, rm, qpad, st));
     SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->timer.begin("knn_kernel", st));
     SFC_TRY(launch_knn(v, qsub, coords, Q, k, mu, list, cnt, thr,
@@ -628,7 +651,7 @@ sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t
     SFC_TRY(ix->qtmp.reserve(need, "query scratch"));
     uint64_t* qkeys = static_cast<uint64_t*>(ix->qtmp.ptr);
     const QueryIndexView v = view_of(ix);
-    return launch_query_prologue(v, t, m, Q, subset, coords, qkeys, ix->st);
+    return launch_query_prologue(v, t, m, Q, subset, coords, qkeys, nullptr, 0, ix->st);
 }
 
 }  // namespace sfc

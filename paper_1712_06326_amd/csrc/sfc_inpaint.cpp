@@ -1,7 +1,16 @@
-// Host side of the fill loop: one iteration = pick the target (device),
-// extract it, query it in the chosen mode, copy the chosen patch (device).
-// The host only reads the unknown count and the chosen centre to decide
-// whether to continue.
+// Host side of the fill loop: one iteration = pick the target, extract it,
+// query it in the chosen mode, copy the chosen patch.
+//
+// Float32-scan and index modes run device-resident: the loop state (unknown
+// count, target, source, iteration count) stays on the device, priorities
+// are kept per voxel and recomputed only around the last filled box, and
+// the iterations are replayed from HIP graphs (one of 16 iterations, one of
+// 1) in rounds. A round holds floor(unknown / K^nd) iterations (at least
+// one): every iteration fills at least one voxel (the target is a front
+// voxel, so its box holds an unknown face neighbour) and at most K^nd, so a
+// round never runs past the last iteration. The host reads the state once
+// per round. The bf16 mode (whose list overflow falls back on the host)
+// keeps one host round trip per iteration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,7 +36,148 @@ struct DevMem {
     }
 };
 
+// Restores the handle's stream and destroys the loop's stream and graphs.
+struct LoopRes {
+    sfc_index* ix;
+    hipStream_t saved;
+    hipStream_t ls = nullptr;
+    hipGraphExec_t g1 = nullptr, g16 = nullptr;
+    ~LoopRes() {
+        ix->st = saved;
+        if (g1) (void)hipGraphExecDestroy(g1);
+        if (g16) (void)hipGraphExecDestroy(g16);
+        if (ls) {
+            (void)hipStreamSynchronize(ls);
+            (void)hipStreamDestroy(ls);
+        }
+    }
+};
+
+struct LoopBufs {
+    float* vol;
+    uint8_t* mask;
+    double* conf;
+    int order;
+    sfc_mode mode;
+    float* t;
+    uint8_t* m;
+    void* pv;
+    void* part1;
+    void* part2;
+    LoopState* state;
+    void* qbuf;        // query temporaries
+    uint32_t* rm;      // float32 scan: row masks, padded target, packed result
+    float* tp;
+    uint64_t* best;
+    int64_t cap;
+    int64_t *lc, *ls;
+    float* lcost;
+};
+
+// One iteration on the handle's stream (kernel launches only).
+sfc_status loop_body(sfc_index* ix, const LoopBufs& b) {
+    const Grid& g = ix->g;
+    hipStream_t st = ix->st;
+    SFC_TRY(launch_loop_pick(b.vol, b.mask, b.conf, g, b.order, b.pv, b.part1, b.part2, b.state, st));
+    SFC_TRY(launch_extract(b.vol, b.mask, g, &b.state->centre, 1, b.t, b.m, st));
+    if (b.mode == SFC_MODE_BRUTE_FP32) {
+        SFC_TRY(scan_fp32_on(ix, b.t, b.m, 1, b.rm, b.tp, b.best));
+        SFC_TRY(launch_unpack_best(b.best, 1, &b.state->source, &b.state->cost, st));
+    } else {
+        SFC_TRY(query_index_on(ix, b.t, b.m, 1, b.qbuf, &b.state->source, &b.state->cost, nullptr,
+                               nullptr));
+    }
+    return launch_loop_fill(b.vol, b.mask, b.conf, g, b.state, b.cap, b.lc, b.ls, b.lcost, st);
+}
+
+sfc_status capture(sfc_index* ix, const LoopBufs& b, int iters, hipGraphExec_t* out) {
+    SFC_HIP(hipStreamBeginCapture(ix->st, hipStreamCaptureModeThreadLocal));
+    sfc_status s = SFC_OK;
+    for (int i = 0; i < iters && s == SFC_OK; i++) s = loop_body(ix, b);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ix->st, &graph);
+    if (s != SFC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return check_hip(e, "fill loop capture");
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return check_hip(e, "fill loop graph");
+    return SFC_OK;
+}
+
 }  // namespace
+
+// The device-resident loop (float32 scan or index queries).
+sfc_status device_loop(sfc_index* ix, float* volume, uint8_t* mask, double* conf, int order,
+                       sfc_mode mode, float* t, uint8_t* m, int64_t cap, int64_t* lc, int64_t* lsrc,
+                       float* lcost, int64_t* iters) {
+    const Grid& g = ix->g;
+    LoopRes res{ix, ix->st};
+    SFC_HIP(hipStreamCreateWithFlags(&res.ls, hipStreamNonBlocking));
+    // the loop's stream follows the work already queued on the handle's
+    hipEvent_t ev = nullptr;
+    SFC_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t he = hipEventRecord(ev, res.saved);
+    if (he == hipSuccess) he = hipStreamWaitEvent(res.ls, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (he != hipSuccess) return check_hip(he, "fill loop stream");
+    ix->st = res.ls;
+    ix->timer.reset(false);
+
+    int64_t nb1, nb2;
+    loop_part_entries(g, &nb1, &nb2);
+    DevMem mem;
+    LoopBufs b{};
+    b.vol = volume;
+    b.mask = mask;
+    b.conf = conf;
+    b.order = order;
+    b.mode = mode;
+    b.t = t;
+    b.m = m;
+    b.cap = cap;
+    b.lc = lc;
+    b.ls = lsrc;
+    b.lcost = lcost;
+    const size_t cb = loop_cand_bytes();
+    SFC_TRY(mem.alloc(&b.pv, (size_t)g.nvox * cb, "voxel priorities"));
+    SFC_TRY(mem.alloc(&b.part1, (size_t)nb1 * cb, "priority partials"));
+    SFC_TRY(mem.alloc(&b.part2, (size_t)nb2 * cb, "priority partials"));
+    SFC_TRY(mem.alloc((void**)&b.state, sizeof(LoopState), "loop state"));
+    if (mode == SFC_MODE_INDEX) {
+        SFC_TRY(mem.alloc(&b.qbuf, index_query_bytes(ix, 1), "query scratch"));
+    } else {
+        const int64_t qpad = scan_qpad(1);
+        SFC_TRY(mem.alloc((void**)&b.rm, (size_t)qpad * g.rows * 4, "row masks"));
+        SFC_TRY(mem.alloc((void**)&b.tp, (size_t)qpad * g.Kd * g.C * 4, "padded target"));
+        SFC_TRY(mem.alloc((void**)&b.best, 8, "scan result"));
+    }
+    SFC_TRY(launch_loop_init(volume, mask, conf, g, order, b.pv, b.part1, b.part2, b.state, res.ls));
+
+    // the first iteration runs eagerly (it also settles every lazily
+    // computed launch parameter before the capture)
+    SFC_TRY(loop_body(ix, b));
+    SFC_TRY(capture(ix, b, 1, &res.g1));
+    SFC_TRY(capture(ix, b, 16, &res.g16));
+    LoopState h{};
+    int64_t prev_it = -1;
+    for (;;) {
+        SFC_HIP(hipMemcpyAsync(&h, b.state, sizeof(h), hipMemcpyDeviceToHost, res.ls));
+        SFC_HIP(hipStreamSynchronize(res.ls));
+        if (h.unknown == 0) break;
+        if (h.it == prev_it)   // a whole round without a target
+            return fail(SFC_EEMPTY, "unknown voxels remain but the fill front is empty");
+        prev_it = h.it;
+        int64_t r = (int64_t)(h.unknown / (unsigned long long)g.Kd);
+        if (r < 1) r = 1;
+        for (; r >= 16; r -= 16) SFC_HIP(hipGraphLaunch(res.g16, res.ls));
+        for (; r > 0; r--) SFC_HIP(hipGraphLaunch(res.g1, res.ls));
+    }
+    *iters = h.it;
+    return SFC_OK;
+}
 
 }  // namespace sfc
 
@@ -100,6 +250,22 @@ extern "C" sfc_status sfc_inpaint(float* volume, uint8_t* mask, const sfc_geomet
     SFC_TRY(mem.alloc((void**)&ls, (size_t)std::max<int64_t>(cap, 1) * 8, "log"));
     SFC_TRY(mem.alloc((void**)&lcost, (size_t)std::max<int64_t>(cap, 1) * 4, "log"));
     SFC_TRY(launch_conf_init(mask, gr, conf, st));
+    if (mode == SFC_MODE_BRUTE_FP32 || mode == SFC_MODE_INDEX) {
+        int64_t it = 0;
+        SFC_TRY(device_loop(ix, volume, mask, conf, order == SFC_ORDER_CRIMINISI ? 0 : 1, mode, t,
+                            m, cap, lc, ls, lcost, &it));
+        if (log) {
+            const int64_t k = std::min(it, cap);
+            if (k > 0) {
+                SFC_HIP(hipMemcpy(log->centre_host, lc, (size_t)k * 8, hipMemcpyDeviceToHost));
+                SFC_HIP(hipMemcpy(log->source_host, ls, (size_t)k * 8, hipMemcpyDeviceToHost));
+                SFC_HIP(hipMemcpy(log->cost_host, lcost, (size_t)k * 4, hipMemcpyDeviceToHost));
+            }
+            log->len = k;
+        }
+        *n_iters = it;
+        return SFC_OK;
+    }
     int64_t it = 0;
     for (;;) {
         SFC_TRY(launch_pick(volume, mask, conf, gr, order == SFC_ORDER_CRIMINISI ? 0 : 1, part,

@@ -34,7 +34,7 @@ class Geometry(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("key_bits", C.c_int32), ("window", C.c_int32),
-                ("curve", C.c_int32), ("rescore_top", C.c_int32), ("certify", C.c_int32),
+                ("curve", C.c_int32),
                 ("query_block", C.c_int32), ("scan_variant", C.c_int32), ("stream", C.c_void_p),
                 ("timing", C.c_int32), ("norm", C.c_int32)]
 
@@ -84,8 +84,8 @@ _SIG = {
     "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
     "sfc_query_kernel_times": (ST, [P, P, I32, C.POINTER(C.c_int32)]),
     "sfc_query_filter_tiles": (ST, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
-    "sfc_autotune_window": (ST, [P, P, P, I64, C.c_float, P, I32, C.POINTER(C.c_int32),
-                                 C.POINTER(C.c_int32)]),
+    "sfc_autotune_window": (ST, [P, P, P, I64, C.c_float, C.c_float, P, I32,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "sfc_autotune": (ST, [P, P, P, I64, C.POINTER(C.c_int32)]),
     "sfc_index_info_get": (ST, [P, C.POINTER(IndexInfo)]),
     "sfc_index_dictionary": (ST, [P, P]),
@@ -156,15 +156,13 @@ def geometry(mask: torch.Tensor, channels: int) -> Geometry:
 NORMS = {"l2": 0, "l1": 1}
 
 
-def options(key_bits=8, window=32, curve="morton", rescore_top=16, certify=True,
-            query_block=0, scan_variant=0, timing=False, norm="l2") -> Options:
+def options(key_bits=8, window=32, curve="morton", query_block=0, scan_variant=0,
+            timing=False, norm="l2") -> Options:
     o = Options()
     _L.sfc_options_default(C.byref(o))
     o.key_bits = key_bits
     o.window = window
     o.curve = CURVES[curve] if isinstance(curve, str) else int(curve)
-    o.rescore_top = rescore_top
-    o.certify = 1 if certify else 0
     o.query_block = query_block
     o.scan_variant = scan_variant
     o.stream = _stream()
@@ -300,15 +298,17 @@ class Index:
         _check(_L.sfc_autotune(self._h, _ptr(t), _ptr(m), m.shape[0], C.byref(v)))
         return v.value
 
-    def autotune_window(self, t: torch.Tensor, m: torch.Tensor, target_recall: float = 0.9):
-        """Smallest window reaching target_recall against the float32 scan on
+    def autotune_window(self, t: torch.Tensor, m: torch.Tensor, target_recall: float = 0.9,
+                        max_accel_error: float = -1.0):
+        """Smallest window reaching target_recall (and an acceleration error
+        of at most max_accel_error, if >= 0) against the float32 scan on
         these targets; set on the handle. Returns (window, [trials])."""
         cap = 32
         arr = (WindowTrial * cap)()
         n, w = C.c_int32(), C.c_int32()
         _check(_L.sfc_autotune_window(self._h, _ptr(t), _ptr(m), m.shape[0],
-                                      C.c_float(target_recall), C.cast(arr, C.c_void_p), cap,
-                                      C.byref(n), C.byref(w)))
+                                      C.c_float(target_recall), C.c_float(max_accel_error),
+                                      C.cast(arr, C.c_void_p), cap, C.byref(n), C.byref(w)))
         trials = [{"window": arr[i].window, "recall": arr[i].recall,
                    "accel_error": arr[i].accel_error, "ms": arr[i].ms}
                   for i in range(min(n.value, cap))]

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_only_calls():
     lib = ctypes.CDLL(LIB)
     lib.sfc_abi_version.restype = ctypes.c_int32
-    assert lib.sfc_abi_version() == 1
+    assert lib.sfc_abi_version() == 2
     lib.sfc_last_error.restype = ctypes.c_char_p
     assert lib.sfc_last_error() == b""
     # argument errors are reported before any device work
@@ -141,3 +141,19 @@ def test_index_file_errors(tmp_path):
     # sums 25 * 8, bases 5 * 10 * 4, grid 5 * 4 * 8 + 5 * 8 bytes
     assert b"truncated" in run(_index_header() + b"\0" * 599)
     assert b"data after" in run(_index_header() + b"\0" * 601)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_options_layout_matches_the_header():
+    # sfc_options_default is host-only; its struct_size is the C sizeof, and
+    # the binding's mirror must have the same size and defaults
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None:
+        pytest.skip("torch missing")
+    from paper_1712_06326_amd import native
+    o = native.Options()
+    native.lib().sfc_options_default(ctypes.byref(o))
+    assert o.struct_size == ctypes.sizeof(native.Options)
+    assert (o.key_bits, o.window, o.curve, o.query_block, o.scan_variant, o.timing, o.norm) == \
+        (8, 32, 0, 0, 0, 0, 0)

@@ -58,6 +58,9 @@ def _check(vol, mask, K, D, L, b, curve, W, queries=None, with_basis=False):
     # eight dimensions: one key byte per level (2 and 4 words, one curve)
     (46, 58, 3, 7, 8, 3, 16, "hilbert", 16, 6),
     (44, 50, 1, 7, 8, 2, 31, "morton", 16, 7),
+    # wide windows: L * W up to 2048 candidates per query
+    (50, 70, 3, 9, 8, 4, 21, "morton", 512, 8),
+    (60, 64, 1, 7, 6, 4, 10, "hilbert", 300, 9),
     (42, 48, 2, 5, 8, 1, 12, "morton", 8, 8),
 ])
 def test_index_small_images(h, w, c, K, D, L, b, curve, W, seed):
@@ -110,3 +113,9 @@ def test_window_autotuner():
     b2, c2 = ix2.query(t, m, "index")
     assert np.array_equal(host(bi), host(b2))
     assert np.array_equal(host(bc).view(np.uint32), host(c2).view(np.uint32))
+    # an acceleration-error target (Section III.D's 1 %) instead of recall
+    W3, trials3 = ix.autotune_window(t, m, 0.0, 0.01)
+    assert [x["window"] for x in trials3] == [x["window"] for x in trials]
+    first3 = next((x["window"] for x in trials3 if x["accel_error"] <= 0.01), trials3[-1]["window"])
+    assert W3 == first3 and ix.info.window == W3
+    assert trials3[-1]["window"] * 4 <= 2048 < trials3[-1]["window"] * 4 * 1.5

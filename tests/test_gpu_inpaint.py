@@ -51,3 +51,19 @@ def test_inpaint_config1_criminisi():
 def test_inpaint_config1_index():
     d = synth.config1()
     _run(d["volume"], d["mask"], 9, "criminisi", "index", D=8, L=4, b=8, W=32)
+
+
+@pytest.mark.parametrize("order,mode", [("criminisi", "fp32"), ("raster", "index"),
+                                        ("criminisi", "index")])
+def test_inpaint_many_rounds(order, mode):
+    # enough unknown voxels that the loop replays its 16-iteration graph
+    # (rounds of floor(unknown / K^2) iterations) as well as single ones
+    d = synth.small_image(80, 96, 2, 33, holes=4, frac=0.1)
+    assert int((d["mask"] == 0).sum()) // 25 >= 16
+    it = _run(d["volume"], d["mask"], 5, order, mode, D=6, L=3, b=10, W=16)
+    say(f"  {it} iterations")
+
+
+def test_inpaint_volume_index():
+    d = synth.small_volume(18, 34, frac=0.04)
+    _run(d["volume"], d["mask"], 5, "criminisi", "index", D=6, L=3, b=8, W=16)
