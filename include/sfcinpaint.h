@@ -189,6 +189,37 @@ sfc_status sfc_index_build_with_basis(const float *volume, const uint8_t *mask,
 sfc_status sfc_query(sfc_index *idx, const float *targets, const uint8_t *target_masks,
                      int64_t Q, sfc_mode mode, int64_t *best_id, float *best_cost);
 
+/* Size of the fixed device array that sfc_query_fp32_noalloc works in: one
+ * copy per device, held until the process ends. */
+#define SFC_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * float32 full scan as sfc_query in SFC_MODE_BRUTE_FP32, with the same
+ * answers bit for bit, but neither this call nor anything it calls allocates
+ * device memory or creates events. Its row masks, padded targets and packed
+ * per-query results live in the library's fixed array of
+ * SFC_NOALLOC_SCRATCH_BYTES on the current device; sfc_noalloc_bytes(idx, Q)
+ * gives what Q queries need: round256(qpad * K^(ndim-1) * 4) +
+ * round256(qpad * K^ndim * channels * 4) + round256(qpad * 8), qpad = Q
+ * rounded up to a multiple of 48 (about 16,500 queries of 9x9x3, 150,000 of
+ * 9x9x1). The caller passes device inputs and outputs as for sfc_query;
+ * the index's device must be the current device. Every call on a device
+ * shares that device's array: two calls whose work overlaps on one device
+ * (on different streams, or from different threads before the first has
+ * finished on its stream) race and give wrong answers. The handle's own
+ * growable buffers are not touched; the handle's timing switch is ignored.
+ * Errors: SFC_EINVAL for a null pointer, Q < 0, Q above the array's
+ * capacity (with the needed size in the message) or another device current;
+ * SFC_EDEVICE if the array's address cannot be found. */
+sfc_status sfc_query_fp32_noalloc(sfc_index *idx, const float *targets,
+                                  const uint8_t *target_masks, int64_t Q, int64_t *best_id,
+                                  float *best_cost);
+
+/* Bytes of the fixed array that Q queries need in sfc_query_fp32_noalloc
+ * (-1 for a NULL handle or Q < 0). */
+int64_t sfc_noalloc_bytes(const sfc_index *idx, int64_t Q);
+
 /* Exact k-NN query of Section II.D on an index built with Morton curves:
  * for each target, the chosen subset and grid cell as in SFC_MODE_INDEX, the
  * k dictionary patches whose cells on the unshifted curve (curve 0) are

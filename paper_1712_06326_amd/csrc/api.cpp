@@ -390,6 +390,10 @@ static sfc_status new_handle(const float* volume, const uint8_t* mask, const sfc
     sfc_options o = resolve_options(opt);
     SFC_TRY(validate_options(o));
     sfc_index* ix = new sfc_index();
+    if (hipGetDevice(&ix->device) != hipSuccess) {
+        delete ix;
+        return fail(SFC_EDEVICE, "hipGetDevice failed");
+    }
     ix->g = make_grid(g, K);
     ix->tuned_variant = recalled_variant(g->ndim, K, g->channels);
     ix->opt = o;

@@ -63,6 +63,7 @@ struct sfc_index {
     sfc::Grid g{};
     sfc_options opt{};
     hipStream_t st = nullptr;
+    int device = -1;                 // the device current when the handle was made
     const float* vol = nullptr;      // borrowed
     uint8_t* valid = nullptr;        // [nvox] 1 = dictionary centre
     uint32_t* dict = nullptr;        // [n] ascending centre ids

@@ -78,6 +78,8 @@ _SIG = {
     "sfc_index_build_with_basis": (ST, [P, P, C.POINTER(Geometry), I32, I32, I32,
                                         C.POINTER(Options), P, C.POINTER(P)]),
     "sfc_query": (ST, [P, P, P, I64, C.c_int, P, P]),
+    "sfc_query_fp32_noalloc": (ST, [P, P, P, I64, P, P]),
+    "sfc_noalloc_bytes": (I64, [P, I64]),
     "sfc_query_candidates": (ST, [P, P, P, I64, P, P]),
     "sfc_query_knn": (ST, [P, P, P, I64, I32, I32, P, P, P, P]),
     "sfc_query_coords": (ST, [P, P, P, I64, P, P]),
@@ -278,6 +280,16 @@ class Index:
         bc = torch.empty(Q, dtype=torch.float32, device=t.device)
         _check(_L.sfc_query(self._h, _ptr(t), _ptr(m), Q, MODES[mode], _ptr(bi), _ptr(bc)))
         return bi, bc
+
+    def query_noalloc(self, t: torch.Tensor, m: torch.Tensor, best_id: torch.Tensor,
+                      best_cost: torch.Tensor) -> None:
+        """The float32 full scan into caller-allocated outputs, through the
+        entry point that allocates nothing (sfc_query_fp32_noalloc)."""
+        _check(_L.sfc_query_fp32_noalloc(self._h, _ptr(t), _ptr(m), m.shape[0], _ptr(best_id),
+                                         _ptr(best_cost)))
+
+    def noalloc_bytes(self, Q: int) -> int:
+        return int(_L.sfc_noalloc_bytes(self._h, Q))
 
     def knn(self, t: torch.Tensor, m: torch.Tensor, k: int = 80, mu: int = 256,
             candidates: bool = False):
