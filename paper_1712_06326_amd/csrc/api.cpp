@@ -295,6 +295,16 @@ sfc_index::~sfc_index() {
 
 namespace sfc {
 
+sfc_status scan_fp32_prepared(sfc_index* ix, int64_t Q, const uint32_t* rm, const float* tp,
+                              uint64_t* best) {
+    ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best, ix->opt.query_block,
+               ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant,
+               ix->spans, ix->n_spans, ix->opt.norm};
+    SFC_TRY(ix->timer.begin("scan_fp32_kernel", ix->st));
+    SFC_TRY(launch_scan_fp32(ix->g, a, ix->st));
+    return ix->timer.end(ix->st);
+}
+
 sfc_status scan_fp32_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, uint32_t* rm,
                         float* tp, uint64_t* best) {
     const Grid& g = ix->g;
@@ -303,12 +313,7 @@ sfc_status scan_fp32_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t
     // targets padded with zero rows up to the scan's query block
     SFC_TRY(launch_pad_f32(t, (int64_t)Q * g.Kd * g.C, (int64_t)qpad * g.Kd * g.C, tp, ix->st));
     SFC_TRY(launch_fill_u64(best, Q, ~0ull, ix->st));
-    ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best, ix->opt.query_block,
-               ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant,
-               ix->spans, ix->n_spans, ix->opt.norm};
-    SFC_TRY(ix->timer.begin("scan_fp32_kernel", ix->st));
-    SFC_TRY(launch_scan_fp32(g, a, ix->st));
-    return ix->timer.end(ix->st);
+    return scan_fp32_prepared(ix, Q, rm, tp, best);
 }
 
 sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,

@@ -140,6 +140,10 @@ sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int
 // word of the three is written before it is read.
 sfc_status scan_fp32_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, uint32_t* rm,
                         float* tp, uint64_t* best);
+// The scan alone, on row masks, padded targets and a cleared result that
+// are already in place.
+sfc_status scan_fp32_prepared(sfc_index* ix, int64_t Q, const uint32_t* rm, const float* tp,
+                              uint64_t* best);
 sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                                sfc_mode mode, int64_t* best_id, float* best_cost);
 sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,

@@ -13,8 +13,10 @@ struct LoopState {
     int64_t source;               // its best patch
     float cost;
     float pad;
-    int64_t last;                 // centre filled by the previous iteration (-1: none)
+    int64_t last;                 // centre filled by the last apply (-1: none)
     int64_t it;                   // iterations done
+    int32_t pending;              // 1: centre's query answer not applied yet
+    int32_t pad2;
 };
 
 // entries of the two partial levels (nb1 = blocks of 256 voxels, nb2 =
@@ -25,13 +27,18 @@ size_t loop_cand_bytes();
 sfc_status launch_loop_init(const float* vol, const uint8_t* mask, const double* conf, const Grid& g,
                             int order, void* pv, void* part1, void* part2, LoopState* ls,
                             hipStream_t st);
-// candidates and partials around the last filled centre, then the next target
-sfc_status launch_loop_pick(const float* vol, const uint8_t* mask, const double* conf, const Grid& g,
-                            int order, void* pv, void* part1, void* part2, LoopState* ls,
-                            hipStream_t st);
-// copy the chosen patch, log the iteration, count it
-sfc_status launch_loop_fill(float* vol, uint8_t* mask, double* conf, const Grid& g, LoopState* ls,
-                            int64_t cap, int64_t* lc, int64_t* lsrc, float* lcost, hipStream_t st);
+// applies the pending answer (best: the float32 scan's packed result, or
+// null when the query wrote source and cost into the state)
+sfc_status launch_loop_apply(float* vol, uint8_t* mask, double* conf, const Grid& g, LoopState* ls,
+                             const uint64_t* best, int64_t cap, int64_t* lc, int64_t* lsrc,
+                             float* lcost, hipStream_t st);
+// candidates and partials around the last fill, the next target and its
+// extraction (t, m; with tp/rm/best non-null also the float32 scan's query
+// slot 0 and a cleared result)
+sfc_status launch_loop_select(const float* vol, const uint8_t* mask, const double* conf,
+                              const Grid& g, int order, void* pv, void* part1, void* part2,
+                              LoopState* ls, float* t, uint8_t* m, float* tp, uint32_t* rm,
+                              int64_t qpad, uint64_t* best, hipStream_t st);
 
 size_t inpaint_part_bytes(const Grid& g);
 sfc_status launch_conf_init(const uint8_t* mask, const Grid& g, double* conf, hipStream_t st);

@@ -282,6 +282,7 @@ __global__ void loop_init_kernel(LoopState* ls) {
     ls->cost = 0.0f;
     ls->last = -1;
     ls->it = 0;
+    ls->pending = 0;
 }
 
 // The region whose candidates a fill at centre p can change: the box of
@@ -331,96 +332,208 @@ __global__ __launch_bounds__(256) void region_cand_kernel(const float* __restric
     if (v <= id1) pv[v] = voxel_cand(vol, mask, conf, g, order, v);
 }
 
-// level-1 partials of the blocks of 256 voxels that a region line touches
-// (at most two per line); lines sharing a block write the same value
-__global__ __launch_bounds__(256) void region_part1_kernel(const Cand* __restrict__ pv, Grid g,
-                                                           int order, const LoopState* __restrict__ ls,
-                                                           Cand* __restrict__ part1) {
-    const int64_t p = ls->last;
-    if (p < 0) return;
-    int64_t id0, id1;
-    if (!region_line(g, p, blockIdx.x >> 1, &id0, &id1)) return;
-    const int64_t b = id0 / 256 + (blockIdx.x & 1);
-    if (b > id1 / 256) return;
-    const int64_t i = b * 256 + threadIdx.x;
-    const Cand x = i < g.nvox ? pv[i] : Cand{-1.0, -1.0, INT64_MAX};
-    const Cand best = block_best(x, order);
-    if (threadIdx.x == 0) part1[b] = best;
-}
-
-// level-2 partials over the level-1 blocks that changed
-__global__ __launch_bounds__(256) void region_part2_kernel(const Cand* __restrict__ part1,
-                                                           int64_t nb1, Grid g, int order,
-                                                           const LoopState* __restrict__ ls,
-                                                           Cand* __restrict__ part2) {
-    const int64_t p = ls->last;
-    if (p < 0) return;
-    int64_t id0, id1;
-    if (!region_line(g, p, blockIdx.x >> 1, &id0, &id1)) return;
-    const int64_t b = id0 / 256 + (blockIdx.x & 1);
-    if (b > id1 / 256) return;
-    const int64_t c = b / 256;
-    const int64_t i = c * 256 + threadIdx.x;
-    const Cand x = i < nb1 ? part1[i] : Cand{-1.0, -1.0, INT64_MAX};
-    const Cand best = block_best(x, order);
-    if (threadIdx.x == 0) part2[c] = best;
-}
-
-// the next target from the level-2 partials; none when nothing is unknown
-__global__ __launch_bounds__(256) void loop_pick_kernel(const Cand* __restrict__ part2, int64_t nb2,
-                                                        int order, LoopState* __restrict__ ls) {
-    Cand best{-1.0, -1.0, INT64_MAX};
-    for (int64_t i = threadIdx.x; i < nb2; i += blockDim.x) {
-        const Cand o = part2[i];
-        if (ranks_before(o, best, order)) best = o;
+__device__ inline Cand wave_best(Cand x, int order) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const Cand o = shfl_cand(x, off);
+        if (ranks_before(o, x, order)) x = o;
     }
-    const Cand b = block_best(best, order);
+    return x;
+}
+
+// Applies the previous iteration's answer (pending): copies the chosen patch
+// into the unknown in-bounds voxels of the target box, marks them known with
+// the target's confidence, logs the iteration and counts the filled voxels.
+// best: the float32 scan's packed (cost bits << 32 | id), or null when the
+// query wrote source and cost into the state. One workgroup.
+__global__ __launch_bounds__(256) void loop_apply_kernel(float* __restrict__ vol,
+                                                         uint8_t* __restrict__ mask,
+                                                         double* __restrict__ conf, Grid g,
+                                                         LoopState* __restrict__ ls,
+                                                         const uint64_t* __restrict__ best,
+                                                         int64_t cap, int64_t* __restrict__ lc,
+                                                         int64_t* __restrict__ lsrc,
+                                                         float* __restrict__ lcost) {
+    __shared__ int64_t sh_s;
+    __shared__ float sh_cost;
+    __shared__ int sh_filled;
+    const int64_t p = ls->centre;
+    // nothing pending: the last fill (applied by a standalone apply at the
+    // start of a round) keeps its region marked for the update that follows
+    if (!ls->pending) return;
     if (threadIdx.x == 0) {
-        const bool none = b.id == INT64_MAX || ls->unknown == 0;
-        ls->centre = none ? -1 : b.id;
-        ls->cpick = order == 0 ? b.c : -b.p;
+        int64_t s = ls->source;
+        float c = ls->cost;
+        if (best) {
+            const uint64_t b = best[0];
+            s = b == ~0ull ? -1 : (int64_t)(b & 0xffffffffull);
+            c = __uint_as_float((uint32_t)(b >> 32));
+        }
+        sh_s = s;
+        sh_cost = c;
+        sh_filled = 0;
+    }
+    __syncthreads();
+    const int64_t s = sh_s;
+    if (s >= 0) {
+        int64_t cp[kMaxDims], cs[kMaxDims];
+        coords_of(g, p, cp);
+        coords_of(g, s, cs);
+        const double cpick = ls->cpick;
+        int filled = 0;
+        for (int rho = threadIdx.x; rho < g.Kd; rho += blockDim.x) {
+            int64_t up = 0, us = 0;
+            bool inb = true;
+            int r = rho;
+            for (int a = g.nd - 1; a >= 0; a--) {
+                const int64_t o = (r % g.K) - g.h;
+                r /= g.K;
+                const int64_t x = cp[a] + o;
+                if (x < 0 || x >= g.shape[a]) inb = false;
+                up += x * g.stride[a];
+                us += (cs[a] + o) * g.stride[a];
+            }
+            if (!inb || mask[up]) continue;
+            for (int ch = 0; ch < g.C; ch++) vol[up * g.C + ch] = vol[us * g.C + ch];
+            mask[up] = 1;
+            conf[up] = cpick;
+            filled++;
+        }
+        if (filled) atomicAdd(&sh_filled, filled);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ls->pending = 0;
+        if (s >= 0) {
+            const int64_t it = ls->it;
+            if (it < cap) {
+                lc[it] = p;
+                lsrc[it] = s;
+                lcost[it] = sh_cost;
+            }
+            ls->it = it + 1;
+            ls->last = p;
+            ls->unknown -= (unsigned long long)sh_filled;
+        } else {
+            ls->last = -1;
+        }
     }
 }
 
-// As fill_kernel, with the iteration count, the last centre and the unknown
-// count kept in the loop state.
-__global__ void loop_fill_kernel(float* __restrict__ vol, uint8_t* __restrict__ mask,
-                                 double* __restrict__ conf, Grid g, LoopState* __restrict__ ls,
-                                 int64_t cap, int64_t* __restrict__ lc, int64_t* __restrict__ ls_src,
-                                 float* __restrict__ lcost) {
-    const int rho = blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = ls->centre, s = ls->source;
-    if (p < 0 || s < 0) return;
-    if (rho == 0) {
-        const int64_t it = ls->it;
-        if (it < cap) {
-            lc[it] = p;
-            ls_src[it] = s;
-            lcost[it] = ls->cost;
+// One workgroup: the level-1 and level-2 partials that the last fill's
+// region touches, the next target, and its extraction (t, m; for the
+// float32 scan also query slot 0 of the padded targets and row masks, and a
+// cleared result).
+constexpr int kSelThreads = 1024;
+__global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
+    const float* __restrict__ vol, const uint8_t* __restrict__ mask, Grid g, int order,
+    const Cand* __restrict__ pv, Cand* __restrict__ part1, int64_t nb1, Cand* __restrict__ part2,
+    int64_t nb2, LoopState* __restrict__ ls, float* __restrict__ t, uint8_t* __restrict__ m,
+    float* __restrict__ tp, uint32_t* __restrict__ rm, int64_t qpad, uint64_t* __restrict__ best) {
+    constexpr int NW = kSelThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Cand none{-1.0, -1.0, INT64_MAX};
+    const int64_t p = ls->last;
+    if (p >= 0) {
+        int64_t lines = 1;
+        for (int a = 0; a < g.nd - 1; a++) lines *= 2 * g.K - 1;
+        // level 1: one wave per (region line, block of 256 voxels)
+        for (int64_t u = wave; u < 2 * lines; u += NW) {
+            int64_t id0, id1;
+            if (!region_line(g, p, u >> 1, &id0, &id1)) continue;
+            const int64_t b = id0 / 256 + (u & 1);
+            if (b > id1 / 256) continue;
+            Cand x = none;
+            for (int k = lane; k < 256; k += 64) {
+                const int64_t i = b * 256 + k;
+                if (i < g.nvox && ranks_before(pv[i], x, order)) x = pv[i];
+            }
+            x = wave_best(x, order);
+            if (lane == 0) part1[b] = x;
         }
-        ls->it = it + 1;
-        ls->last = p;
+        __syncthreads();
+        // level 2 over the changed level-1 blocks
+        for (int64_t u = wave; u < 2 * lines; u += NW) {
+            int64_t id0, id1;
+            if (!region_line(g, p, u >> 1, &id0, &id1)) continue;
+            const int64_t b = id0 / 256 + (u & 1);
+            if (b > id1 / 256) continue;
+            const int64_t c = b / 256;
+            Cand x = none;
+            for (int k = lane; k < 256; k += 64) {
+                const int64_t i = c * 256 + k;
+                if (i < nb1 && ranks_before(part1[i], x, order)) x = part1[i];
+            }
+            x = wave_best(x, order);
+            if (lane == 0) part2[c] = x;
+        }
+        __syncthreads();
     }
-    if (rho >= g.Kd) return;
-    int64_t cp[kMaxDims], cs[kMaxDims];
-    coords_of(g, p, cp);
-    coords_of(g, s, cs);
-    int64_t up = 0, us = 0;
-    bool inb = true;
-    int r = rho;
-    for (int a = g.nd - 1; a >= 0; a--) {
-        const int64_t o = (r % g.K) - g.h;
-        r /= g.K;
-        const int64_t x = cp[a] + o;
-        if (x < 0 || x >= g.shape[a]) inb = false;
-        up += x * g.stride[a];
-        us += (cs[a] + o) * g.stride[a];
+    // the next target
+    __shared__ Cand sb[NW];
+    __shared__ int64_t sh_centre;
+    Cand x = none;
+    for (int64_t i = threadIdx.x; i < nb2; i += kSelThreads)
+        if (ranks_before(part2[i], x, order)) x = part2[i];
+    x = wave_best(x, order);
+    if (lane == 0) sb[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Cand b = sb[0];
+        for (int w = 1; w < NW; w++)
+            if (ranks_before(sb[w], b, order)) b = sb[w];
+        const bool nothing = b.id == INT64_MAX || ls->unknown == 0;
+        const int64_t c = nothing ? -1 : b.id;
+        ls->centre = c;
+        ls->cpick = order == 0 ? b.c : -b.p;
+        ls->pending = c >= 0 ? 1 : 0;
+        sh_centre = c;
+        if (best) best[0] = ~0ull;
     }
-    if (!inb || mask[up]) return;
-    for (int ch = 0; ch < g.C; ch++) vol[up * g.C + ch] = vol[us * g.C + ch];
-    mask[up] = 1;
-    conf[up] = ls->cpick;
-    atomicAdd(&ls->unknown, ~0ull);   // minus one
+    __syncthreads();
+    const int64_t c = sh_centre;
+    if (c < 0) return;
+    // extraction of the target at c
+    int64_t cc[kMaxDims];
+    coords_of(g, c, cc);
+    for (int rho = threadIdx.x; rho < g.Kd; rho += kSelThreads) {
+        int64_t v = 0;
+        bool inb = true;
+        int r = rho;
+        for (int a = g.nd - 1; a >= 0; a--) {
+            const int64_t xx = cc[a] + (r % g.K) - g.h;
+            r /= g.K;
+            if (xx < 0 || xx >= g.shape[a]) inb = false;
+            v += xx * g.stride[a];
+        }
+        const bool known = inb && mask[v];
+        m[rho] = known ? 1 : 0;
+        for (int ch = 0; ch < g.C; ch++) {
+            const float val = known ? vol[v * g.C + ch] : 0.0f;
+            t[rho * g.C + ch] = val;
+            if (tp) tp[rho * g.C + ch] = val;
+        }
+    }
+    if (rm) {
+        // row r of the patch: bit dx set when pixel r*K + dx is known
+        for (int r = threadIdx.x; r < g.rows; r += kSelThreads) {
+            int rr = r;
+            int64_t base = 0;
+            bool inrow = true;
+            for (int a = g.nd - 2; a >= 0; a--) {
+                const int64_t xx = cc[a] + (rr % g.K) - g.h;
+                rr /= g.K;
+                if (xx < 0 || xx >= g.shape[a]) inrow = false;
+                base += xx * g.stride[a];
+            }
+            uint32_t bits = 0;
+            const int f = g.nd - 1;
+            for (int dx = 0; dx < g.K; dx++) {
+                const int64_t xx = cc[f] + dx - g.h;
+                if (inrow && xx >= 0 && xx < g.shape[f] && mask[base + xx]) bits |= 1u << dx;
+            }
+            rm[(int64_t)r * qpad] = bits;
+        }
+    }
 }
 
 __global__ void conf_init_kernel(const uint8_t* __restrict__ mask, int64_t n, double* __restrict__ conf) {
@@ -477,9 +590,17 @@ sfc_status launch_loop_init(const float* vol, const uint8_t* mask, const double*
     return launched("part_all_kernel");
 }
 
-sfc_status launch_loop_pick(const float* vol, const uint8_t* mask, const double* conf, const Grid& g,
-                            int order, void* pv, void* part1, void* part2, LoopState* ls,
-                            hipStream_t st) {
+sfc_status launch_loop_apply(float* vol, uint8_t* mask, double* conf, const Grid& g, LoopState* ls,
+                             const uint64_t* best, int64_t cap, int64_t* lc, int64_t* lsrc,
+                             float* lcost, hipStream_t st) {
+    loop_apply_kernel<<<1, 256, 0, st>>>(vol, mask, conf, g, ls, best, cap, lc, lsrc, lcost);
+    return launched("loop_apply_kernel");
+}
+
+sfc_status launch_loop_select(const float* vol, const uint8_t* mask, const double* conf,
+                              const Grid& g, int order, void* pv, void* part1, void* part2,
+                              LoopState* ls, float* t, uint8_t* m, float* tp, uint32_t* rm,
+                              int64_t qpad, uint64_t* best, hipStream_t st) {
     int64_t nb1, nb2;
     loop_part_entries(g, &nb1, &nb2);
     int64_t lines = 1;
@@ -487,20 +608,11 @@ sfc_status launch_loop_pick(const float* vol, const uint8_t* mask, const double*
     region_cand_kernel<<<(unsigned)lines, 256, 0, st>>>(vol, mask, conf, g, order, ls,
                                                         static_cast<Cand*>(pv));
     SFC_TRY(launched("region_cand_kernel"));
-    region_part1_kernel<<<(unsigned)(2 * lines), 256, 0, st>>>(static_cast<const Cand*>(pv), g, order, ls,
-                                                              static_cast<Cand*>(part1));
-    SFC_TRY(launched("region_part1_kernel"));
-    region_part2_kernel<<<(unsigned)(2 * lines), 256, 0, st>>>(static_cast<const Cand*>(part1), nb1, g,
-                                                              order, ls, static_cast<Cand*>(part2));
-    SFC_TRY(launched("region_part2_kernel"));
-    loop_pick_kernel<<<1, 256, 0, st>>>(static_cast<const Cand*>(part2), nb2, order, ls);
-    return launched("loop_pick_kernel");
-}
-
-sfc_status launch_loop_fill(float* vol, uint8_t* mask, double* conf, const Grid& g, LoopState* ls,
-                            int64_t cap, int64_t* lc, int64_t* lsrc, float* lcost, hipStream_t st) {
-    loop_fill_kernel<<<blocks_for(g.Kd), 256, 0, st>>>(vol, mask, conf, g, ls, cap, lc, lsrc, lcost);
-    return launched("loop_fill_kernel");
+    loop_select_kernel<<<1, kSelThreads, 0, st>>>(vol, mask, g, order, static_cast<const Cand*>(pv),
+                                                  static_cast<Cand*>(part1), nb1,
+                                                  static_cast<Cand*>(part2), nb2, ls, t, m, tp, rm,
+                                                  qpad, best);
+    return launched("loop_select_kernel");
 }
 
 sfc_status launch_fill(float* vol, uint8_t* mask, double* conf, const Grid& g, const int64_t* centre,

@@ -11,6 +11,7 @@ namespace sfc {
 
 namespace {
 
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef const __attribute__((address_space(4))) float cfloat_as4;
 typedef const __attribute__((address_space(4))) uint32_t cu32_as4;
 __device__ inline float ldu(const float* p) { return *(cfloat_as4*)p; }
@@ -244,11 +245,14 @@ __device__ inline bool key_less(const uint64_t* K, int64_t n, int64_t pos, const
 }
 
 // One wave per (query, curve): first position whose key is >= the query key,
-// by rounds of 64 probes splitting the interval into 65 parts (ballot gives
-// the number of probes below the key), then a final round over <= 64 entries.
+// by rounds of 256 probes (four per lane, issued together) splitting the
+// interval into 257 parts; the ballots count the probes below the key. A
+// last round checks the <= 256 remaining entries the same way.
+constexpr int kProbes = 4;
 __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int32_t* __restrict__ qsub,
                                                      const uint64_t* __restrict__ qkeys, int64_t Q,
                                                      int64_t* __restrict__ wstart) {
+    constexpr int NP = 64 * kProbes;
     const int lane = threadIdx.x & 63;
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (wid >= Q * v.L) return;
@@ -259,19 +263,30 @@ __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int
     uint64_t qk[kMaxKeyWords];
     for (int w = 0; w < v.W64; w++) qk[w] = qkeys[(q * v.L + j) * v.W64 + w];
     int64_t a = 0, z = v.n;
-    while (z - a > 64) {
+    while (z - a > NP) {
         const int64_t len = z - a;
-        const int64_t pos = a + ((int64_t)(lane + 1) * len) / 65;
-        const bool less = key_less(K, v.n, pos, qk, v.W64);
-        const int cnt = __popcll(__ballot(less));
-        const int64_t na = cnt > 0 ? a + ((int64_t)cnt * len) / 65 + 1 : a;
-        const int64_t nz = cnt < 64 ? a + ((int64_t)(cnt + 1) * len) / 65 : z;
+        bool less[kProbes];
+#pragma unroll
+        for (int k = 0; k < kProbes; k++) {
+            const int64_t pos = a + ((int64_t)(lane * kProbes + k + 1) * len) / (NP + 1);
+            less[k] = key_less(K, v.n, pos, qk, v.W64);
+        }
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kProbes; k++) cnt += __popcll(__ballot(less[k]));
+        const int64_t na = cnt > 0 ? a + ((int64_t)cnt * len) / (NP + 1) + 1 : a;
+        const int64_t nz = cnt < NP ? a + ((int64_t)(cnt + 1) * len) / (NP + 1) : z;
         a = na;
         z = nz;
     }
     const int64_t len = z - a;
-    const bool less = lane < len && key_less(K, v.n, a + lane, qk, v.W64);
-    const int64_t p = a + __popcll(__ballot(less));
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kProbes; k++) {
+        const int i = lane * kProbes + k;
+        cnt += __popcll(__ballot(i < len && key_less(K, v.n, a + i, qk, v.W64)));
+    }
+    const int64_t p = a + cnt;
     int64_t lo = p - v.window / 2;
     int64_t lmax = v.n - v.window;
     if (lmax < 0) lmax = 0;
@@ -299,8 +314,19 @@ __device__ inline float cand_cost(const QueryIndexView& v, const float* __restri
         else roff = (int64_t)(r / K - H) * v.stride[0] + (int64_t)(r % K - H) * v.stride[1] - H;
         const float* vp = vol + ((int64_t)c + roff) * C;
         float vv[RW];
+        // the row's K*C floats by 16-byte loads at 4-byte alignment (global
+        // loads of this width need only dword alignment)
+        const f4u* vp4 = reinterpret_cast<const f4u*>(vp);
 #pragma unroll
-        for (int i = 0; i < RW; i++) vv[i] = vp[i];
+        for (int i = 0; i < RW / 4; i++) {
+            const f4u x = vp4[i];
+            vv[4 * i] = x.x;
+            vv[4 * i + 1] = x.y;
+            vv[4 * i + 2] = x.z;
+            vv[4 * i + 3] = x.w;
+        }
+#pragma unroll
+        for (int i = (RW / 4) * 4; i < RW; i++) vv[i] = vp[i];
         const float* tp = tq + (int64_t)r * RW;
 #pragma unroll
         for (int dx = 0; dx < K; dx++) {

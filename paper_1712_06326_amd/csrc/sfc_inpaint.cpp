@@ -74,20 +74,21 @@ struct LoopBufs {
     float* lcost;
 };
 
-// One iteration on the handle's stream (kernel launches only).
+// One iteration on the handle's stream (kernel launches only): apply the
+// previous iteration's answer, refresh the priorities around it, pick and
+// extract the next target, query it.
 sfc_status loop_body(sfc_index* ix, const LoopBufs& b) {
     const Grid& g = ix->g;
     hipStream_t st = ix->st;
-    SFC_TRY(launch_loop_pick(b.vol, b.mask, b.conf, g, b.order, b.pv, b.part1, b.part2, b.state, st));
-    SFC_TRY(launch_extract(b.vol, b.mask, g, &b.state->centre, 1, b.t, b.m, st));
-    if (b.mode == SFC_MODE_BRUTE_FP32) {
-        SFC_TRY(scan_fp32_on(ix, b.t, b.m, 1, b.rm, b.tp, b.best));
-        SFC_TRY(launch_unpack_best(b.best, 1, &b.state->source, &b.state->cost, st));
-    } else {
-        SFC_TRY(query_index_on(ix, b.t, b.m, 1, b.qbuf, &b.state->source, &b.state->cost, nullptr,
-                               nullptr));
-    }
-    return launch_loop_fill(b.vol, b.mask, b.conf, g, b.state, b.cap, b.lc, b.ls, b.lcost, st);
+    const bool scan = b.mode == SFC_MODE_BRUTE_FP32;
+    SFC_TRY(launch_loop_apply(b.vol, b.mask, b.conf, g, b.state, scan ? b.best : nullptr, b.cap,
+                              b.lc, b.ls, b.lcost, st));
+    SFC_TRY(launch_loop_select(b.vol, b.mask, b.conf, g, b.order, b.pv, b.part1, b.part2, b.state,
+                               b.t, b.m, scan ? b.tp : nullptr, scan ? b.rm : nullptr,
+                               scan_qpad(1), scan ? b.best : nullptr, st));
+    if (scan) return scan_fp32_prepared(ix, 1, b.rm, b.tp, b.best);
+    return query_index_on(ix, b.t, b.m, 1, b.qbuf, &b.state->source, &b.state->cost, nullptr,
+                          nullptr);
 }
 
 sfc_status capture(sfc_index* ix, const LoopBufs& b, int iters, hipGraphExec_t* out) {
@@ -153,6 +154,9 @@ sfc_status device_loop(sfc_index* ix, float* volume, uint8_t* mask, double* conf
         SFC_TRY(mem.alloc((void**)&b.rm, (size_t)qpad * g.rows * 4, "row masks"));
         SFC_TRY(mem.alloc((void**)&b.tp, (size_t)qpad * g.Kd * g.C * 4, "padded target"));
         SFC_TRY(mem.alloc((void**)&b.best, 8, "scan result"));
+        // query slots 1.. of the padded target and row masks stay zero
+        SFC_TRY(launch_zero_f32(b.tp, qpad * g.Kd * g.C, res.ls));
+        SFC_TRY(launch_zero_f32(reinterpret_cast<float*>(b.rm), qpad * g.rows, res.ls));
     }
     SFC_TRY(launch_loop_init(volume, mask, conf, g, order, b.pv, b.part1, b.part2, b.state, res.ls));
 
@@ -162,14 +166,19 @@ sfc_status device_loop(sfc_index* ix, float* volume, uint8_t* mask, double* conf
     SFC_TRY(capture(ix, b, 1, &res.g1));
     SFC_TRY(capture(ix, b, 16, &res.g16));
     LoopState h{};
-    int64_t prev_it = -1;
+    unsigned long long prev_unknown = ~0ull;
+    const uint64_t* abest = mode == SFC_MODE_BRUTE_FP32 ? b.best : nullptr;
     for (;;) {
+        // the last iteration's answer, so the unknown count is current
+        SFC_TRY(launch_loop_apply(volume, mask, conf, g, b.state, abest, cap, lc, lsrc, lcost, res.ls));
         SFC_HIP(hipMemcpyAsync(&h, b.state, sizeof(h), hipMemcpyDeviceToHost, res.ls));
         SFC_HIP(hipStreamSynchronize(res.ls));
         if (h.unknown == 0) break;
-        if (h.it == prev_it)   // a whole round without a target
+        // every iteration with a target fills at least one voxel, so a whole
+        // round that leaves the unknown count unchanged had no target
+        if (h.unknown >= prev_unknown)
             return fail(SFC_EEMPTY, "unknown voxels remain but the fill front is empty");
-        prev_it = h.it;
+        prev_unknown = h.unknown;
         int64_t r = (int64_t)(h.unknown / (unsigned long long)g.Kd);
         if (r < 1) r = 1;
         for (; r >= 16; r -= 16) SFC_HIP(hipGraphLaunch(res.g16, res.ls));
