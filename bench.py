@@ -339,6 +339,28 @@ def main():
                 np.sqrt(ck[ok].astype(np.float64)) / np.sqrt(bc_s[ok]) - 1.0)) * 100, 4)}
         log(f"k-NN query: {k_ms:.2f} ms for {Qs} queries")
 
+    # the index rescoring's gather: algorithmic bytes = every candidate's
+    # known elements (float32), per query, over one launch
+    if cfg.get("D") and "rescore_kernel" in kavg:
+        ixc = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], **w.opts)
+        fc = native.fill_front(w.mask)
+        tc, mc = native.extract_targets(w.vol, w.mask, K, fc)
+        _, ncq = ixc.candidates(tc, mc)
+        ixc.close()
+        known_q = mc.sum(dim=1).double()
+        gbytes = float((ncq.double() * known_q).sum().item()) * C * 4
+        roofs["rescore_kernel"] = {
+            "bound": "hbm", "kernel": "rescore_kernel",
+            "achieved": gbytes / (kavg["rescore_kernel"] * 1e-3) / 1e9,
+            "peak": PEAK_HBM, "unit": "GB/s", "traffic": None,
+            "work_per_launch": f"{gbytes:.4g} bytes = sum over queries of candidates x known "
+                               f"elements x 4 (mean {float(ncq.double().mean()):.1f} candidates)"}
+        roofs["rescore_kernel"]["achieved"] = round(roofs["rescore_kernel"]["achieved"], 1)
+        roofs["rescore_kernel"]["frac"] = round(roofs["rescore_kernel"]["achieved"] / PEAK_HBM, 4)
+        roofs["rescore_kernel"]["avg_ms"] = round(kavg["rescore_kernel"], 3)
+        forms["rooflines"]["rescore_kernel"] = roofs["rescore_kernel"]
+        del fc, tc, mc
+
     # the brute-force reduced-precision form without an index seed: the
     # two-pass bf16 filter (tile minima, then the tiles that can reach them)
     if cfg["bf16"]:

@@ -56,76 +56,76 @@ __device__ inline Cand shfl_cand(const Cand& x, int off) {
     return y;
 }
 
-// The fill-order candidate of voxel v: (P, C, id) for a front voxel under
-// order 0 (Criminisi), (-C, 0, id) under order 1 (raster: only the id ranks,
-// C is carried for the confidence update); {-1, -1, max} otherwise.
+// The candidate of front voxel v (coordinates c) whose box confidence sum
+// is cs: (P, C, id) under order 0 (Criminisi), (-C, 0, id) under order 1
+// (raster: only the id ranks, C is carried for the confidence update).
+__device__ inline Cand cand_from_box(const float* __restrict__ vol, const uint8_t* __restrict__ mask,
+                                     const Grid& g, int order, int64_t v, const int64_t* c,
+                                     double cs) {
+    const double Cp = cs / (double)g.Kd;
+    if (order != 0) return Cand{-Cp, 0.0, v};   // carried, not compared (see reduce with order 1)
+    double gr[kMaxDims], nr[kMaxDims], nn = 0.0;
+    const double I0 = mean_intensity(vol, v, g.C);
+    for (int i = 0; i < g.nd; i++) {
+        const bool hasp = c[i] + 1 < g.shape[i], hasm = c[i] > 0;
+        const int64_t vp = v + g.stride[i], vm = v - g.stride[i];
+        const bool kp = hasp && mask[vp], km = hasm && mask[vm];
+        if (kp && km)
+            gr[i] = (mean_intensity(vol, vp, g.C) - mean_intensity(vol, vm, g.C)) / 2.0;
+        else if (kp)
+            gr[i] = mean_intensity(vol, vp, g.C) - I0;
+        else if (km)
+            gr[i] = I0 - mean_intensity(vol, vm, g.C);
+        else
+            gr[i] = 0.0;
+        const int ip = hasp ? mask[vp] : 1, im = hasm ? mask[vm] : 1;
+        nr[i] = (double)(ip - im);
+        nn += nr[i] * nr[i];
+    }
+    double Dp = 0.0;
+    if (nn > 0.0) {
+        const double len = sqrt(nn);
+        for (int i = 0; i < g.nd; i++) nr[i] = nr[i] / len;
+        if (g.nd == 2) {
+            Dp = fabs(gr[0] * nr[1] - gr[1] * nr[0]);
+        } else {
+            const double c0 = gr[1] * nr[2] - gr[2] * nr[1];
+            const double c1 = gr[2] * nr[0] - gr[0] * nr[2];
+            const double c2 = gr[0] * nr[1] - gr[1] * nr[0];
+            Dp = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        }
+    }
+    return Cand{Cp * Dp, Cp, v};
+}
+
+// The fill-order candidate of voxel v: cand_from_box for a front voxel,
+// {-1, -1, max} otherwise.
 __device__ inline Cand voxel_cand(const float* __restrict__ vol, const uint8_t* __restrict__ mask,
                                   const double* __restrict__ conf, const Grid& g, int order,
                                   int64_t v) {
-    Cand best{-1.0, -1.0, INT64_MAX};
-    if (mask[v]) {
-        int64_t c[kMaxDims];
-        coords_of(g, v, c);
-        bool front = false;
-        for (int i = 0; i < g.nd; i++) {
-            if (c[i] > 0 && !mask[v - g.stride[i]]) front = true;
-            if (c[i] + 1 < g.shape[i] && !mask[v + g.stride[i]]) front = true;
-        }
-        if (front) {
-            double cs = 0.0;
-            for (int rho = 0; rho < g.Kd; rho++) {
-                int64_t u = 0;
-                bool inb = true;
-                int r = rho;
-                for (int a = g.nd - 1; a >= 0; a--) {
-                    const int64_t x = c[a] + (r % g.K) - g.h;
-                    r /= g.K;
-                    if (x < 0 || x >= g.shape[a]) inb = false;
-                    u += x * g.stride[a];
-                }
-                if (inb && mask[u]) cs += conf[u];
-            }
-            const double Cp = cs / (double)g.Kd;
-            if (order == 0) {
-                double gr[kMaxDims], nr[kMaxDims], nn = 0.0;
-                const double I0 = mean_intensity(vol, v, g.C);
-                for (int i = 0; i < g.nd; i++) {
-                    const bool hasp = c[i] + 1 < g.shape[i], hasm = c[i] > 0;
-                    const int64_t vp = v + g.stride[i], vm = v - g.stride[i];
-                    const bool kp = hasp && mask[vp], km = hasm && mask[vm];
-                    if (kp && km)
-                        gr[i] = (mean_intensity(vol, vp, g.C) - mean_intensity(vol, vm, g.C)) / 2.0;
-                    else if (kp)
-                        gr[i] = mean_intensity(vol, vp, g.C) - I0;
-                    else if (km)
-                        gr[i] = I0 - mean_intensity(vol, vm, g.C);
-                    else
-                        gr[i] = 0.0;
-                    const int ip = hasp ? mask[vp] : 1, im = hasm ? mask[vm] : 1;
-                    nr[i] = (double)(ip - im);
-                    nn += nr[i] * nr[i];
-                }
-                double Dp = 0.0;
-                if (nn > 0.0) {
-                    const double len = sqrt(nn);
-                    for (int i = 0; i < g.nd; i++) nr[i] = nr[i] / len;
-                    if (g.nd == 2) {
-                        Dp = fabs(gr[0] * nr[1] - gr[1] * nr[0]);
-                    } else {
-                        const double c0 = gr[1] * nr[2] - gr[2] * nr[1];
-                        const double c1 = gr[2] * nr[0] - gr[0] * nr[2];
-                        const double c2 = gr[0] * nr[1] - gr[1] * nr[0];
-                        Dp = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-                    }
-                }
-                best = Cand{Cp * Dp, Cp, v};
-            } else {
-                // raster: only the id ranks; keep Cp for the confidence update
-                best = Cand{-Cp, 0.0, v};   // carried, not compared (see reduce with order 1)
-            }
-        }
+    if (!mask[v]) return Cand{-1.0, -1.0, INT64_MAX};
+    int64_t c[kMaxDims];
+    coords_of(g, v, c);
+    bool front = false;
+    for (int i = 0; i < g.nd; i++) {
+        if (c[i] > 0 && !mask[v - g.stride[i]]) front = true;
+        if (c[i] + 1 < g.shape[i] && !mask[v + g.stride[i]]) front = true;
     }
-    return best;
+    if (!front) return Cand{-1.0, -1.0, INT64_MAX};
+    double cs = 0.0;
+    for (int rho = 0; rho < g.Kd; rho++) {
+        int64_t u = 0;
+        bool inb = true;
+        int r = rho;
+        for (int a = g.nd - 1; a >= 0; a--) {
+            const int64_t x = c[a] + (r % g.K) - g.h;
+            r /= g.K;
+            if (x < 0 || x >= g.shape[a]) inb = false;
+            u += x * g.stride[a];
+        }
+        if (inb && mask[u]) cs += conf[u];
+    }
+    return cand_from_box(vol, mask, g, order, v, c, cs);
 }
 
 __device__ inline bool ranks_before(const Cand& a, const Cand& b, int order) {
@@ -317,19 +317,75 @@ __device__ inline int64_t region_lines(const Grid& g) {
     return n;
 }
 
-// candidates of the region around the last filled centre; one workgroup per
-// region line, a thread per voxel of it (2K - 1 <= 256 for K <= 127)
+// candidates of the region around the last filled centre: one wave per
+// voxel of the region, four per workgroup. The lanes load the voxel's box
+// (confidence where known and in bounds, else +0, which leaves the sum
+// unchanged) into LDS in parallel; lane 0 then adds them in ascending rho,
+// the definition's order, and finishes the candidate.
+constexpr int kBoxChunk = 512;   // box values staged per wave at a time
 __global__ __launch_bounds__(256) void region_cand_kernel(const float* __restrict__ vol,
                                                           const uint8_t* __restrict__ mask,
                                                           const double* __restrict__ conf, Grid g,
                                                           int order, const LoopState* __restrict__ ls,
                                                           Cand* __restrict__ pv) {
+    __shared__ double box_lds[4][kBoxChunk];
     const int64_t p = ls->last;
     if (p < 0) return;
-    int64_t id0, id1;
-    if (!region_line(g, p, blockIdx.x, &id0, &id1)) return;
-    const int64_t v = id0 + threadIdx.x;
-    if (v <= id1) pv[v] = voxel_cand(vol, mask, conf, g, order, v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int R = g.K - 1, side = 2 * R + 1;
+    int64_t nreg = 1;
+    for (int a = 0; a < g.nd; a++) nreg *= side;
+    const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+    if (k >= nreg) return;
+    // the region voxel: offsets in [-R, R] per axis, last axis fastest
+    int64_t cp[kMaxDims], c[kMaxDims];
+    coords_of(g, p, cp);
+    int64_t kk = k, v = 0;
+    for (int a = g.nd - 1; a >= 0; a--) {
+        c[a] = cp[a] + (kk % side) - R;
+        kk /= side;
+        if (c[a] < 0 || c[a] >= g.shape[a]) return;
+        v += c[a] * g.stride[a];
+    }
+    if (!mask[v]) {
+        if (lane == 0) pv[v] = Cand{-1.0, -1.0, INT64_MAX};
+        return;
+    }
+    bool front = false;
+    for (int i = 0; i < g.nd; i++) {
+        if (c[i] > 0 && !mask[v - g.stride[i]]) front = true;
+        if (c[i] + 1 < g.shape[i] && !mask[v + g.stride[i]]) front = true;
+    }
+    if (!front) {
+        if (lane == 0) pv[v] = Cand{-1.0, -1.0, INT64_MAX};
+        return;
+    }
+    double* bx = box_lds[wave];
+    double cs = 0.0;
+    for (int base = 0; base < g.Kd; base += kBoxChunk) {
+        const int n = g.Kd - base < kBoxChunk ? g.Kd - base : kBoxChunk;
+        for (int i = lane; i < n; i += 64) {
+            int64_t u = 0;
+            bool inb = true;
+            int r = base + i;
+            for (int a = g.nd - 1; a >= 0; a--) {
+                const int64_t x = c[a] + (r % g.K) - g.h;
+                r /= g.K;
+                if (x < 0 || x >= g.shape[a]) inb = false;
+                u += x * g.stride[a];
+            }
+            bx[i] = (inb && mask[u]) ? conf[u] : 0.0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0)
+            for (int i = 0; i < n; i++) cs += bx[i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (lane == 0) pv[v] = cand_from_box(vol, mask, g, order, v, c, cs);
 }
 
 __device__ inline Cand wave_best(Cand x, int order) {
@@ -424,6 +480,7 @@ __global__ __launch_bounds__(256) void loop_apply_kernel(float* __restrict__ vol
 // float32 scan also query slot 0 of the padded targets and row masks, and a
 // cleared result).
 constexpr int kSelThreads = 1024;
+constexpr int64_t kOneLevel = 16384;   // level-1 entries the pick reads directly (4M voxels)
 __global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
     const float* __restrict__ vol, const uint8_t* __restrict__ mask, Grid g, int order,
     const Cand* __restrict__ pv, Cand* __restrict__ part1, int64_t nb1, Cand* __restrict__ part2,
@@ -451,8 +508,9 @@ __global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
             if (lane == 0) part1[b] = x;
         }
         __syncthreads();
-        // level 2 over the changed level-1 blocks
-        for (int64_t u = wave; u < 2 * lines; u += NW) {
+        // level 2 over the changed level-1 blocks (not needed when the pick
+        // reads level 1 directly)
+        for (int64_t u = wave; u < 2 * lines && nb1 > kOneLevel; u += NW) {
             int64_t id0, id1;
             if (!region_line(g, p, u >> 1, &id0, &id1)) continue;
             const int64_t b = id0 / 256 + (u & 1);
@@ -472,8 +530,10 @@ __global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
     __shared__ Cand sb[NW];
     __shared__ int64_t sh_centre;
     Cand x = none;
-    for (int64_t i = threadIdx.x; i < nb2; i += kSelThreads)
-        if (ranks_before(part2[i], x, order)) x = part2[i];
+    const Cand* top = nb1 > kOneLevel ? part2 : part1;
+    const int64_t ntop = nb1 > kOneLevel ? nb2 : nb1;
+    for (int64_t i = threadIdx.x; i < ntop; i += kSelThreads)
+        if (ranks_before(top[i], x, order)) x = top[i];
     x = wave_best(x, order);
     if (lane == 0) sb[wave] = x;
     __syncthreads();
@@ -603,10 +663,10 @@ sfc_status launch_loop_select(const float* vol, const uint8_t* mask, const doubl
                               int64_t qpad, uint64_t* best, hipStream_t st) {
     int64_t nb1, nb2;
     loop_part_entries(g, &nb1, &nb2);
-    int64_t lines = 1;
-    for (int a = 0; a < g.nd - 1; a++) lines *= 2 * g.K - 1;
-    region_cand_kernel<<<(unsigned)lines, 256, 0, st>>>(vol, mask, conf, g, order, ls,
-                                                        static_cast<Cand*>(pv));
+    int64_t nreg = 1;
+    for (int a = 0; a < g.nd; a++) nreg *= 2 * g.K - 1;
+    region_cand_kernel<<<(unsigned)((nreg + 3) / 4), 256, 0, st>>>(vol, mask, conf, g, order, ls,
+                                                                 static_cast<Cand*>(pv));
     SFC_TRY(launched("region_cand_kernel"));
     loop_select_kernel<<<1, kSelThreads, 0, st>>>(vol, mask, g, order, static_cast<const Cand*>(pv),
                                                   static_cast<Cand*>(part1), nb1,

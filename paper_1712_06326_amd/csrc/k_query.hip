@@ -44,6 +44,7 @@ sfc_status launched(const char* what) {
 //     exchanges in float64).
 //  5. The grid cell, then one key per shifted curve (lane j: curve j).
 constexpr int kPrologueLanes = 16;
+constexpr int64_t kPrologueWideQ = 256;   // up to this many queries: 64 lanes per query
 constexpr int kMaxKnownWords = 16;   // K^nd <= 1024
 constexpr int kMaxSubsets = 26;      // 3^3 - 1
 
@@ -245,14 +246,11 @@ __device__ inline bool key_less(const uint64_t* K, int64_t n, int64_t pos, const
 }
 
 // One wave per (query, curve): first position whose key is >= the query key,
-// by rounds of 256 probes (four per lane, issued together) splitting the
-// interval into 257 parts; the ballots count the probes below the key. A
-// last round checks the <= 256 remaining entries the same way.
-constexpr int kProbes = 4;
+// by rounds of 64 probes splitting the interval into 65 parts (ballot gives
+// the number of probes below the key), then a final round over <= 64 entries.
 __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int32_t* __restrict__ qsub,
                                                      const uint64_t* __restrict__ qkeys, int64_t Q,
                                                      int64_t* __restrict__ wstart) {
-    constexpr int NP = 64 * kProbes;
     const int lane = threadIdx.x & 63;
     const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (wid >= Q * v.L) return;
@@ -263,30 +261,19 @@ __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int
     uint64_t qk[kMaxKeyWords];
     for (int w = 0; w < v.W64; w++) qk[w] = qkeys[(q * v.L + j) * v.W64 + w];
     int64_t a = 0, z = v.n;
-    while (z - a > NP) {
+    while (z - a > 64) {
         const int64_t len = z - a;
-        bool less[kProbes];
-#pragma unroll
-        for (int k = 0; k < kProbes; k++) {
-            const int64_t pos = a + ((int64_t)(lane * kProbes + k + 1) * len) / (NP + 1);
-            less[k] = key_less(K, v.n, pos, qk, v.W64);
-        }
-        int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < kProbes; k++) cnt += __popcll(__ballot(less[k]));
-        const int64_t na = cnt > 0 ? a + ((int64_t)cnt * len) / (NP + 1) + 1 : a;
-        const int64_t nz = cnt < NP ? a + ((int64_t)(cnt + 1) * len) / (NP + 1) : z;
+        const int64_t pos = a + ((int64_t)(lane + 1) * len) / 65;
+        const bool less = key_less(K, v.n, pos, qk, v.W64);
+        const int cnt = __popcll(__ballot(less));
+        const int64_t na = cnt > 0 ? a + ((int64_t)cnt * len) / 65 + 1 : a;
+        const int64_t nz = cnt < 64 ? a + ((int64_t)(cnt + 1) * len) / 65 : z;
         a = na;
         z = nz;
     }
     const int64_t len = z - a;
-    int cnt = 0;
-#pragma unroll
-    for (int k = 0; k < kProbes; k++) {
-        const int i = lane * kProbes + k;
-        cnt += __popcll(__ballot(i < len && key_less(K, v.n, a + i, qk, v.W64)));
-    }
-    const int64_t p = a + cnt;
+    const bool less = lane < len && key_less(K, v.n, a + lane, qk, v.W64);
+    const int64_t p = a + __popcll(__ballot(less));
     int64_t lo = p - v.window / 2;
     int64_t lmax = v.n - v.window;
     if (lmax < 0) lmax = 0;
@@ -297,6 +284,7 @@ __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int
 
 // ------------------------------------------------------------ rescore
 constexpr int kCap = 2048;   // maximum L*W
+constexpr int64_t kRescoreSharedQ = 512;   // up to this many queries: a workgroup per query
 
 template <int ND, int K, int C, int NORM>
 __device__ inline float cand_cost(const QueryIndexView& v, const float* __restrict__ vol,
@@ -355,17 +343,21 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
                                                       int cap, int64_t* __restrict__ best_id,
                                                       float* __restrict__ best_cost,
                                                       int64_t* __restrict__ cand,
-                                                      int32_t* __restrict__ ncand) {
+                                                      int32_t* __restrict__ ncand, int wpq) {
     // per wave: cap ids to sort (A), then the unique ones (Bu); cap is the
     // power of two >= L*W, so the launch sizes the LDS to 2 * 4 * cap words
     extern __shared__ uint32_t rescore_lds[];
+    __shared__ uint64_t wbest[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // XCD-aware: workgroup b runs on XCD b % 8; each XCD takes one
     // contiguous eighth of the queries, whose neighbouring targets share
-    // candidates, so the patches they gather stay in that XCD's L2
+    // candidates, so the patches they gather stay in that XCD's L2.
+    // wpq = 1: four queries per workgroup, one wave each; wpq = 4 (few
+    // queries): the four waves share one query (each builds the same
+    // candidate set) and split its candidates.
     const int64_t nblk = gridDim.x, per_xcd = (nblk + 7) / 8;
     const int64_t qb = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    const int64_t q = qb * 4 + w;
+    const int64_t q = wpq == 4 ? qb : qb * 4 + w;
     const bool live = q < Q;
     const int LW = v.L * v.window;
     uint32_t* A = rescore_lds + (size_t)w * cap;
@@ -407,8 +399,9 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
         nu += __popcll(bal);
     }
     __syncthreads();
-    if (!live) return;
-    if (cand) {
+    if (!live) return;   // uniform over the workgroup when wpq = 4
+    const bool lead = wpq == 1 || w == 0;
+    if (cand && lead) {
         for (int i = lane; i < LW; i += 64) cand[q * LW + i] = i < nu ? (int64_t)Bu[i] : -1;
         if (lane == 0) ncand[q] = nu;
     }
@@ -416,7 +409,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
     const float* tq = t + q * (int64_t)v.Kd * C;
     const uint32_t* rm = rowmask + q;
     uint64_t best = ~0ull;
-    for (int i = lane; i < nu; i += 64) {
+    for (int i = (wpq == 4 ? w * 64 : 0) + lane; i < nu; i += 64 * wpq) {
         const uint32_t c = Bu[i];
         const float cost = cand_cost<ND, K, C, NORM>(v, vol, tq, rm, qpad, c);
         const uint64_t pk = ((uint64_t)__float_as_uint(cost) << 32) | c;
@@ -425,6 +418,12 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
     for (int off = 32; off > 0; off >>= 1) {
         const uint64_t o = (uint64_t)__shfl_xor((long long)best, off, 64);
         if (o < best) best = o;
+    }
+    if (wpq == 4) {
+        if (lane == 0) wbest[w] = best;
+        __syncthreads();
+        if (w != 0) return;
+        for (int k = 1; k < 4; k++) best = wbest[k] < best ? wbest[k] : best;
     }
     if (lane == 0) {
         best_id[q] = best == ~0ull ? -1 : (int64_t)(best & 0xffffffffull);
@@ -804,10 +803,12 @@ __global__ void knn_cand_kernel(const uint32_t* __restrict__ list, const int32_t
 
 using RescoreFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
                            const int32_t*, const int64_t*, int64_t, int, int64_t*, float*,
-                           int64_t*, int32_t*);
+                           int64_t*, int32_t*, int);
 
 template <int D>
-PrologueFn prologue_fn() { return prologue_kernel<D, kPrologueLanes>; }
+PrologueFn prologue_fn(bool wide) {
+    return wide ? prologue_kernel<D, 64> : prologue_kernel<D, kPrologueLanes>;
+}
 
 using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
                        const uint32_t*, const int32_t*, const int32_t*, int, int64_t, int64_t*,
@@ -839,26 +840,29 @@ sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const 
                                  int64_t Q, int32_t* qsub, double* qcoords, uint64_t* qkeys,
                                  uint32_t* rowmask, int64_t qpad, hipStream_t st) {
     if (Q == 0) return SFC_OK;
+    // few queries: a whole wave per query shortens each one's serial sums
+    const bool wide = Q <= kPrologueWideQ;
+    const int G = wide ? 64 : kPrologueLanes;
     PrologueFn fn = nullptr;
     switch (v.D) {
-    case 1: fn = prologue_fn<1>(); break;
-    case 2: fn = prologue_fn<2>(); break;
-    case 3: fn = prologue_fn<3>(); break;
-    case 4: fn = prologue_fn<4>(); break;
-    case 5: fn = prologue_fn<5>(); break;
-    case 6: fn = prologue_fn<6>(); break;
-    case 7: fn = prologue_fn<7>(); break;
-    case 8: fn = prologue_fn<8>(); break;
-    case 9: fn = prologue_fn<9>(); break;
-    case 10: fn = prologue_fn<10>(); break;
-    case 11: fn = prologue_fn<11>(); break;
-    case 12: fn = prologue_fn<12>(); break;
-    case 16: fn = prologue_fn<16>(); break;
+    case 1: fn = prologue_fn<1>(wide); break;
+    case 2: fn = prologue_fn<2>(wide); break;
+    case 3: fn = prologue_fn<3>(wide); break;
+    case 4: fn = prologue_fn<4>(wide); break;
+    case 5: fn = prologue_fn<5>(wide); break;
+    case 6: fn = prologue_fn<6>(wide); break;
+    case 7: fn = prologue_fn<7>(wide); break;
+    case 8: fn = prologue_fn<8>(wide); break;
+    case 9: fn = prologue_fn<9>(wide); break;
+    case 10: fn = prologue_fn<10>(wide); break;
+    case 11: fn = prologue_fn<11>(wide); break;
+    case 12: fn = prologue_fn<12>(wide); break;
+    case 16: fn = prologue_fn<16>(wide); break;
     default: return fail(SFC_EUNSUPPORTED, "index query: reduced dimension not in {1..12, 16}");
     }
     if (v.Kd > 64 * kMaxKnownWords || v.S > kMaxSubsets)
         return fail(SFC_EUNSUPPORTED, "index query: more than 1024 pixels or 26 subsets per patch");
-    hipLaunchKernelGGL(fn, dim3(blocks_for(Q, 256 / kPrologueLanes)), dim3(256), 0, st, v, t, m, Q,
+    hipLaunchKernelGGL(fn, dim3(blocks_for(Q, 256 / G)), dim3(256), 0, st, v, t, m, Q,
                        qsub, qcoords, qkeys, rowmask, qpad);
     return launched("prologue_kernel");
 }
@@ -919,11 +923,13 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return check_hip(e, "rescore LDS attribute");
     }
+    // few queries: a workgroup per query (four waves split its candidates);
     // a multiple of 8 workgroups, so the XCD-aware query order is a bijection
-    const unsigned nblk = (blocks_for(Q, 4) + 7) / 8 * 8;
+    const int wpq = Q <= kRescoreSharedQ ? 4 : 1;
+    const unsigned nblk = (blocks_for(Q, 4 / wpq) + 7) / 8 * 8;
     hipLaunchKernelGGL(norm == 1 ? ent->fn_l1 : ent->fn, dim3(nblk), dim3(256), lds,
                        st, v, vol, t, rowmask, qpad, qsub, wstart, Q, cap, best_id, best_cost,
-                       cand, ncand);
+                       cand, ncand, wpq);
     return launched("rescore_kernel");
 }
 

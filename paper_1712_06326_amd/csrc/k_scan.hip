@@ -393,6 +393,27 @@ const ScanEntry kScanTable[] = {
     SFC_SCAN(3, 7, 1, 16, 4), SFC_SCAN(3, 7, 1, 16, 8), SFC_SCAN1(3, 7, 1, 8, 8),
 };
 
+// One shape per (ndim, K, C) for one or two queries (the fill loop asks for
+// a single target): QB = 2, so a lone query costs two query slots of work
+// instead of a whole query block. Not offered to the autotuner.
+const ScanEntry kScanSmall[] = {
+    SFC_SCAN(2, 3, 1, 2, 8), SFC_SCAN(2, 3, 2, 2, 8), SFC_SCAN(2, 3, 3, 2, 8),
+    SFC_SCAN(2, 5, 1, 2, 8), SFC_SCAN(2, 5, 2, 2, 8), SFC_SCAN(2, 5, 3, 2, 8),
+    SFC_SCAN(2, 7, 1, 2, 8), SFC_SCAN(2, 7, 2, 2, 8), SFC_SCAN(2, 7, 3, 2, 8),
+    SFC_SCAN(2, 9, 1, 2, 8), SFC_SCAN(2, 9, 2, 2, 8), SFC_SCAN(2, 9, 3, 2, 8),
+    SFC_SCAN(2, 11, 1, 2, 8), SFC_SCAN(2, 11, 3, 2, 4),
+    SFC_SCAN(2, 13, 1, 2, 8), SFC_SCAN(2, 13, 3, 2, 4),
+    SFC_SCAN(3, 3, 1, 2, 8), SFC_SCAN(3, 3, 2, 2, 8),
+    SFC_SCAN(3, 5, 1, 2, 8), SFC_SCAN(3, 5, 2, 2, 8),
+    SFC_SCAN(3, 7, 1, 2, 8),
+};
+
+const ScanEntry* scan_entry_small(int nd, int K, int C) {
+    for (const auto& e : kScanSmall)
+        if (e.nd == nd && e.K == K && e.C == C) return &e;
+    return nullptr;
+}
+
 // variant v (0 = default) of a shape, or null
 const ScanEntry* scan_entry(int nd, int K, int C, int v) {
     int k = 0;
@@ -416,9 +437,11 @@ inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 // Workgroups of a table entry resident on the whole device at once (its
 // occupancy per CU from its register use, times the CUs), cached per entry.
 int64_t resident_slots(const ScanEntry* e) {
-    constexpr int kEntries = sizeof(kScanTable) / sizeof(kScanTable[0]);
+    constexpr int kMain = sizeof(kScanTable) / sizeof(kScanTable[0]);
+    constexpr int kEntries = kMain + sizeof(kScanSmall) / sizeof(kScanSmall[0]);
     static int64_t slots[kEntries] = {0};
-    const int idx = (int)(e - kScanTable);
+    const bool small = e >= kScanSmall && e < kScanSmall + (kEntries - kMain);
+    const int idx = small ? kMain + (int)(e - kScanSmall) : (int)(e - kScanTable);
     if (slots[idx] == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -498,7 +521,8 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     if (a.norm == 1) {
         ent = scan_entry_l1(g.nd, g.K, g.C);
     } else {
-        ent = scan_entry(g.nd, g.K, g.C, a.variant);
+        ent = a.Q <= 2 ? scan_entry_small(g.nd, g.K, g.C) : nullptr;
+        if (!ent) ent = scan_entry(g.nd, g.K, g.C, a.variant);
         if (!ent) ent = scan_entry(g.nd, g.K, g.C, 0);
     }
     if (!ent)

@@ -119,3 +119,15 @@ def test_window_autotuner():
     first3 = next((x["window"] for x in trials3 if x["accel_error"] <= 0.01), trials3[-1]["window"])
     assert W3 == first3 and ix.info.window == W3
     assert trials3[-1]["window"] * 4 <= 2048 < trials3[-1]["window"] * 4 * 1.5
+
+
+@pytest.mark.parametrize("h,w,c,seed,holes,frac,curve", [(200, 260, 3, 50, 8, 0.12, "morton"),
+                                                        (180, 220, 1, 51, 10, 0.15, "hilbert")])
+def test_index_many_queries(h, w, c, seed, holes, frac, curve):
+    """More than 512 front targets: the query runs with 16 lanes per target
+    in the prologue and one wave per target in the rescoring (fewer targets
+    take a wave per target and a workgroup per target); every stage equals
+    the oracle's."""
+    d = synth.small_image(h, w, c, seed, holes=holes, frac=frac)
+    assert oracle.front(d["mask"]).size > 512
+    _check(d["volume"], d["mask"], 7, 6, 3, 12, curve, 16)

@@ -144,3 +144,23 @@ def test_scan_config2_sampled():
     assert np.array_equal(bi[sel], boi)
     assert np.array_equal(bc[sel].view(np.uint32), boc.view(np.uint32))
     say("scan config2: 256 sampled queries equal the oracle's full scan")
+
+
+@pytest.mark.parametrize("nd,K,C", [(2, 3, 1), (2, 5, 3), (2, 7, 2), (2, 9, 1), (2, 9, 3),
+                                    (2, 11, 3), (2, 13, 1), (3, 3, 2), (3, 5, 1), (3, 7, 1)])
+def test_scan_one_and_two_queries(nd, K, C):
+    """One or two targets take the scan's two-query shape (the fill loop's
+    case); answers equal the oracle's for both counts."""
+    nat = need_gpu()
+    d = synth.small_image(45, 70, C, 40 + K) if nd == 2 else synth.small_volume(17, 40 + K, c=C)
+    vol, mask = d["volume"], d["mask"]
+    vd, md = dev(vol), dev(mask)
+    f = oracle.front(mask)
+    do = oracle.dictionary(mask, K)
+    ix = nat.Index(vd, md, K)
+    for sel in ([f.size // 3], [0, f.size - 1]):
+        t, m = oracle.extract(vol, mask, K, f[sel])
+        bi, bc = ix.query(dev(t), dev(m), "fp32")
+        boi, boc = oracle.brute(vol, mask.shape, K, do, t, m)
+        assert np.array_equal(host(bi), boi)
+        assert np.array_equal(host(bc).view(np.uint32), boc.view(np.uint32))
