@@ -469,7 +469,7 @@ def main():
     if args.workload == "config2" and not args.no_inpaint:
         del res
         torch.cuda.empty_cache()
-        line["inpaint"] = inpaint_pass(torch, native, synth)
+        line["inpaint"] = inpaint_pass(torch, native, synth, ("config1", "config2", "config3"))
         res = None
     if args.workload == "config2" and not args.no_n1e8:
         del w, res

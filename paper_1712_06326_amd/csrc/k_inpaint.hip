@@ -475,10 +475,45 @@ __global__ __launch_bounds__(256) void loop_apply_kernel(float* __restrict__ vol
     }
 }
 
-// One workgroup: the level-1 and level-2 partials that the last fill's
-// region touches, the next target, and its extraction (t, m; for the
-// float32 scan also query slot 0 of the padded targets and row masks, and a
-// cleared result).
+// level-1 partials of the blocks of 256 voxels that the last fill's region
+// touches: a workgroup per (region line, block); lines that share a block
+// write the same value
+__global__ __launch_bounds__(256) void loop_part1_kernel(const Cand* __restrict__ pv, Grid g,
+                                                         int order, const LoopState* __restrict__ ls,
+                                                         Cand* __restrict__ part1) {
+    const int64_t p = ls->last;
+    if (p < 0) return;
+    int64_t id0, id1;
+    if (!region_line(g, p, blockIdx.x >> 1, &id0, &id1)) return;
+    const int64_t b = id0 / 256 + (blockIdx.x & 1);
+    if (b > id1 / 256) return;
+    const int64_t i = b * 256 + threadIdx.x;
+    const Cand x = i < g.nvox ? pv[i] : Cand{-1.0, -1.0, INT64_MAX};
+    const Cand best = block_best(x, order);
+    if (threadIdx.x == 0) part1[b] = best;
+}
+
+// level-2 partials over the level-1 blocks that changed
+__global__ __launch_bounds__(256) void loop_part2_kernel(const Cand* __restrict__ part1,
+                                                         int64_t nb1, Grid g, int order,
+                                                         const LoopState* __restrict__ ls,
+                                                         Cand* __restrict__ part2) {
+    const int64_t p = ls->last;
+    if (p < 0) return;
+    int64_t id0, id1;
+    if (!region_line(g, p, blockIdx.x >> 1, &id0, &id1)) return;
+    const int64_t b = id0 / 256 + (blockIdx.x & 1);
+    if (b > id1 / 256) return;
+    const int64_t c = b / 256;
+    const int64_t i = c * 256 + threadIdx.x;
+    const Cand x = i < nb1 ? part1[i] : Cand{-1.0, -1.0, INT64_MAX};
+    const Cand best = block_best(x, order);
+    if (threadIdx.x == 0) part2[c] = best;
+}
+
+// One workgroup: the next target from the top partial level, and its
+// extraction (t, m; for the float32 scan also query slot 0 of the padded
+// targets and row masks, and a cleared result).
 constexpr int kSelThreads = 1024;
 constexpr int64_t kOneLevel = 16384;   // level-1 entries the pick reads directly (4M voxels)
 __global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
@@ -489,43 +524,6 @@ __global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
     constexpr int NW = kSelThreads / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const Cand none{-1.0, -1.0, INT64_MAX};
-    const int64_t p = ls->last;
-    if (p >= 0) {
-        int64_t lines = 1;
-        for (int a = 0; a < g.nd - 1; a++) lines *= 2 * g.K - 1;
-        // level 1: one wave per (region line, block of 256 voxels)
-        for (int64_t u = wave; u < 2 * lines; u += NW) {
-            int64_t id0, id1;
-            if (!region_line(g, p, u >> 1, &id0, &id1)) continue;
-            const int64_t b = id0 / 256 + (u & 1);
-            if (b > id1 / 256) continue;
-            Cand x = none;
-            for (int k = lane; k < 256; k += 64) {
-                const int64_t i = b * 256 + k;
-                if (i < g.nvox && ranks_before(pv[i], x, order)) x = pv[i];
-            }
-            x = wave_best(x, order);
-            if (lane == 0) part1[b] = x;
-        }
-        __syncthreads();
-        // level 2 over the changed level-1 blocks (not needed when the pick
-        // reads level 1 directly)
-        for (int64_t u = wave; u < 2 * lines && nb1 > kOneLevel; u += NW) {
-            int64_t id0, id1;
-            if (!region_line(g, p, u >> 1, &id0, &id1)) continue;
-            const int64_t b = id0 / 256 + (u & 1);
-            if (b > id1 / 256) continue;
-            const int64_t c = b / 256;
-            Cand x = none;
-            for (int k = lane; k < 256; k += 64) {
-                const int64_t i = c * 256 + k;
-                if (i < nb1 && ranks_before(part1[i], x, order)) x = part1[i];
-            }
-            x = wave_best(x, order);
-            if (lane == 0) part2[c] = x;
-        }
-        __syncthreads();
-    }
     // the next target
     __shared__ Cand sb[NW];
     __shared__ int64_t sh_centre;
@@ -668,6 +666,17 @@ sfc_status launch_loop_select(const float* vol, const uint8_t* mask, const doubl
     region_cand_kernel<<<(unsigned)((nreg + 3) / 4), 256, 0, st>>>(vol, mask, conf, g, order, ls,
                                                                  static_cast<Cand*>(pv));
     SFC_TRY(launched("region_cand_kernel"));
+    int64_t lines = 1;
+    for (int a = 0; a < g.nd - 1; a++) lines *= 2 * g.K - 1;
+    loop_part1_kernel<<<(unsigned)(2 * lines), 256, 0, st>>>(static_cast<const Cand*>(pv), g, order,
+                                                             ls, static_cast<Cand*>(part1));
+    SFC_TRY(launched("loop_part1_kernel"));
+    if (nb1 > kOneLevel) {
+        loop_part2_kernel<<<(unsigned)(2 * lines), 256, 0, st>>>(static_cast<const Cand*>(part1), nb1,
+                                                                 g, order, ls,
+                                                                 static_cast<Cand*>(part2));
+        SFC_TRY(launched("loop_part2_kernel"));
+    }
     loop_select_kernel<<<1, kSelThreads, 0, st>>>(vol, mask, g, order, static_cast<const Cand*>(pv),
                                                   static_cast<Cand*>(part1), nb1,
                                                   static_cast<Cand*>(part2), nb2, ls, t, m, tp, rm,
