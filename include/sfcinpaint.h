@@ -130,6 +130,13 @@ void sfc_options_default(sfc_options *opt);
  * allocation failure"; n <= 0 turns this off. Not for production use. */
 void sfc_debug_fail_alloc(int64_t n);
 
+/* Overflow-path testing: the candidate list of each query of the
+ * reduced-precision scan holds `cap` entries (rounded down to a multiple of
+ * 64, at least 64) instead of the automatic 2048..16384, so that lists
+ * overflow and those queries take the float32 scan; cap <= 0 restores the
+ * automatic size. Process-wide. Not for production use. */
+void sfc_debug_list_capacity(int32_t cap);
+
 /* Fill front (Fig. 1a: known pixels adjacent to unknown ones; adjacency =
  * shared face). Writes the front's voxel ids in ascending order to
  * centres[0 .. min(count, capacity)), and the total to *count_host.
@@ -232,7 +239,9 @@ int64_t sfc_noalloc_bytes(const sfc_index *idx, int64_t Q);
  * cand (nullable) int64 [Q, k] the k ids ascending, padded with -1 when the
  * dictionary has fewer; ncand (nullable) int32 [Q]. Q = 0 is a no-op.
  * SFC_EINVAL: no SFC index, k outside 1..256, mu < 1, null targets or
- * results; SFC_EUNSUPPORTED: Hilbert curves, reduced_dim above 16. */
+ * results; SFC_EUNSUPPORTED: Hilbert curves, reduced_dim above 16, or
+ * 2*key_bits + ceil(log2(reduced_dim)) above 62 (the squared cell distances
+ * are summed in int64). */
 sfc_status sfc_query_knn(sfc_index *idx, const float *targets, const uint8_t *target_masks,
                          int64_t Q, int32_t k, int32_t mu, int64_t *best_id, float *best_cost,
                          int64_t *cand, int32_t *ncand);

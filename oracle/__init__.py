@@ -570,7 +570,8 @@ class Index:
         r = lib().orc_knn(C.byref(self.struct()), _p(volume), _p(t), _p(m), Q, k, _p(bi), _p(bc),
                           _p(cand), _p(nc))
         if r != 0:
-            raise ValueError("k-NN needs a Morton-ordered index and k >= 1")
+            raise ValueError("k-NN needs a Morton-ordered index, k >= 1 and "
+                             "2*key_bits + ceil(log2(D)) <= 62")
         return bi, bc, cand, nc
 
 

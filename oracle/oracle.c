@@ -1051,6 +1051,10 @@ int64_t orc_knn_one(const orc_index *ix, const float *vol, const float *t, const
                     int k, int64_t *best_id, float *best_cost, int64_t *cand)
 {
     if (ix->curve != 0 || k < 1) return -1;
+    /* squared cell distances summed in int64: D * (2^b)^2 below 2^62 */
+    int lg = 0;
+    while ((1 << lg) < ix->D) lg++;
+    if (2 * ix->b + lg > 62) return -1;
     grid_t g = make_grid(ix->nd, ix->shape);
     int64_t Kd = ipow(ix->K, ix->nd);
     int W64 = (ix->D * ix->b + 63) / 64;

@@ -336,6 +336,8 @@ int32_t sfc_abi_version(void) { return SFC_ABI_VERSION; }
 
 void sfc_debug_fail_alloc(int64_t n) { g_fail_in.store(n > 0 ? (long)n : 0); }
 
+void sfc_debug_list_capacity(int32_t cap) { set_list_capacity_override(cap); }
+
 const char* sfc_last_error(void) { return g_last_error.c_str(); }
 
 void sfc_options_default(sfc_options* o) {
@@ -713,6 +715,15 @@ sfc_status sfc_query_knn(sfc_index* ix, const float* targets, const uint8_t* tar
     if (mu < 1) return fail(SFC_EINVAL, "mu must be >= 1");
     if (ix->opt.curve != SFC_CURVE_MORTON)
         return fail(SFC_EUNSUPPORTED, "k-NN queries need Morton curves (litmax/bigmin)");
+    {
+        // squared cell distances are summed in int64: D * (2^b)^2 must stay
+        // below 2^62
+        int lg = 0;
+        while ((1 << lg) < ix->D) lg++;
+        if (2 * ix->b + lg > 62)
+            return fail(SFC_EUNSUPPORTED,
+                        "k-NN queries need 2*key_bits + ceil(log2(reduced_dim)) <= 62");
+    }
     if (Q == 0) return SFC_OK;
     if (!targets || !target_masks || !best_id || !best_cost)
         return fail(SFC_EINVAL, "sfc_query_knn: null pointer");

@@ -146,6 +146,8 @@ sfc_status scan_fp32_prepared(sfc_index* ix, int64_t Q, const uint32_t* rm, cons
                               uint64_t* best);
 sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                                sfc_mode mode, int64_t* best_id, float* best_cost);
+// forces the reduced-precision scan's list capacity (<= 0: automatic)
+void set_list_capacity_override(int32_t cap);
 sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                        int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
 // The index query on a caller buffer of index_query_bytes(ix, Q) bytes

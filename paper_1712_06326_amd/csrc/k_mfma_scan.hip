@@ -281,10 +281,18 @@ __global__ __launch_bounds__(256, 2) void filter_kernel(FilterArgs a) {
         const bool more = nt < a.ntiles;
         if (MODE != 1) {
             // this tile's query thresholds (read after the next barrier); a
-            // query whose list already overflowed (the float32 scan will
-            // answer it) takes no more hits
+            // query whose list is full takes no more hits: its count is
+            // raised above the capacity first, so that the float32 scan
+            // answers it even if the count had stopped exactly at the
+            // capacity (hits dropped here would otherwise go unnoticed)
             const int64_t q = qt * BM + tid;
-            sth[tid] = (q < a.Q && a.cnt[q] < a.cap) ? a.thr[q] - a.T2[q] : (int32_t)0x80000000;
+            int32_t th = (int32_t)0x80000000;
+            if (q < a.Q) {
+                const int32_t c = a.cnt[q];
+                if (c < a.cap) th = a.thr[q] - a.T2[q];
+                else if (c == a.cap) atomicMax(&a.cnt[q], a.cap + 1);
+            }
+            sth[tid] = th;
         }
         __syncthreads();
         f32x16 acc[TI][TJ];

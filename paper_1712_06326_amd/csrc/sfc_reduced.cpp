@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "index.hpp"
@@ -35,14 +36,20 @@ __global__ void scatter_results_kernel(const uint64_t* __restrict__ best, const 
 
 constexpr double kMaxOperandBytes = 32.0 * (1ull << 30);   // bf16 dictionary operand
 
+std::atomic<int32_t> g_cap_override{0};
+
 // candidates kept per query: 2048 .. 16384, the lists within 512 MiB
 int list_capacity(int64_t Q) {
+    const int32_t forced = g_cap_override.load();
+    if (forced > 0) return std::max(64, forced & ~63);
     int64_t cap = (int64_t(512) << 20) / 4 / (Q > 0 ? Q : 1);
     cap = std::max<int64_t>(2048, std::min<int64_t>(16384, cap));
     return (int)(cap & ~int64_t(63));
 }
 
 }  // namespace
+
+void set_list_capacity_override(int32_t cap) { g_cap_override.store(cap > 0 ? cap : 0); }
 
 sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                                sfc_mode mode, int64_t* best_id, float* best_cost) {

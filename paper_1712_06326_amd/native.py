@@ -102,6 +102,7 @@ _SIG = {
                             C.POINTER(P)]),
     "sfc_sort_pairs": (ST, [P, P, I64, I32, I32, P]),
     "sfc_debug_fail_alloc": (None, [I64]),
+    "sfc_debug_list_capacity": (None, [I32]),
     "sfc_batch_create": (ST, [I32, P, P, P, I32, C.POINTER(Options), C.POINTER(P)]),
     "sfc_batch_query": (ST, [P, P, P, P, P, P]),
     "sfc_batch_autotune": (ST, [P, P, P, P, P, P, C.POINTER(C.c_int32)]),
@@ -176,6 +177,11 @@ def options(key_bits=8, window=32, curve="morton", query_block=0, scan_variant=0
 def debug_fail_alloc(n: int) -> None:
     """Makes the library's n-th device allocation from now fail (0: off)."""
     _L.sfc_debug_fail_alloc(n)
+
+
+def debug_list_capacity(cap: int) -> None:
+    """Forces the reduced-precision scan's per-query list capacity (0: automatic)."""
+    _L.sfc_debug_list_capacity(cap)
 
 
 def fill_front(mask: torch.Tensor) -> torch.Tensor:

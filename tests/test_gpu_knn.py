@@ -84,6 +84,10 @@ def test_knn_argument_errors():
         with pytest.raises(nat.SfcError):
             ix.knn(dev(t), dev(m), k=k, mu=mu)
     ix.close()
+    ix = nat.Index(vd, md, 5, reduced_dim=8, n_curves=1, key_bits=30)
+    with pytest.raises(nat.SfcError, match="62"):
+        ix.knn(dev(t), dev(m))
+    ix.close()
     ix = nat.Index(vd, md, 5)
     with pytest.raises(nat.SfcError, match="SFC index"):
         ix.knn(dev(t), dev(m))

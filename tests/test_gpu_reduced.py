@@ -112,6 +112,38 @@ def test_reduced_seeded_by_index():
     assert np.array_equal(host(bc).view(np.uint32), host(sc).view(np.uint32))
 
 
+def test_reduced_small_lists_overflow_to_the_fp32_scan():
+    """Lists of 64..256 entries overflow for many queries, while other
+    workgroups are still appending: every query whose list lost a candidate
+    must take the float32 scan (also when the count stopped exactly at the
+    capacity), so both the two-pass and the seeded filter still equal the
+    float32 scan, on every repetition."""
+    nat = need_gpu()
+    d = synth.config2()
+    vol, mask = d["volume"], d["mask"]
+    vd, md = dev(vol), dev(mask)
+    f = host(nat.fill_front(md))
+    f = np.sort(np.random.default_rng(12).choice(f, 1000, replace=False))
+    t, m = nat.extract_targets(vd, md, 9, dev(f))
+    plain = nat.Index(vd, md, 9)
+    seeded = nat.Index(vd, md, 9, reduced_dim=8, n_curves=4, key_bits=21)
+    si, sc = (host(a) for a in plain.query(t, m, "fp32"))
+    try:
+        for cap in (64, 256):
+            nat.debug_list_capacity(cap)
+            for name, ix in (("two-pass", plain), ("seeded", seeded)):
+                for rep in range(3):
+                    bi, bc = (host(a) for a in ix.query(t, m, "bf16"))
+                    fb = ix.fallbacks()
+                    say(f"  cap {cap} {name} rep {rep}: fallbacks {fb}/{f.size}")
+                    if cap == 64:
+                        assert fb > 0
+                    assert np.array_equal(bi, si)
+                    assert np.array_equal(bc.view(np.uint32), sc.view(np.uint32))
+    finally:
+        nat.debug_list_capacity(0)
+
+
 def test_reduced_constant_and_duplicates():
     """Exact duplicates everywhere (a constant image): every cost ties at 0
     and the set overflows; the fallback still returns the lowest id."""

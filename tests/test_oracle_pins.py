@@ -635,6 +635,21 @@ def test_knn_needs_a_morton_index(orc):
         ix.knn_query(vol, t, m, k=4)
 
 
+def test_knn_rejects_keys_whose_distances_could_overflow(orc):
+    # D * (2^b)^2 must stay below 2^62: D=8, b=30 gives 2^63 and is refused;
+    # D=4, b=30 gives exactly 2^62 and still ranks the dictionary exactly
+    vol, mask = _img(h=20, w=22, c=1, seed=3)
+    t, m = orc.extract(vol, mask, 5, orc.front(mask)[:3])
+    ix = orc.Index(vol, mask, 5, D=8, L=1, key_bits=30)
+    with pytest.raises(ValueError):
+        ix.knn_query(vol, t, m, k=4)
+    ix = orc.Index(vol, mask, 5, D=4, L=1, key_bits=30)
+    bi, bc, _, nc = ix.knn_query(vol, t, m, k=ix.n + 5)
+    b2, c2 = orc.brute(vol, mask.shape, 5, ix.dict, t, m)
+    assert np.all(nc == ix.n)
+    assert np.array_equal(bi, b2) and np.array_equal(bc.view(np.uint32), c2.view(np.uint32))
+
+
 def test_query_coords_full_mask_exact_and_partial_least_squares(orc):
     import ctypes
     vol, mask = _img(h=40, w=40, c=1, seed=14)
