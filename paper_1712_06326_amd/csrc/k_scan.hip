@@ -156,17 +156,9 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
                         mn = ldu(mrb + qi + 1);
                     }
                     const uint32_t mr = mc;
-                    if (mr == (1u << K) - 1u) {
-                        // element outer, candidate inner: NX independent
-                        // accumulation chains, each in element order
-#pragma unroll
-                        for (int i = 0; i < RW; i++)
-#pragma unroll
-                            for (int j = 0; j < NX; j++) {
-                                const float d = tc[i] - v[j * C + i];
-                                acc[qi][j] = accum<NORM>(acc[qi][j], d);
-                            }
-                    } else if (mr != 0) {
+                    // known pixels of the row only, each updating the NX
+                    // accumulators in place (a full row takes every branch)
+                    if (mr != 0) {
 #pragma unroll
                         for (int dx = 0; dx < K; dx++) {
                             if (mr & (1u << dx)) {
@@ -383,14 +375,14 @@ const ScanEntry kScanTable[] = {
     SFC_SCAN1(2, 7, 1, 16, 8), SFC_SCAN1(2, 7, 2, 16, 4), SFC_SCAN1(2, 7, 3, 16, 4),
     SFC_SCAN1(2, 9, 1, 16, 8), SFC_SCAN(2, 9, 1, 16, 4), SFC_SCAN(2, 9, 1, 8, 8),
     SFC_SCAN1(2, 9, 2, 16, 4),
-    SFC_SCAN(2, 9, 3, 16, 4), SFC_SCAN1(2, 9, 3, 8, 4), SFC_SCAN(2, 9, 3, 16, 2),
-    SFC_SCAN(2, 9, 3, 8, 8), SFC_SCAN(2, 9, 3, 12, 4),
+    SFC_SCAN1(2, 9, 3, 8, 4), SFC_SCAN(2, 9, 3, 8, 8), SFC_SCAN(2, 9, 3, 16, 4),
+    SFC_SCAN(2, 9, 3, 16, 2), SFC_SCAN(2, 9, 3, 12, 4),
     SFC_SCAN1(2, 11, 1, 16, 4), SFC_SCAN1(2, 11, 3, 16, 2),
     SFC_SCAN1(2, 13, 1, 16, 4), SFC_SCAN1(2, 13, 3, 8, 2),
     SFC_SCAN1(3, 3, 1, 16, 8), SFC_SCAN1(3, 3, 2, 16, 8),
-    SFC_SCAN(3, 5, 1, 16, 8), SFC_SCAN(3, 5, 1, 16, 4), SFC_SCAN1(3, 5, 1, 8, 8),
+    SFC_SCAN1(3, 5, 1, 8, 8), SFC_SCAN(3, 5, 1, 16, 8), SFC_SCAN(3, 5, 1, 16, 4),
     SFC_SCAN1(3, 5, 2, 16, 4),
-    SFC_SCAN(3, 7, 1, 16, 4), SFC_SCAN(3, 7, 1, 16, 8), SFC_SCAN1(3, 7, 1, 8, 8),
+    SFC_SCAN1(3, 7, 1, 8, 8), SFC_SCAN(3, 7, 1, 16, 4), SFC_SCAN(3, 7, 1, 16, 8),
 };
 
 // One shape per (ndim, K, C) for one or two queries (the fill loop asks for
