@@ -312,15 +312,18 @@ typedef struct {
     float ms;              /* their total duration (HIP events on the handle's stream) */
 } sfc_kernel_time;
 
-/* Kernel durations of the last sfc_query call on this handle, one entry per
- * kernel, recorded only when the handle's options.timing was 1 (else
- * *count_host = 0). The float32 scan records "scan_fp32_kernel", the bf16
- * scan "filter_kernel<list>" and "list_rescore_kernel", plus
+/* Kernel durations of the sfc_query / sfc_query_knn calls made on this
+ * handle since the times were last read, one entry per kernel (launches and
+ * total milliseconds), recorded only while the handle's options.timing is 1
+ * (else *count_host = 0); reading clears them, and at most 4096 launches
+ * are kept between reads. The float32 scan records "scan_fp32_kernel", the
+ * bf16 scan "filter_kernel<list>" and "list_rescore_kernel", plus
  * "filter_kernel<min>" on a dictionary-only handle (its first pass) and
- * "scan_fp32_kernel" for the queries it could not settle, the index query
- * "prologue_kernel", "search_kernel" and "rescore_kernel". Writes
- * min(count, capacity) entries to times_host and the number of kernels to
- * *count_host. Synchronises the handle's stream. */
+ * "scan_fp32_kernel<fallback>" for the queries it could not settle, the
+ * index query "prologue_kernel", "search_kernel" and "rescore_kernel", the
+ * k-NN query "prologue_kernel", "knn_kernel" and "list_rescore_kernel".
+ * Writes min(count, capacity) entries to times_host and the number of
+ * kernels to *count_host. Waits for the timed launches to finish. */
 sfc_status sfc_query_kernel_times(const sfc_index *idx, sfc_kernel_time *times_host,
                                   int32_t capacity, int32_t *count_host);
 

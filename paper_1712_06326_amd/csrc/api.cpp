@@ -177,7 +177,8 @@ static sfc_status check_geometry(const sfc_geometry* g, int K) {
 }
 
 sfc_status KernelTimer::begin(const char* name, hipStream_t st) {
-    if (!on) return SFC_OK;
+    open = false;
+    if (!on || used >= kMaxMarks) return SFC_OK;
     if (used == (int)marks.size()) {
         Mark mk;
         SFC_HIP(hipEventCreate(&mk.a));
@@ -190,11 +191,13 @@ sfc_status KernelTimer::begin(const char* name, hipStream_t st) {
     }
     marks[used].name = name;
     SFC_HIP(hipEventRecord(marks[used].a, st));
+    open = true;
     return SFC_OK;
 }
 
 sfc_status KernelTimer::end(hipStream_t st) {
-    if (!on) return SFC_OK;
+    if (!open) return SFC_OK;
+    open = false;
     SFC_HIP(hipEventRecord(marks[used].b, st));
     used++;
     return SFC_OK;
@@ -296,34 +299,34 @@ sfc_index::~sfc_index() {
 namespace sfc {
 
 sfc_status scan_fp32_prepared(sfc_index* ix, int64_t Q, const uint32_t* rm, const float* tp,
-                              uint64_t* best) {
+                              uint64_t* best, const char* label) {
     ScanArgs a{ix->vol, ix->valid, tp, rm, Q, best, ix->opt.query_block,
                ix->opt.scan_variant > 0 ? ix->opt.scan_variant - 1 : ix->tuned_variant,
                ix->spans, ix->n_spans, ix->opt.norm};
-    SFC_TRY(ix->timer.begin("scan_fp32_kernel", ix->st));
+    SFC_TRY(ix->timer.begin(label, ix->st));
     SFC_TRY(launch_scan_fp32(ix->g, a, ix->st));
     return ix->timer.end(ix->st);
 }
 
 sfc_status scan_fp32_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, uint32_t* rm,
-                        float* tp, uint64_t* best) {
+                        float* tp, uint64_t* best, const char* label) {
     const Grid& g = ix->g;
     const int64_t qpad = scan_qpad(Q);
     SFC_TRY(launch_pack_rowmask(m, g, Q, rm, ix->st));
     // targets padded with zero rows up to the scan's query block
     SFC_TRY(launch_pad_f32(t, (int64_t)Q * g.Kd * g.C, (int64_t)qpad * g.Kd * g.C, tp, ix->st));
     SFC_TRY(launch_fill_u64(best, Q, ~0ull, ix->st));
-    return scan_fp32_prepared(ix, Q, rm, tp, best);
+    return scan_fp32_prepared(ix, Q, rm, tp, best, label);
 }
 
 sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
-                            uint64_t* best_dev) {
+                            uint64_t* best_dev, const char* label) {
     const Grid& g = ix->g;
     const int64_t qpad = scan_qpad(Q);
     SFC_TRY(ix->rowmask.reserve((size_t)qpad * g.rows * sizeof(uint32_t), "row masks"));
     SFC_TRY(ix->tpad.reserve((size_t)qpad * g.Kd * g.C * sizeof(float), "padded targets"));
     return scan_fp32_on(ix, t, m, Q, static_cast<uint32_t*>(ix->rowmask.ptr),
-                        static_cast<float*>(ix->tpad.ptr), best_dev);
+                        static_cast<float*>(ix->tpad.ptr), best_dev, label);
 }
 
 }  // namespace sfc
@@ -947,6 +950,7 @@ sfc_status sfc_query_kernel_times(const sfc_index* ix, sfc_kernel_time* times, i
     }
     for (size_t k = 0; k < out.size() && (int32_t)k < capacity; k++) times[k] = out[k];
     *count = (int32_t)out.size();
+    tm.used = 0;   // read: the next queries start a new record
     return SFC_OK;
 }
 

@@ -36,18 +36,21 @@ struct Scratch {
 // HIP-event timing of a handle's main query kernels (options.timing = 1):
 // begin/end bracket one launch on the handle's stream; the events are pooled
 // and reused by the next query.
+// Events around the timed kernels of the queries made since the times were
+// last read (sfc_query_kernel_times clears them); at most kMaxMarks launches
+// are kept.
 struct KernelTimer {
+    static constexpr int kMaxMarks = 4096;
     struct Mark {
         const char* name = nullptr;
         hipEvent_t a = nullptr, b = nullptr;
     };
     std::vector<Mark> marks;
-    int used = 0;
+    mutable int used = 0;
     bool on = false;
-    void reset(bool enable) {
-        used = 0;
-        on = enable;
-    }
+    bool open = false;   // begin recorded, end pending
+    // timing on or off for the next query; unread marks are kept
+    void reset(bool enable) { on = enable; }
     sfc_status begin(const char* name, hipStream_t st);
     sfc_status end(hipStream_t st);
     ~KernelTimer();
@@ -133,17 +136,18 @@ sfc_status build_sfc(sfc_index* ix, const uint8_t* mask, int D, int L, const int
 void release_sfc(sfc_index* ix);
 // checksum of the byte codes of the known voxels (quantises first if needed)
 sfc_status code_checksum(sfc_index* ix, uint64_t* out_host);
+// label: the name its launch is timed under
 sfc_status query_brute_fp32(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
-                            uint64_t* best_dev);
+                            uint64_t* best_dev, const char* label = "scan_fp32_kernel");
 // The float32 scan on caller buffers: rm [scan_qpad(Q) * rows] u32 row masks,
 // tp [scan_qpad(Q) * Kd * C] padded targets, best [Q] packed results. Every
 // word of the three is written before it is read.
 sfc_status scan_fp32_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, uint32_t* rm,
-                        float* tp, uint64_t* best);
+                        float* tp, uint64_t* best, const char* label = "scan_fp32_kernel");
 // The scan alone, on row masks, padded targets and a cleared result that
 // are already in place.
 sfc_status scan_fp32_prepared(sfc_index* ix, int64_t Q, const uint32_t* rm, const float* tp,
-                              uint64_t* best);
+                              uint64_t* best, const char* label = "scan_fp32_kernel");
 sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                                sfc_mode mode, int64_t* best_id, float* best_cost);
 // forces the reduced-precision scan's list capacity (<= 0: automatic)

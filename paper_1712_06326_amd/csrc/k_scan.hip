@@ -29,6 +29,8 @@ constexpr int kScanQB = 48;   // row-mask padding: a multiple of every variant's
 // s_waitcnt with lgkmcnt(0) and the vector-memory and export counters at
 // their maxima: waits for LDS, scalar-memory and message results only
 constexpr int kWaitScalar = 0xC07F;
+// vmcnt(0) with the export and LDS/scalar counters at their maxima
+constexpr int kWaitVector = 0x0F70;
 
 typedef const __attribute__((address_space(4))) float cfloat_as4;
 typedef const __attribute__((address_space(4))) uint32_t cu32_as4;
@@ -55,6 +57,16 @@ template <int NORM>
 __device__ __forceinline__ float accum(float acc, float d) {
     if constexpr (NORM == 0) return __builtin_fmaf(d, d, acc);
     else return acc + __builtin_fabsf(d);
+}
+
+// Queries whose target rows are requested together: the largest power of
+// two dividing QB whose rows (and masks) fit 16 scalar registers, so that
+// short rows (one channel, small K) wait once per group instead of once per
+// query.
+constexpr int scan_group(int QB, int RW) {
+    int g = 1;
+    while (g * 2 <= QB && QB % (g * 2) == 0 && g * 2 * (RW + 1) <= 16) g *= 2;
+    return g;
 }
 
 template <int ND, int K, int C, int QB, int NX, int NORM = 0>
@@ -134,48 +146,67 @@ __device__ __forceinline__ void scan_range(const ScanParams& p, int64_t q0, int6
                     for (int i = 0; i < SEG; i++)
                         v[i] = (x0 + i / C < p.shape[ND - 1]) ? vp[i] : 0.0f;
                 }
+                // the row's loads are complete before any query's pixels,
+                // so the conditional pixel blocks carry no waits of their own
+                __builtin_amdgcn_s_waitcnt(kWaitVector);
                 const float* tb = p.t + (qb * ROWS + r) * RW;
                 // The query rows come through scalar loads, which return out
-                // of order, so a wait covers every one in flight. The next
-                // query's row is requested only after the current one has
-                // arrived and is consumed while that request is in flight.
+                // of order, so a wait covers every one in flight. Queries go
+                // in groups of G (G > 1 for short rows): the next group's
+                // rows are requested only after the current group's have
+                // arrived, and are consumed while that request is in flight.
                 // (Targets are padded to the query block: all in bounds.)
-                float tc[RW];
-                uint32_t mc;
+                constexpr int G = scan_group(QB, RW);
+                float tc[G][RW];
+                uint32_t mc[G];
 #pragma unroll
-                for (int i = 0; i < RW; i++) tc[i] = ldu(tb + i);
-                mc = ldu(mrb);
+                for (int k = 0; k < G; k++) {
 #pragma unroll
-                for (int qi = 0; qi < QB; qi++) {
+                    for (int i = 0; i < RW; i++) tc[k][i] = ldu(tb + k * ROWS * RW + i);
+                    mc[k] = ldu(mrb + k);
+                }
+#pragma unroll
+                for (int q0g = 0; q0g < QB; q0g += G) {
                     __builtin_amdgcn_s_waitcnt(kWaitScalar);
-                    float tn[RW];
-                    uint32_t mn = 0;
-                    if (qi + 1 < QB) {
+                    float tn[G][RW];
+                    uint32_t mn[G];
+                    if (q0g + G < QB) {
 #pragma unroll
-                        for (int i = 0; i < RW; i++) tn[i] = ldu(tb + (qi + 1) * ROWS * RW + i);
-                        mn = ldu(mrb + qi + 1);
+                        for (int k = 0; k < G; k++) {
+#pragma unroll
+                            for (int i = 0; i < RW; i++)
+                                tn[k][i] = ldu(tb + (q0g + G + k) * ROWS * RW + i);
+                            mn[k] = ldu(mrb + q0g + G + k);
+                        }
                     }
-                    const uint32_t mr = mc;
-                    // known pixels of the row only, each updating the NX
-                    // accumulators in place (a full row takes every branch)
-                    if (mr != 0) {
 #pragma unroll
-                        for (int dx = 0; dx < K; dx++) {
-                            if (mr & (1u << dx)) {
+                    for (int k = 0; k < G; k++) {
+                        const int qi = q0g + k;
+                        const uint32_t mr = mc[k];
+                        // known pixels of the row only, each updating the NX
+                        // accumulators in place (a full row takes every branch)
+                        if (mr != 0) {
 #pragma unroll
-                                for (int j = 0; j < NX; j++)
+                            for (int dx = 0; dx < K; dx++) {
+                                if (mr & (1u << dx)) {
 #pragma unroll
-                                    for (int ch = 0; ch < C; ch++) {
-                                        const float d = tc[dx * C + ch] - v[(j + dx) * C + ch];
-                                        acc[qi][j] = accum<NORM>(acc[qi][j], d);
-                                    }
+                                    for (int j = 0; j < NX; j++)
+#pragma unroll
+                                        for (int ch = 0; ch < C; ch++) {
+                                            const float d = tc[k][dx * C + ch] - v[(j + dx) * C + ch];
+                                            acc[qi][j] = accum<NORM>(acc[qi][j], d);
+                                        }
+                                }
                             }
                         }
                     }
-                    if (qi + 1 < QB) {
+                    if (q0g + G < QB) {
 #pragma unroll
-                        for (int i = 0; i < RW; i++) tc[i] = tn[i];
-                        mc = mn;
+                        for (int k = 0; k < G; k++) {
+#pragma unroll
+                            for (int i = 0; i < RW; i++) tc[k][i] = tn[k][i];
+                            mc[k] = mn[k];
+                        }
                     }
                 }
             }
@@ -223,13 +254,15 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     __shared__ uint64_t sred[(kLanes / 64) * QB];
     // XCD-aware mapping: workgroups are dispatched to the 8 XCDs round-robin,
     // so block b runs on XCD b % 8. Each XCD gets a contiguous band of tile
-    // chunks (all query splits of it), keeping its band of the volume in
-    // that XCD's L2.
+    // chunks; within it the query splits vary fastest, so the workgroups
+    // resident on an XCD at one time walk the same chunk's tiles (each with
+    // its own queries) and each patch row comes from HBM about once per XCD
+    // and then from its L2.
     const int64_t b = blockIdx.x;
     const int64_t xcd = b % kXcds, slot = b / kXcds;
-    const int64_t chunk = xcd * p.chunks_per_xcd + slot % p.chunks_per_xcd;
-    const int64_t qs = slot / p.chunks_per_xcd;
-    if (chunk >= p.n_chunks || qs >= p.q_splits) return;
+    const int64_t chunk = xcd * p.chunks_per_xcd + slot / p.q_splits;
+    const int64_t qs = slot % p.q_splits;
+    if (slot >= p.chunks_per_xcd * p.q_splits || chunk >= p.n_chunks) return;
     const int64_t q0 = qs * p.q_per_wg;
     const int64_t q1 = min(p.Q, q0 + p.q_per_wg);
     if (q0 >= q1) return;
@@ -545,18 +578,21 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
         p.spans_per_line = (p.line_len + 7) / 8;
         p.n_tiles = (a.n_spans + 8 * ent->nx - 1) / (8 * ent->nx);
     }
-    // queries per workgroup, then tiles per workgroup so that the grid holds
-    // about 16 rounds of the workgroups resident at once: with equal
-    // workgroups the last, partly filled round then costs a few percent
-    // instead of up to a third of the launch
-    int64_t qpw = a.query_block > 0 ? a.query_block : 256;
+    // queries per workgroup (one block of QB unless the caller asks for
+    // more), then tiles per workgroup so that the grid holds about 16 rounds
+    // of the workgroups resident at once (with equal workgroups the last,
+    // partly filled round costs a few percent instead of up to a third of
+    // the launch), in a multiple of 8 chunks so the XCDs' bands are equal
+    int64_t qpw = a.query_block > 0 ? a.query_block : ent->qb;
     qpw = ((qpw + ent->qb - 1) / ent->qb) * ent->qb;
     if (qpw > a.Q) qpw = ((a.Q + ent->qb - 1) / ent->qb) * ent->qb;
     p.q_per_wg = qpw;
     p.qpad = scan_qpad(a.Q);
     const int64_t qsplit = (a.Q + qpw - 1) / qpw;
     const int64_t target = 16 * resident_slots(ent);
-    int64_t tpw = (p.n_tiles * qsplit + target - 1) / target;
+    int64_t want = (target + qsplit - 1) / qsplit;              // chunks
+    want = ((want + kXcds - 1) / kXcds) * kXcds;
+    int64_t tpw = (p.n_tiles + want - 1) / want;
     tpw = ((tpw + 3) / 4) * 4;
     if (tpw < 4) tpw = 4;
     p.tiles_per_wg = tpw;

@@ -185,7 +185,7 @@ sfc_status query_brute_reduced(sfc_index* ix, const float* t, const uint8_t* m, 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) s = check_hip(e, "gather_queries_kernel");
     }
-    if (s == SFC_OK) s = query_brute_fp32(ix, t2, m2, nfb, b2);
+    if (s == SFC_OK) s = query_brute_fp32(ix, t2, m2, nfb, b2, "scan_fp32_kernel<fallback>");
     if (s == SFC_OK) {
         scatter_results_kernel<<<(unsigned)((nfb + 255) / 256), 256, 0, st>>>(b2, fidx, nfb, best_id,
                                                                             best_cost);

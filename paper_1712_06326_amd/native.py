@@ -333,7 +333,8 @@ class Index:
         return w.value, trials
 
     def kernel_times(self) -> dict:
-        """{kernel: (launches, total ms)} of the last query (timing=True)."""
+        """{kernel: (launches, total ms)} of the timed queries since the last
+        read (timing=True); reading clears them."""
         cap = 16
         arr = (KernelTime * cap)()
         n = C.c_int32()

@@ -164,3 +164,22 @@ def test_scan_one_and_two_queries(nd, K, C):
         boi, boc = oracle.brute(vol, mask.shape, K, do, t, m)
         assert np.array_equal(host(bi), boi)
         assert np.array_equal(host(bc).view(np.uint32), boc.view(np.uint32))
+
+
+def test_kernel_times_accumulate_until_read():
+    """With timing on, the handle keeps every timed launch of its queries
+    until the times are read; reading clears them."""
+    nat = need_gpu()
+    d = synth.small_image(40, 44, 3, 2)
+    vd, md = dev(d["volume"]), dev(d["mask"])
+    f = nat.fill_front(md)
+    t, m = nat.extract_targets(vd, md, 5, f)
+    ix = nat.Index(vd, md, 5, timing=True)
+    assert ix.kernel_times() == {}
+    for _ in range(3):
+        ix.query(t, m, "fp32")
+    kt = ix.kernel_times()
+    assert list(kt) == ["scan_fp32_kernel"] and kt["scan_fp32_kernel"][0] == 3
+    assert kt["scan_fp32_kernel"][1] > 0
+    assert ix.kernel_times() == {}
+    ix.close()
