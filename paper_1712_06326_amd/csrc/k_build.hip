@@ -2,6 +2,8 @@
 // exact integer patch statistics over a strided subsample of the dictionary,
 // per-subset covariance, float64 Jacobi eigendecomposition and the int8
 // basis of the first D principal components.
+#include <mutex>
+
 #include "build.hpp"
 
 namespace sfc {
@@ -300,7 +302,7 @@ constexpr int kJacMaxSweeps = 60;
 
 // state per subset: [0] sweeps done, [1] converged, [2] sweeps in this chunk
 struct JacState {
-    int32_t done, conv, nsw, pad;
+    int32_t done, conv, pad0, pad1;
     double tiny;
 };
 
@@ -441,11 +443,12 @@ __global__ __launch_bounds__(256) void jacobi_init_kernel(const double* __restri
 template <bool kSplit>
 __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
     double* __restrict__ Tall, int64_t tri_stride, const int32_t* __restrict__ msz,
-    JacState* __restrict__ state, double2* __restrict__ logall, int64_t log_stride) {
+    JacState* __restrict__ state, double2* __restrict__ logall, int64_t log_stride,
+    int32_t* __restrict__ nsw_out) {
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
     if (state[s].conv) {
-        if (tid == 0) state[s].nsw = 0;
+        if (tid == 0) nsw_out[s] = 0;
         return;
     }
     const int m = msz[s];
@@ -549,7 +552,7 @@ __global__ __launch_bounds__(kJacThreads) void jacobi_sweeps_kernel(
     for (int t = G + tid; t < total; t += kJacThreads) Tg[t] = lds[t - G];
     if (tid == 0) {
         state[s].done = done0 + sw;
-        state[s].nsw = sw;
+        nsw_out[s] = sw;
         state[s].conv = (conv || done0 + sw >= kJacMaxSweeps) ? 1 : 0;
     }
 }
@@ -561,9 +564,9 @@ constexpr int kRepStage = 4096;   // (c, s) entries staged per batch
 
 __global__ __launch_bounds__(kRepRows * 64) void jacobi_replay_kernel(
     double* __restrict__ Vall, const int32_t* __restrict__ msz, int mmax,
-    const JacState* __restrict__ state, const double2* __restrict__ logall, int64_t log_stride) {
+    const int32_t* __restrict__ nsw_in, const double2* __restrict__ logall, int64_t log_stride) {
     const int s = blockIdx.y;
-    const int nsw = state[s].nsw;
+    const int nsw = nsw_in[s];
     const int m = msz[s];
     const int row0 = blockIdx.x * kRepRows;
     if (nsw == 0 || row0 >= m) return;
@@ -725,11 +728,41 @@ sfc_status launch_cov_matrix(const uint64_t* sum, const uint64_t* gram, int64_t 
     return launched("cov_matrix_kernel");
 }
 
-size_t jacobi_scratch_bytes(int S, int mmax) {
+namespace {
+// Two rotation logs and two per-launch sweep-count arrays: the replay of
+// launch c reads buffer c % 2 while launch c + 1 writes the other one.
+struct JacScratch {
+    size_t tri, log, state, nsw;
+};
+JacScratch jacobi_layout(int S, int mmax) {
     const int64_t Mx = mmax + (mmax & 1);
-    const size_t tri = (size_t)S * ((size_t)mmax * (mmax + 1) / 2) * sizeof(double);
-    const size_t log = (size_t)S * kJacChunk * (Mx - 1) * (Mx / 2) * sizeof(double2);
-    return ((tri + 255) & ~size_t(255)) + ((log + 255) & ~size_t(255)) + (size_t)S * sizeof(JacState);
+    auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+    JacScratch L;
+    L.tri = r256((size_t)S * ((size_t)mmax * (mmax + 1) / 2) * sizeof(double));
+    L.log = r256((size_t)S * kJacChunk * (Mx - 1) * (Mx / 2) * sizeof(double2));
+    L.state = r256((size_t)S * sizeof(JacState));
+    L.nsw = r256((size_t)S * sizeof(int32_t));
+    return L;
+}
+
+// The replays run on a second stream of the library (one per device,
+// default priority), so that replaying one launch's rotations overlaps the
+// next launch's sweeps.
+std::mutex g_aux_mu;
+hipStream_t g_aux[64] = {};
+sfc_status aux_stream(hipStream_t* out) {
+    int dev = 0;
+    SFC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(SFC_EUNSUPPORTED, "device ordinal above 63");
+    if (!g_aux[dev]) SFC_HIP(hipStreamCreateWithFlags(&g_aux[dev], hipStreamNonBlocking));
+    *out = g_aux[dev];
+    return SFC_OK;
+}
+}  // namespace
+
+size_t jacobi_scratch_bytes(int S, int mmax) {
+    const JacScratch L = jacobi_layout(S, mmax);
+    return L.tri + 2 * L.log + L.state + 2 * L.nsw;
 }
 
 sfc_status launch_jacobi(double* A, double* V, void* scratch, const int32_t* m, int S, int mmax,
@@ -738,29 +771,64 @@ sfc_status launch_jacobi(double* A, double* V, void* scratch, const int32_t* m, 
     const int64_t Mx = mmax + (mmax & 1);
     const int64_t tri_stride = (int64_t)mmax * (mmax + 1) / 2;
     const int64_t log_stride = (int64_t)kJacChunk * (Mx - 1) * (Mx / 2);
-    const size_t tri = (size_t)S * tri_stride * sizeof(double);
-    const size_t log = (size_t)S * log_stride * sizeof(double2);
+    const JacScratch L = jacobi_layout(S, mmax);
     char* base = static_cast<char*>(scratch);
     double* T = reinterpret_cast<double*>(base);
-    double2* lg = reinterpret_cast<double2*>(base + ((tri + 255) & ~size_t(255)));
-    JacState* state =
-        reinterpret_cast<JacState*>(base + ((tri + 255) & ~size_t(255)) + ((log + 255) & ~size_t(255)));
+    double2* lg[2] = {reinterpret_cast<double2*>(base + L.tri),
+                      reinterpret_cast<double2*>(base + L.tri + L.log)};
+    JacState* state = reinterpret_cast<JacState*>(base + L.tri + 2 * L.log);
+    int32_t* nsw[2] = {reinterpret_cast<int32_t*>(base + L.tri + 2 * L.log + L.state),
+                       reinterpret_cast<int32_t*>(base + L.tri + 2 * L.log + L.state + L.nsw)};
     jacobi_init_kernel<<<dim3(blocks_for((int64_t)mmax * mmax), S), 256, 0, st>>>(A, V, T, m, mmax,
                                                                                  tri_stride, state);
     SFC_TRY(launched("jacobi_init_kernel"));
-    const unsigned rblocks = (unsigned)((mmax + kRepRows - 1) / kRepRows);
-    for (int c = 0; c < (kJacMaxSweeps + kJacChunk - 1) / kJacChunk; c++) {
-        if (tri_stride > kJacTriLds)
-            jacobi_sweeps_kernel<true><<<S, kJacThreads, 0, st>>>(T, tri_stride, m, state, lg,
-                                                                  log_stride);
-        else
-            jacobi_sweeps_kernel<false><<<S, kJacThreads, 0, st>>>(T, tri_stride, m, state, lg,
-                                                                   log_stride);
-        SFC_TRY(launched("jacobi_sweeps_kernel"));
-        jacobi_replay_kernel<<<dim3(rblocks, S), kRepRows * 64, 0, st>>>(V, m, mmax, state, lg,
-                                                                        log_stride);
-        SFC_TRY(launched("jacobi_replay_kernel"));
+    auto hs = [](hipError_t e, const char* what) { return e == hipSuccess ? SFC_OK : check_hip(e, what); };
+    std::lock_guard<std::mutex> lock(g_aux_mu);
+    hipStream_t aux = nullptr;
+    SFC_TRY(aux_stream(&aux));
+    // swept[b]: launch c (c % 2 == b) has written log b; replayed[b]: its
+    // replay has read log b (launch c + 2 may overwrite it)
+    hipEvent_t ev[5] = {};
+    sfc_status status = SFC_OK;
+    for (auto& e : ev) {
+        const hipError_t he = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (he != hipSuccess) status = hs(he, "hipEventCreateWithFlags");
     }
+    hipEvent_t* swept = ev;
+    hipEvent_t* replayed = ev + 2;
+    hipEvent_t ready = ev[4];
+    // the replays may start once V is initialised
+    if (status == SFC_OK) status = hs(hipEventRecord(ready, st), "hipEventRecord");
+    if (status == SFC_OK) status = hs(hipStreamWaitEvent(aux, ready, 0), "hipStreamWaitEvent");
+    const unsigned rblocks = (unsigned)((mmax + kRepRows - 1) / kRepRows);
+    const int chunks = (kJacMaxSweeps + kJacChunk - 1) / kJacChunk;
+    for (int c = 0; c < chunks && status == SFC_OK; c++) {
+        const int b = c & 1;
+        if (c >= 2) status = hs(hipStreamWaitEvent(st, replayed[b], 0), "hipStreamWaitEvent");
+        if (status != SFC_OK) break;
+        if (tri_stride > kJacTriLds)
+            jacobi_sweeps_kernel<true><<<S, kJacThreads, 0, st>>>(T, tri_stride, m, state, lg[b],
+                                                                  log_stride, nsw[b]);
+        else
+            jacobi_sweeps_kernel<false><<<S, kJacThreads, 0, st>>>(T, tri_stride, m, state, lg[b],
+                                                                   log_stride, nsw[b]);
+        status = launched("jacobi_sweeps_kernel");
+        if (status == SFC_OK) status = hs(hipEventRecord(swept[b], st), "hipEventRecord");
+        if (status == SFC_OK) status = hs(hipStreamWaitEvent(aux, swept[b], 0), "hipStreamWaitEvent");
+        if (status != SFC_OK) break;
+        jacobi_replay_kernel<<<dim3(rblocks, S), kRepRows * 64, 0, aux>>>(V, m, mmax, nsw[b], lg[b],
+                                                                         log_stride);
+        status = launched("jacobi_replay_kernel");
+        if (status == SFC_OK) status = hs(hipEventRecord(replayed[b], aux), "hipEventRecord");
+    }
+    // the caller's stream continues once the last replay is done (with an
+    // error above, after whatever was enqueued)
+    const int last = (chunks - 1) & 1;
+    if (status == SFC_OK) status = hs(hipStreamWaitEvent(st, replayed[last], 0), "hipStreamWaitEvent");
+    else (void)hipStreamSynchronize(aux);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    SFC_TRY(status);
     jacobi_finish_kernel<<<S, 256, 0, st>>>(A, T, tri_stride, m, mmax, state, sweeps);
     return launched("jacobi_finish_kernel");
 }
