@@ -22,6 +22,7 @@ struct ScanParams {
     int64_t q_per_wg;
     int64_t qpad;            // row-mask stride (queries padded to the block size)
     int64_t n_chunks, chunks_per_xcd, q_splits;
+    int64_t q_group;         // query splits walked over every chunk of a band in turn
     // null: tiles cover whole lines; else the tiles walk this list of spans
     // (8 line positions, index line * spans_per_line + x / 8) that hold a
     // dictionary centre

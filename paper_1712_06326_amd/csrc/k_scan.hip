@@ -17,6 +17,8 @@
 // Two entry kernels share the body: one image, with an XCD-aware grid; and a
 // batch of images of uneven size (each its own dictionary), a persistent grid
 // walking (image, query block, tile chunk) work items.
+#include <algorithm>
+
 #include "batch.hpp"
 
 namespace sfc {
@@ -254,15 +256,19 @@ __global__ __launch_bounds__(kLanes) void scan_fp32_kernel(ScanParams p) {
     __shared__ uint64_t sred[(kLanes / 64) * QB];
     // XCD-aware mapping: workgroups are dispatched to the 8 XCDs round-robin,
     // so block b runs on XCD b % 8. Each XCD gets a contiguous band of tile
-    // chunks; within it the query splits vary fastest, so the workgroups
-    // resident on an XCD at one time walk the same chunk's tiles (each with
-    // its own queries) and each patch row comes from HBM about once per XCD
-    // and then from its L2.
+    // chunks. Its slots walk groups of q_group query splits (targets of a
+    // group fit the XCD's L2 next to a chunk's patch rows); within a group
+    // every chunk of the band in turn, and within a chunk the group's splits
+    // fastest. So the workgroups resident on an XCD at one time walk the same
+    // chunk's tiles (each with its own queries): a patch row comes from HBM
+    // about once per group and XCD, a target once per XCD.
     const int64_t b = blockIdx.x;
     const int64_t xcd = b % kXcds, slot = b / kXcds;
-    const int64_t chunk = xcd * p.chunks_per_xcd + slot / p.q_splits;
-    const int64_t qs = slot % p.q_splits;
-    if (slot >= p.chunks_per_xcd * p.q_splits || chunk >= p.n_chunks) return;
+    const int64_t per_group = p.chunks_per_xcd * p.q_group;
+    const int64_t qg = slot / per_group, rem = slot - qg * per_group;
+    const int64_t chunk = xcd * p.chunks_per_xcd + rem / p.q_group;
+    const int64_t qs = qg * p.q_group + rem % p.q_group;
+    if (qs >= p.q_splits || chunk >= p.n_chunks) return;
     const int64_t q0 = qs * p.q_per_wg;
     const int64_t q1 = min(p.Q, q0 + p.q_per_wg);
     if (q0 >= q1) return;
@@ -600,7 +606,11 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     p.n_chunks = chunks;
     p.chunks_per_xcd = (chunks + kXcds - 1) / kXcds;
     p.q_splits = qsplit;
-    const int64_t nblocks = kXcds * p.chunks_per_xcd * qsplit;
+    // query splits per group: their targets and row masks within 2 MiB
+    const int64_t split_bytes = qpw * ((int64_t)g.Kd * g.C + g.rows) * 4;
+    p.q_group = std::max<int64_t>(1, std::min<int64_t>(qsplit, (int64_t(2) << 20) / split_bytes));
+    const int64_t groups = (qsplit + p.q_group - 1) / p.q_group;
+    const int64_t nblocks = kXcds * p.chunks_per_xcd * p.q_group * groups;
     if (nblocks > 0x7fffffffLL) return fail(SFC_EUNSUPPORTED, "float32 scan: grid too large");
     hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(kLanes), 0, st, p);
     hipError_t e = hipGetLastError();
