@@ -168,7 +168,11 @@ def main():
         ix = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], timing=True,
                           **w.opts)
         e.append(ev())
+        # the index query runs without the library's timing events (its
+        # kernels are timed separately after the steps); the scans with them
+        ix.set_timing(False)
         bi_x, bc_x = ix.query(t, m, "index")
+        ix.set_timing(True)
         e.append(ev())
         ts, ms = (t, m) if w.sel is None else (t[w.sel].contiguous(), m[w.sel].contiguous())
         bi_s, bc_s = ix.query(ts, ms, "fp32")
@@ -228,6 +232,20 @@ def main():
     ms_step = 1e3 * wall / args.steps
     ph = np.array([[a.elapsed_time(b) for a, b in zip(mk[:-1], mk[1:])] for mk in marks]).mean(0)
     kavg = {k: float(np.mean([kt[k][1] / kt[k][0] for kt in ktimes])) for k in ktimes[0]}
+    # the index query's kernels: three timed runs of the same query on a
+    # handle of the same build, after the steps
+    if cfg.get("D"):
+        fx = native.fill_front(w.mask)
+        tx, mx = native.extract_targets(w.vol, w.mask, K, fx)
+        ixt = native.Index(w.vol, w.mask, K, reduced_dim=cfg["D"], n_curves=cfg["L"], timing=True,
+                           **w.opts)
+        ixt.query(tx, mx, "index")
+        ixt.kernel_times()
+        for _ in range(3):
+            ixt.query(tx, mx, "index")
+        kavg.update({k: v[1] / v[0] for k, v in ixt.kernel_times().items()})
+        ixt.close()
+        del fx, tx, mx
     Q, n = w.Q, res["n"]
     Qs = int(res["m"].shape[0])
     m_h = res["m"].cpu().numpy()
@@ -665,12 +683,14 @@ def large_pass(torch, native, synth, ev):
     torch.cuda.synchronize()
     build_ms = e0.elapsed_time(e1)
     log(f"n~1.25e8: index built in {build_ms:.0f} ms")
+    ix.set_timing(False)   # the index query's own time, without timing events
     for _ in range(2):
         a = ev()
         bi_x, bc_x = ix.query(t, m, "index")
         b = ev()
         torch.cuda.synchronize()
     idx_ms = a.elapsed_time(b)
+    ix.set_timing(True)
     ts, ms = t[w.sel].contiguous(), m[w.sel].contiguous()
     # the float32 scan's tile shape, autotuned on the first 512 sampled targets
     shape = ix.autotune(ts[:512].contiguous(), ms[:512].contiguous())

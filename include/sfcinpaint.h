@@ -312,6 +312,11 @@ typedef struct {
     float ms;              /* their total duration (HIP events on the handle's stream) */
 } sfc_kernel_time;
 
+/* Turns the recording of kernel durations (options.timing) on (1) or off
+ * (0) for this handle's next queries; times already recorded and not yet
+ * read are kept. SFC_EINVAL: NULL handle. */
+sfc_status sfc_set_timing(sfc_index *idx, int32_t on);
+
 /* Kernel durations of the sfc_query / sfc_query_knn calls made on this
  * handle since the times were last read, one entry per kernel (launches and
  * total milliseconds), recorded only while the handle's options.timing is 1

@@ -915,6 +915,13 @@ sfc_status sfc_autotune_window(sfc_index* ix, const float* targets, const uint8_
     return SFC_OK;
 }
 
+sfc_status sfc_set_timing(sfc_index* ix, int32_t on) {
+    clear_error();
+    if (!ix) return fail(SFC_EINVAL, "index is NULL");
+    ix->opt.timing = on ? 1 : 0;
+    return SFC_OK;
+}
+
 sfc_status sfc_query_stats(const sfc_index* ix, int64_t* n_fallback) {
     clear_error();
     if (!ix || !n_fallback) return fail(SFC_EINVAL, "null pointer");

@@ -247,41 +247,60 @@ __device__ inline bool key_less(const uint64_t* K, int64_t n, int64_t pos, const
     return false;
 }
 
-// One wave per (query, curve): first position whose key is >= the query key,
-// by rounds of 64 probes splitting the interval into 65 parts (ballot gives
-// the number of probes below the key), then a final round over <= 64 entries.
+// First position whose key is >= the query key, for each (query, curve),
+// by G lanes: rounds of G probes split the interval into G + 1 parts (a
+// ballot gives the number of probes below the key), then a final round over
+// <= G entries; the window starts half a window before it, clamped. G = 64
+// is one wave per search (fewest rounds, for small batches); G = 16 puts
+// four searches in a wave, so that a large batch's searches are all resident
+// at once.
+template <int G>
 __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int32_t* __restrict__ qsub,
                                                      const uint64_t* __restrict__ qkeys, int64_t Q,
                                                      int64_t* __restrict__ wstart) {
     const int lane = threadIdx.x & 63;
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (wid >= Q * v.L) return;
-    const int64_t q = wid / v.L;
-    const int j = (int)(wid - q * v.L);
-    const int s = qsub[q];
+    const int sl = lane % G, grp = lane / G;
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;   // search index
+    const int64_t wave0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 / G);
+    if (wave0 >= Q * v.L) return;   // uniform over the wave
+    const bool live = wid < Q * v.L;
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1) << (grp * G));
+    int64_t q = 0;
+    int j = 0;
+    if (live) {
+        q = wid / v.L;
+        j = (int)(wid - q * v.L);
+    }
+    const int s = live ? qsub[q] : 0;
     const uint64_t* K = v.keys + ((int64_t)s * v.L + j) * v.W64 * v.n;
     uint64_t qk[kMaxKeyWords];
-    for (int w = 0; w < v.W64; w++) qk[w] = qkeys[(q * v.L + j) * v.W64 + w];
-    int64_t a = 0, z = v.n;
-    while (z - a > 64) {
+    for (int w = 0; w < v.W64; w++) qk[w] = live ? qkeys[(q * v.L + j) * v.W64 + w] : 0;
+    int64_t a = 0, z = live ? v.n : 0;
+    // every group takes part in every ballot; a finished group probes nothing
+    bool more = __ballot(z - a > G) != 0;
+    while (more) {
         const int64_t len = z - a;
-        const int64_t pos = a + ((int64_t)(lane + 1) * len) / 65;
-        const bool less = key_less(K, v.n, pos, qk, v.W64);
-        const int cnt = __popcll(__ballot(less));
-        const int64_t na = cnt > 0 ? a + ((int64_t)cnt * len) / 65 + 1 : a;
-        const int64_t nz = cnt < 64 ? a + ((int64_t)(cnt + 1) * len) / 65 : z;
-        a = na;
-        z = nz;
+        const bool act = len > G;
+        const int64_t pos = a + ((int64_t)(sl + 1) * len) / (G + 1);
+        const bool less = act && key_less(K, v.n, pos, qk, v.W64);
+        const int cnt = __popcll(__ballot(less) & gmask);
+        if (act) {
+            const int64_t na = cnt > 0 ? a + ((int64_t)cnt * len) / (G + 1) + 1 : a;
+            const int64_t nz = cnt < G ? a + ((int64_t)(cnt + 1) * len) / (G + 1) : z;
+            a = na;
+            z = nz;
+        }
+        more = __ballot(z - a > G) != 0;
     }
     const int64_t len = z - a;
-    const bool less = lane < len && key_less(K, v.n, a + lane, qk, v.W64);
-    const int64_t p = a + __popcll(__ballot(less));
+    const bool less = live && sl < len && key_less(K, v.n, a + sl, qk, v.W64);
+    const int64_t p = a + __popcll(__ballot(less) & gmask);
     int64_t lo = p - v.window / 2;
     int64_t lmax = v.n - v.window;
     if (lmax < 0) lmax = 0;
     if (lo > lmax) lo = lmax;
     if (lo < 0) lo = 0;
-    if (lane == 0) wstart[wid] = lo;
+    if (live && sl == 0) wstart[wid] = lo;
 }
 
 // ------------------------------------------------------------ rescore
@@ -872,7 +891,11 @@ sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const 
 sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub, const uint64_t* qkeys,
                                int64_t Q, int64_t* wstart, hipStream_t st) {
     if (Q == 0) return SFC_OK;
-    search_kernel<<<blocks_for(Q * v.L * 64), 256, 0, st>>>(v, qsub, qkeys, Q, wstart);
+    // up to a few thousand searches: one wave each; beyond, four per wave
+    if (Q * v.L <= 4096)
+        search_kernel<64><<<blocks_for(Q * v.L * 64), 256, 0, st>>>(v, qsub, qkeys, Q, wstart);
+    else
+        search_kernel<16><<<blocks_for(Q * v.L * 16), 256, 0, st>>>(v, qsub, qkeys, Q, wstart);
     return launched("search_kernel");
 }
 

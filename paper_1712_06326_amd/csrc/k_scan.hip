@@ -606,10 +606,12 @@ sfc_status launch_scan_fp32(const Grid& g, const ScanArgs& a, hipStream_t st) {
     p.n_chunks = chunks;
     p.chunks_per_xcd = (chunks + kXcds - 1) / kXcds;
     p.q_splits = qsplit;
-    // query splits per group: their targets and row masks within 2 MiB
+    // query splits per group: their targets and row masks within 2 MiB,
+    // the groups as equal as the split count allows
     const int64_t split_bytes = qpw * ((int64_t)g.Kd * g.C + g.rows) * 4;
-    p.q_group = std::max<int64_t>(1, std::min<int64_t>(qsplit, (int64_t(2) << 20) / split_bytes));
-    const int64_t groups = (qsplit + p.q_group - 1) / p.q_group;
+    const int64_t most = std::max<int64_t>(1, std::min<int64_t>(qsplit, (int64_t(2) << 20) / split_bytes));
+    const int64_t groups = (qsplit + most - 1) / most;
+    p.q_group = (qsplit + groups - 1) / groups;
     const int64_t nblocks = kXcds * p.chunks_per_xcd * p.q_group * groups;
     if (nblocks > 0x7fffffffLL) return fail(SFC_EUNSUPPORTED, "float32 scan: grid too large");
     hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(kLanes), 0, st, p);

@@ -85,6 +85,7 @@ _SIG = {
     "sfc_query_coords": (ST, [P, P, P, I64, P, P]),
     "sfc_query_stats": (ST, [P, C.POINTER(C.c_int64)]),
     "sfc_query_kernel_times": (ST, [P, P, I32, C.POINTER(C.c_int32)]),
+    "sfc_set_timing": (ST, [P, I32]),
     "sfc_query_filter_tiles": (ST, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "sfc_autotune_window": (ST, [P, P, P, I64, C.c_float, C.c_float, P, I32,
                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -331,6 +332,10 @@ class Index:
                    "accel_error": arr[i].accel_error, "ms": arr[i].ms}
                   for i in range(min(n.value, cap))]
         return w.value, trials
+
+    def set_timing(self, on: bool) -> None:
+        """Records kernel durations of the next queries (or stops)."""
+        _check(_L.sfc_set_timing(self._h, 1 if on else 0))
 
     def kernel_times(self) -> dict:
         """{kernel: (launches, total ms)} of the timed queries since the last

@@ -182,4 +182,10 @@ def test_kernel_times_accumulate_until_read():
     assert list(kt) == ["scan_fp32_kernel"] and kt["scan_fp32_kernel"][0] == 3
     assert kt["scan_fp32_kernel"][1] > 0
     assert ix.kernel_times() == {}
+    ix.set_timing(False)
+    ix.query(t, m, "fp32")
+    assert ix.kernel_times() == {}
+    ix.set_timing(True)
+    ix.query(t, m, "fp32")
+    assert ix.kernel_times()["scan_fp32_kernel"][0] == 1
     ix.close()
