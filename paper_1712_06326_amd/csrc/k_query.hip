@@ -307,45 +307,68 @@ __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int
 constexpr int kCap = 2048;   // maximum L*W
 constexpr int64_t kRescoreSharedQ = 512;   // up to this many queries: a workgroup per query
 
-template <int ND, int K, int C, int NORM>
+// Rows of a patch whose loads a lone query's cost requests together: about
+// 84 floats of them.
+constexpr int cost_row_group(int ND, int K, int C) {
+    const int rows = ND == 2 ? K : K * K, g = 84 / (K * C);
+    return g < 1 ? 1 : (g > rows ? rows : g);
+}
+
+template <int ND, int K, int C, int NORM, int RB = 1>
 __device__ inline float cand_cost(const QueryIndexView& v, const float* __restrict__ vol,
                                   const float* __restrict__ tq, const uint32_t* __restrict__ rm,
                                   int64_t qpad, uint32_t c) {
     constexpr int H = (K - 1) / 2;
     constexpr int ROWS = (ND == 2) ? K : K * K;
     constexpr int RW = K * C;
+    // RB rows are requested together (all their loads before the first
+    // sum): a lone query then waits for ROWS / RB memory round trips
+    // instead of ROWS, at the price of RB rows of registers
     float acc = 0.0f;
-    for (int r = 0; r < ROWS; r++) {
-        const uint32_t mr = ldu(rm + (int64_t)r * qpad);
-        if (mr == 0) continue;
-        int64_t roff;
-        if (ND == 2) roff = (int64_t)(r - H) * v.stride[0] - H;
-        else roff = (int64_t)(r / K - H) * v.stride[0] + (int64_t)(r % K - H) * v.stride[1] - H;
-        const float* vp = vol + ((int64_t)c + roff) * C;
-        float vv[RW];
-        // the row's K*C floats by 16-byte loads at 4-byte alignment (global
-        // loads of this width need only dword alignment)
-        const f4u* vp4 = reinterpret_cast<const f4u*>(vp);
+    for (int r0 = 0; r0 < ROWS; r0 += RB) {
+        uint32_t mrs[RB];
+        float vv[RB][RW];
 #pragma unroll
-        for (int i = 0; i < RW / 4; i++) {
-            const f4u x = vp4[i];
-            vv[4 * i] = x.x;
-            vv[4 * i + 1] = x.y;
-            vv[4 * i + 2] = x.z;
-            vv[4 * i + 3] = x.w;
+        for (int k = 0; k < RB; k++) mrs[k] = (r0 + k < ROWS) ? ldu(rm + (int64_t)(r0 + k) * qpad) : 0u;
+        // the group's rows that hold a known pixel, K*C floats each by
+        // 16-byte loads at 4-byte alignment (global loads of this width
+        // need only dword alignment)
+#pragma unroll
+        for (int k = 0; k < RB; k++) {
+            const int r = r0 + k;
+            if (mrs[k] == 0) continue;
+            int64_t roff;
+            if (ND == 2) roff = (int64_t)(r - H) * v.stride[0] - H;
+            else roff = (int64_t)(r / K - H) * v.stride[0] + (int64_t)(r % K - H) * v.stride[1] - H;
+            const float* vp = vol + ((int64_t)c + roff) * C;
+            const f4u* vp4 = reinterpret_cast<const f4u*>(vp);
+#pragma unroll
+            for (int i = 0; i < RW / 4; i++) {
+                const f4u x = vp4[i];
+                vv[k][4 * i] = x.x;
+                vv[k][4 * i + 1] = x.y;
+                vv[k][4 * i + 2] = x.z;
+                vv[k][4 * i + 3] = x.w;
+            }
+#pragma unroll
+            for (int i = (RW / 4) * 4; i < RW; i++) vv[k][i] = vp[i];
         }
+        // then the costs, rows ascending, pixels and channels ascending
 #pragma unroll
-        for (int i = (RW / 4) * 4; i < RW; i++) vv[i] = vp[i];
-        const float* tp = tq + (int64_t)r * RW;
+        for (int k = 0; k < RB; k++) {
+            const uint32_t mr = mrs[k];
+            if (mr == 0) continue;
+            const float* tp = tq + (int64_t)(r0 + k) * RW;
 #pragma unroll
-        for (int dx = 0; dx < K; dx++) {
-            if (mr & (1u << dx)) {
+            for (int dx = 0; dx < K; dx++) {
+                if (mr & (1u << dx)) {
 #pragma unroll
-                for (int ch = 0; ch < C; ch++) {
-                    const float d = ldu(tp + dx * C + ch) - vv[dx * C + ch];
-                    // d*d fused (L2) or |d| added (L1, Section III.K)
-                    if (NORM == 0) acc = __builtin_fmaf(d, d, acc);
-                    else acc = acc + __builtin_fabsf(d);
+                    for (int ch = 0; ch < C; ch++) {
+                        const float d = ldu(tp + dx * C + ch) - vv[k][dx * C + ch];
+                        // d*d fused (L2) or |d| added (L1, Section III.K)
+                        if (NORM == 0) acc = __builtin_fmaf(d, d, acc);
+                        else acc = acc + __builtin_fabsf(d);
+                    }
                 }
             }
         }
@@ -355,7 +378,7 @@ __device__ inline float cand_cost(const QueryIndexView& v, const float* __restri
 
 // One wave per query: gather the window ids, sort them in LDS (bitonic),
 // keep the unique ones, then each lane rescores every 64th candidate.
-template <int ND, int K, int C, int NORM>
+template <int ND, int K, int C, int NORM, int RB = 1>
 __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const float* __restrict__ vol,
                                                       const float* __restrict__ t,
                                                       const uint32_t* __restrict__ rowmask,
@@ -381,9 +404,65 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
     const int64_t q = wpq == 4 ? qb : qb * 4 + w;
     const bool live = q < Q;
     const int LW = v.L * v.window;
+    const int s = live ? qsub[q] : 0;
+    if (!cand) {
+        // Best answer only: the windows' ids go into a hash set in LDS (2 cap
+        // slots per query, linear probing by compare-and-swap) and the thread
+        // that inserts an id rescores it, so every distinct candidate is
+        // costed once, after a single barrier. The (cost, id) minimum does
+        // not depend on who costs what.
+        const int T = 2 * cap;   // a power of two, at least 2 L W
+        uint32_t* tab = rescore_lds + (size_t)(wpq == 4 ? 0 : w) * T;
+        const int gsz = 64 * wpq, gid = wpq == 4 ? (int)threadIdx.x : lane;
+        for (int i = gid; i < T; i += gsz) tab[i] = 0xffffffffu;
+        __syncthreads();
+        uint64_t best = ~0ull;
+        if (live) {
+            const float* tq = t + q * (int64_t)v.Kd * C;
+            const uint32_t* rm = rowmask + q;
+            const int shift = 32 - __builtin_ctz((unsigned)T);
+            for (int i = gid; i < LW; i += gsz) {
+                const int j = i / v.window, k = i - j * v.window;
+                const int64_t pos = wstart[q * v.L + j] + k;
+                if (pos >= v.n) continue;
+                const uint32_t id = v.ids[((int64_t)s * v.L + j) * v.n + pos];
+                uint32_t h = (id * 0x9E3779B1u) >> shift;
+                bool mine = false;
+                while (true) {   // ends: at most LW of the T >= 2 LW slots are taken
+                    const uint32_t old = atomicCAS(&tab[h], 0xffffffffu, id);
+                    if (old == 0xffffffffu) {
+                        mine = true;
+                        break;
+                    }
+                    if (old == id) break;
+                    h = (h + 1) & (uint32_t)(T - 1);
+                }
+                if (mine) {
+                    const float cost = cand_cost<ND, K, C, NORM, RB>(v, vol, tq, rm, qpad, id);
+                    const uint64_t pk = ((uint64_t)__float_as_uint(cost) << 32) | id;
+                    if (pk < best) best = pk;
+                }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = (uint64_t)__shfl_xor((long long)best, off, 64);
+            if (o < best) best = o;
+        }
+        if (wpq == 4) {
+            if (lane == 0) wbest[w] = best;
+            __syncthreads();
+            if (w != 0) return;
+            for (int k = 1; k < 4; k++) best = wbest[k] < best ? wbest[k] : best;
+        }
+        if (!live || !best_id) return;
+        if (lane == 0) {
+            best_id[q] = best == ~0ull ? -1 : (int64_t)(best & 0xffffffffull);
+            best_cost[q] = best == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(best >> 32));
+        }
+        return;
+    }
     uint32_t* A = rescore_lds + (size_t)w * cap;
     uint32_t* Bu = rescore_lds + (size_t)(4 + w) * cap;
-    const int s = live ? qsub[q] : 0;
     for (int i = lane; i < cap; i += 64) {
         uint32_t id = 0xffffffffu;
         if (live && i < LW) {
@@ -432,7 +511,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
     uint64_t best = ~0ull;
     for (int i = (wpq == 4 ? w * 64 : 0) + lane; i < nu; i += 64 * wpq) {
         const uint32_t c = Bu[i];
-        const float cost = cand_cost<ND, K, C, NORM>(v, vol, tq, rm, qpad, c);
+        const float cost = cand_cost<ND, K, C, NORM, RB>(v, vol, tq, rm, qpad, c);
         const uint64_t pk = ((uint64_t)__float_as_uint(cost) << 32) | c;
         if (pk < best) best = pk;
     }
@@ -835,13 +914,18 @@ using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32
                        const uint32_t*, const int32_t*, const int32_t*, int, int64_t, int64_t*,
                        float*, uint8_t*);
 
+// fn / fn_l1: large batches (one row of a candidate per memory round
+// trip, few registers); gfn / gfn_l1: up to kRescoreSharedQ queries (rows
+// requested in groups, for the latency of small batches)
 struct RescoreEntry {
     int nd, K, C;
-    RescoreFn fn, fn_l1;
+    RescoreFn fn, fn_l1, gfn, gfn_l1;
     ListFn lfn, lfn_l1;
 };
 #define SFC_RESCORE(ND, K, C)                                                                 \
     {ND, K, C, rescore_kernel<ND, K, C, 0>, rescore_kernel<ND, K, C, 1>,                     \
+     rescore_kernel<ND, K, C, 0, cost_row_group(ND, K, C)>,                                 \
+     rescore_kernel<ND, K, C, 1, cost_row_group(ND, K, C)>,                                 \
      list_rescore_kernel<ND, K, C, 0>, list_rescore_kernel<ND, K, C, 1>}
 const RescoreEntry kRescore[] = {
     SFC_RESCORE(2, 3, 1), SFC_RESCORE(2, 3, 2), SFC_RESCORE(2, 3, 3),
@@ -943,16 +1027,19 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
     while (cap < v.L * v.window) cap <<= 1;
     if (cap > kCap) return fail(SFC_EUNSUPPORTED, "n_curves * window above 2048");
     const size_t lds = (size_t)8 * cap * sizeof(uint32_t);
-    const void* fn = reinterpret_cast<const void*>(norm == 1 ? ent->fn_l1 : ent->fn);
+    // few queries: a workgroup per query (four waves split its candidates)
+    // and candidate rows requested in groups; a multiple of 8 workgroups, so
+    // the XCD-aware query order is a bijection
+    const bool few = Q <= kRescoreSharedQ;
+    const int wpq = few ? 4 : 1;
+    const RescoreFn kfn = few ? (norm == 1 ? ent->gfn_l1 : ent->gfn) : (norm == 1 ? ent->fn_l1 : ent->fn);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return check_hip(e, "rescore LDS attribute");
     }
-    // few queries: a workgroup per query (four waves split its candidates);
-    // a multiple of 8 workgroups, so the XCD-aware query order is a bijection
-    const int wpq = Q <= kRescoreSharedQ ? 4 : 1;
     const unsigned nblk = (blocks_for(Q, 4 / wpq) + 7) / 8 * 8;
-    hipLaunchKernelGGL(norm == 1 ? ent->fn_l1 : ent->fn, dim3(nblk), dim3(256), lds,
+    hipLaunchKernelGGL(kfn, dim3(nblk), dim3(256), lds,
                        st, v, vol, t, rowmask, qpad, qsub, wstart, Q, cap, best_id, best_cost,
                        cand, ncand, wpq);
     return launched("rescore_kernel");
