@@ -24,6 +24,39 @@ sfc_status launched(const char* what) {
     return e == hipSuccess ? SFC_OK : check_hip(e, what);
 }
 
+// Sums over a wave's 64 lanes, left in lane 63 (other lanes hold partial
+// sums): a scan within each row of 16 lanes by DPP row shifts (lanes shifted
+// in from outside the row read 0), then row_bcast:15 adds each row's total
+// to the next odd row and row_bcast:31 adds lane 31 to rows 2 and 3. All in
+// vector registers (no scalar register per value). Integer sums, so exact
+// in any order.
+__device__ inline int32_t wave_sum_i32(int32_t x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+template <int CTRL, int ROWS, bool BOUND>
+__device__ inline int64_t dpp_i64(int64_t x) {
+    const uint32_t lo =
+        __builtin_amdgcn_update_dpp(0u, (uint32_t)(uint64_t)x, CTRL, ROWS, 0xf, BOUND);
+    const uint32_t hi =
+        __builtin_amdgcn_update_dpp(0u, (uint32_t)((uint64_t)x >> 32), CTRL, ROWS, 0xf, BOUND);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline int64_t wave_sum_i64(int64_t x) {
+    x += dpp_i64<0x111, 0xf, true>(x);
+    x += dpp_i64<0x112, 0xf, true>(x);
+    x += dpp_i64<0x114, 0xf, true>(x);
+    x += dpp_i64<0x118, 0xf, true>(x);
+    x += dpp_i64<0x142, 0xa, false>(x);
+    x += dpp_i64<0x143, 0xc, false>(x);
+    return x;
+}
+
 // ------------------------------------------------------------ prologue
 // G lanes per query, 256/G queries per workgroup.
 //  1. The target's known pixels as a bit set (Kd <= 1024 bits), built with
@@ -44,7 +77,7 @@ sfc_status launched(const char* what) {
 //     exchanges in float64).
 //  5. The grid cell, then one key per shifted curve (lane j: curve j).
 constexpr int kPrologueLanes = 16;
-constexpr int64_t kPrologueWideQ = 256;   // up to this many queries: 64 lanes per query
+constexpr int64_t kPrologueWideQ = 256;   // up to this many queries: a workgroup per query
 constexpr int kMaxKnownWords = 16;   // K^nd <= 1024
 constexpr int kMaxSubsets = 26;      // 3^3 - 1
 
@@ -174,7 +207,9 @@ __global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const f
         for (int f = 0; f < D; f++) {
             const int lo = d < f ? d : f, hi = d < f ? f : d;
             const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-            a[d][f] = (double)((int64_t)Gk[k] + (d == f ? 1 : 0));
+            // |entries of W^T W and G_k| <= 128^2 * (1024 * 16) = 2^28:
+            // exact through a 32-bit conversion
+            a[d][f] = (double)(Gk[k] + (d == f ? 1 : 0));
         }
         rr[d] = (double)(v.nsub * (int64_t)A[d] - T[d]);
     }
@@ -202,7 +237,7 @@ __global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const f
         for (int e = 0; e < D; e++) {
             const int lo = d < e ? d : e, hi = d < e ? e : d;
             const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-            f = f + (double)(wtw[d * D + e] - (int64_t)Gk[k]) * z[e];
+            f = f + (double)(int32_t)(wtw[d * D + e] - (int64_t)Gk[k]) * z[e];
         }
         y[d] = (double)A[d] + f / (double)v.nsub;
     }
@@ -225,6 +260,265 @@ __global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const f
         u[d] = (uint32_t)(int64_t)uu;
     }
     for (int j = gl; j < v.L; j += G) {
+        const uint32_t sh = (uint32_t)(((int64_t)j * v.R) / (D + 1));
+#pragma unroll
+        for (int d = 0; d < D; d++) cell[d] = u[d] + sh;
+        if (v.curve == SFC_CURVE_HILBERT) hilbert_axes_to_transpose<D>(cell, D, v.b);
+        uint64_t w[kMaxKeyWords];
+        interleave_words<D>(cell, D, v.b, v.W64, w);
+        for (int k = 0; k < v.W64; k++) qkeys[(q * v.L + j) * v.W64 + k] = w[k];
+    }
+}
+
+// One query per workgroup of 256 threads, for small batches (the fill
+// loop's lone target): the steps and arithmetic of prologue_kernel, laid
+// out so that every phase issues all of its global loads before it uses
+// one. A query then waits for a few memory round trips (mask and subset
+// masks; pixel list; element values) instead of one per known word, per
+// subset and per group of G pixels. The subset is chosen by a tournament
+// over the lanes under the same total order (larger k_s/n_s first, then
+// the lower index). With qbest non-null the query's packed best and its
+// ticket counter are cleared for the split rescoring.
+template <int D>
+__global__ __launch_bounds__(256) void prologue_one_kernel(
+    QueryIndexView v, const float* __restrict__ t, const uint8_t* __restrict__ m, int64_t Q,
+    int32_t* __restrict__ qsub, double* __restrict__ qcoords, uint64_t* __restrict__ qkeys,
+    uint32_t* __restrict__ rowmask, int64_t qpad, uint64_t* __restrict__ qbest,
+    int32_t* __restrict__ qticket) {
+    constexpr int NT = D * (D + 1) / 2;
+    constexpr int NV = 3 * D + NT;   // A, T (two words each), G_k
+    __shared__ uint64_t kbits[kMaxKnownWords];
+    __shared__ int32_t kcnt[32], knp[32];
+    __shared__ int32_t red[4][NV];
+    __shared__ int64_t swtw[D * D], sws[D], slo[D];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t q = blockIdx.x;
+    if (q >= Q) return;   // uniform: the grid is Q workgroups
+    const int KW = (v.Kd + 63) >> 6;
+    const int SW = v.S * KW;
+    const uint8_t* mq = m + q * v.Kd;
+    const float* tq = t + q * (int64_t)v.Kd * v.C;
+
+    // 1. known bits (Kd <= 1024: four bytes per thread), the subsets' pixel
+    // masks (S * KW <= 416 words: two per thread) and sizes, all at once
+    uint8_t mb[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int p = tid + 256 * k;
+        mb[k] = mq[p < v.Kd ? p : 0];
+    }
+    uint64_t smw[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const int i = tid + 256 * k;
+        smw[k] = v.smask[i < SW ? i : 0];
+    }
+    const int32_t npx = v.npix[tid < v.S ? tid : 0];
+    if (tid < 32) kcnt[tid] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int p = tid + 256 * k;   // word 4k + wave, bit lane
+        const uint64_t word = __ballot(p < v.Kd && mb[k] != 0);
+        if (lane == 0 && 4 * k + wave < KW) kbits[4 * k + wave] = word;
+    }
+    if (tid < v.S) knp[tid] = npx;
+    __syncthreads();
+
+    // the rescoring's row masks: bit dx of row r = pixel r*K + dx known
+    if (rowmask) {
+        for (int r = tid; r < v.rows; r += 256) {
+            const int p0 = r * v.K;
+            const int w0 = p0 >> 6, b0 = p0 & 63;
+            uint64_t bits = kbits[w0] >> b0;
+            if (b0 + v.K > 64) bits |= kbits[w0 + 1] << (64 - b0);
+            rowmask[(int64_t)r * qpad + q] = (uint32_t)(bits & ((1ull << v.K) - 1ull));
+        }
+    }
+    // 2. known pixels of each subset (exact integer counts)
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const int i = tid + 256 * k;
+        if (i < SW) {
+            const int c = __popcll(kbits[i % KW] & smw[k]);
+            if (c) atomicAdd(&kcnt[i / KW], c);
+        }
+    }
+    __syncthreads();
+    int32_t kk = -1, nn = 1, ss = lane;   // lanes >= S lose every comparison
+    if (lane < v.S) {
+        kk = kcnt[lane];
+        nn = knp[lane];
+    }
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+        const int32_t ko = __shfl_xor(kk, off, 64), no = __shfl_xor(nn, off, 64),
+                      so = __shfl_xor(ss, off, 64);
+        const int64_t l = (int64_t)ko * nn, r = (int64_t)kk * no;
+        if (l > r || (l == r && so < ss)) {
+            kk = ko;
+            nn = no;
+            ss = so;
+        }
+    }
+    const int sb = __builtin_amdgcn_readfirstlane(ss);
+
+    // the subset's constants, loaded now and used after the sums
+    const int64_t wv = v.wtw[(int64_t)sb * D * D + (tid < D * D ? tid : 0)];
+    const int64_t wsv = v.ws[(int64_t)sb * D + (tid < D ? tid : 0)];
+    const int64_t lov = v.lo[(int64_t)sb * D + (tid < D ? tid : 0)];
+    const int64_t spv = v.span[sb];
+
+    // 3. exact sums over the subset's known elements; element j is pixel
+    // j / C of the subset, channel j % C, and row j of its basis
+    int32_t A[D], Gk[NT];
+    int64_t T[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        A[d] = 0;
+        T[d] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < NT; i++) Gk[i] = 0;
+    const float vmin = v.qparams[0], sc = v.qparams[1];
+    const int8_t* wb = v.basis + (int64_t)sb * v.mmax * D;
+    const int32_t* pixs = v.pix + (int64_t)sb * v.Kd;
+    const int C = v.C;
+    const int ne = knp[sb] * C;
+    for (int base = 0; base < ne; base += 512) {
+        int rho[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int j = base + tid + 256 * u;
+            rho[u] = pixs[(j < ne ? j : 0) / C];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int j = base + tid + 256 * u;
+            const bool ok = j < ne && ((kbits[rho[u] >> 6] >> (rho[u] & 63)) & 1ull);
+            const int jc = ok ? j : 0;
+            const int e = (ok ? rho[u] : 0) * C + jc % C;
+            float rr = __builtin_rintf((tq[e] - vmin) * sc);
+            if (!(rr >= 0.0f)) rr = 0.0f;
+            if (rr > 255.0f) rr = 255.0f;
+            const int32_t x = (int32_t)rr;
+            const int64_t se = (int64_t)v.sum[e];
+            const int8_t* wr = wb + (int64_t)jc * D;
+            int32_t w[D];
+#pragma unroll
+            for (int d = 0; d < D; d++) w[d] = ok ? (int32_t)wr[d] : 0;
+            int k = 0;
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+                A[d] += w[d] * x;
+                T[d] += (int64_t)w[d] * se;
+#pragma unroll
+                for (int f = d; f < D; f++) Gk[k++] += w[d] * w[f];
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        A[d] = wave_sum_i32(A[d]);
+        T[d] = wave_sum_i64(T[d]);
+    }
+#pragma unroll
+    for (int i = 0; i < NT; i++) Gk[i] = wave_sum_i32(Gk[i]);
+    if (lane == 63) {   // the wave's totals
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            red[wave][d] = A[d];
+            red[wave][D + 2 * d] = (int32_t)(uint32_t)(uint64_t)T[d];
+            red[wave][D + 2 * d + 1] = (int32_t)(uint32_t)((uint64_t)T[d] >> 32);
+        }
+#pragma unroll
+        for (int i = 0; i < NT; i++) red[wave][3 * D + i] = Gk[i];
+    }
+    if (tid < D * D) swtw[tid] = wv;
+    if (tid < D) {
+        sws[tid] = wsv;
+        slo[tid] = lov;
+    }
+    __syncthreads();
+    // waves without a curve to key have nothing left to do
+    if (wave > 0 && wave * 64 >= v.L) return;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        A[d] = red[0][d] + red[1][d] + red[2][d] + red[3][d];
+        uint64_t tt = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            tt += (uint64_t)(uint32_t)red[k][D + 2 * d] |
+                  ((uint64_t)(uint32_t)red[k][D + 2 * d + 1] << 32);
+        T[d] = (int64_t)tt;
+    }
+#pragma unroll
+    for (int i = 0; i < NT; i++)
+        Gk[i] = red[0][3 * D + i] + red[1][3 * D + i] + red[2][3 * D + i] + red[3][3 * D + i];
+
+    // 4. imputation in float64, the oracle's order
+    double a[D][D], rr[D], z[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+#pragma unroll
+        for (int f = 0; f < D; f++) {
+            const int lo = d < f ? d : f, hi = d < f ? f : d;
+            const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+            // |entries of W^T W and G_k| <= 128^2 * (1024 * 16) = 2^28:
+            // exact through a 32-bit conversion
+            a[d][f] = (double)(Gk[k] + (d == f ? 1 : 0));
+        }
+        rr[d] = (double)(v.nsub * (int64_t)A[d] - T[d]);
+    }
+#pragma unroll
+    for (int k = 0; k < D; k++)
+#pragma unroll
+        for (int i = k + 1; i < D; i++) {
+            const double fct = a[i][k] / a[k][k];
+#pragma unroll
+            for (int j = k + 1; j < D; j++) a[i][j] = a[i][j] - fct * a[k][j];
+            rr[i] = rr[i] - fct * rr[k];
+        }
+#pragma unroll
+    for (int i = D - 1; i >= 0; i--) {
+        double s = rr[i];
+#pragma unroll
+        for (int j = i + 1; j < D; j++) s = s - a[i][j] * z[j];
+        z[i] = s / a[i][i];
+    }
+    double y[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        double f = (double)(sws[d] - T[d]);
+#pragma unroll
+        for (int e = 0; e < D; e++) {
+            const int lo = d < e ? d : e, hi = d < e ? e : d;
+            const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+            f = f + (double)(int32_t)(swtw[d * D + e] - (int64_t)Gk[k]) * z[e];
+        }
+        y[d] = (double)A[d] + f / (double)v.nsub;
+    }
+    if (tid == 0) {
+        qsub[q] = sb;
+#pragma unroll
+        for (int d = 0; d < D; d++) qcoords[q * D + d] = y[d];
+        if (qbest) {
+            qbest[q] = ~0ull;
+            qticket[q] = 0;
+        }
+    }
+
+    // 5. grid cell and one key per shifted curve
+    const double span = (double)spv;
+    const double rm1 = (double)(v.R - 1);
+    uint32_t u[D], cell[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        double uu = floor(((y[d] - (double)slo[d]) * rm1) / span);
+        if (!(uu >= 0.0)) uu = 0.0;
+        if (uu > rm1) uu = rm1;
+        u[d] = (uint32_t)(int64_t)uu;
+    }
+    for (int j = tid; j < v.L; j += 256) {
         const uint32_t sh = (uint32_t)(((int64_t)j * v.R) / (D + 1));
 #pragma unroll
         for (int d = 0; d < D; d++) cell[d] = u[d] + sh;
@@ -306,6 +600,9 @@ __global__ __launch_bounds__(256) void search_kernel(QueryIndexView v, const int
 // ------------------------------------------------------------ rescore
 constexpr int kCap = 2048;   // maximum L*W
 constexpr int64_t kRescoreSharedQ = 512;   // up to this many queries: a workgroup per query
+constexpr int64_t kRescoreSplitQ = 32;     // up to this many: several workgroups per query
+constexpr int64_t kSplitShareBytes = 16384;   // patch bytes per workgroup of the split
+static_assert(kRescoreSplitQ <= kPrologueWideQ, "the one-query prologue clears the split's words");
 
 // Rows of a patch whose loads a lone query's cost requests together: about
 // 84 floats of them.
@@ -529,6 +826,159 @@ __global__ __launch_bounds__(256) void rescore_kernel(QueryIndexView v, const fl
         best_id[q] = best == ~0ull ? -1 : (int64_t)(best & 0xffffffffull);
         best_cost[q] = best == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(best >> 32));
     }
+}
+
+// Rows of a candidate requested together by the split rescoring, where a
+// thread costs a single candidate and a query has few workgroups, so
+// occupancy does not matter: up to 248 floats (a whole 9x9x3 or 5x5x5x2
+// patch; the 7x7x7 one in two groups), as many as the registers hold
+// without spilling, balanced over the groups.
+constexpr int split_row_group(int ND, int K, int C) {
+    const int rows = ND == 2 ? K : K * K;
+    int g = 248 / (K * C);
+    g = g < 1 ? 1 : (g > rows ? rows : g);
+    const int groups = (rows + g - 1) / g;
+    return (rows + groups - 1) / groups;
+}
+
+// The masked cost of candidate c against a target (st: K^nd * C floats) and
+// row masks (srm) staged in LDS, for the split rescoring: every row of the
+// patch is requested at once (RB rows at a time; all lie inside the volume)
+// and the terms are added in cand_cost's order (rows ascending, pixels and
+// channels ascending), an unknown pixel's difference masked to +0, which
+// leaves the sum unchanged.
+template <int ND, int K, int C, int NORM, int RB>
+__device__ inline float staged_cost(const QueryIndexView& v, const float* __restrict__ vol,
+                                    const float* st, const uint32_t* srm, uint32_t c) {
+    constexpr int H = (K - 1) / 2;
+    constexpr int ROWS = (ND == 2) ? K : K * K;
+    constexpr int RW = K * C;
+    float acc = 0.0f;
+    for (int r0 = 0; r0 < ROWS; r0 += RB) {
+        float vv[RB][RW];
+#pragma unroll
+        for (int k = 0; k < RB; k++) {
+            const int r = r0 + k;
+            if (r >= ROWS) continue;
+            int64_t roff;
+            if (ND == 2) roff = (int64_t)(r - H) * v.stride[0] - H;
+            else roff = (int64_t)(r / K - H) * v.stride[0] + (int64_t)(r % K - H) * v.stride[1] - H;
+            const float* vp = vol + ((int64_t)c + roff) * C;
+            const f4u* vp4 = reinterpret_cast<const f4u*>(vp);
+#pragma unroll
+            for (int i = 0; i < RW / 4; i++) {
+                const f4u x = vp4[i];
+                vv[k][4 * i] = x.x;
+                vv[k][4 * i + 1] = x.y;
+                vv[k][4 * i + 2] = x.z;
+                vv[k][4 * i + 3] = x.w;
+            }
+#pragma unroll
+            for (int i = (RW / 4) * 4; i < RW; i++) vv[k][i] = vp[i];
+        }
+#pragma unroll
+        for (int k = 0; k < RB; k++) {
+            const int r = r0 + k;
+            if (r >= ROWS) continue;
+            // the row mask stays in a vector register (the empty asm hides
+            // that it is uniform): selects on scalar lane masks would be
+            // computed for every pixel up front and spilled
+            uint32_t mr = srm[r];
+            asm volatile("" : "+v"(mr));
+            const float* tp = st + r * RW;
+#pragma unroll
+            for (int dx = 0; dx < K; dx++) {
+                // all ones for a known pixel, zero otherwise: the difference
+                // ANDed with it is itself or +0 (NaN included)
+                const uint32_t keep = (uint32_t)__builtin_amdgcn_sbfe((int32_t)mr, dx, 1);
+#pragma unroll
+                for (int ch = 0; ch < C; ch++) {
+                    const float dd = tp[dx * C + ch] - vv[k][dx * C + ch];
+                    const float d = __uint_as_float(__float_as_uint(dd) & keep);
+                    if (NORM == 0) acc = __builtin_fmaf(d, d, acc);
+                    else acc = acc + __builtin_fabsf(d);
+                }
+            }
+        }
+    }
+    return acc;
+}
+
+// A handful of queries (the fill loop's lone target, best answer only):
+// a query's L*W window entries are split into shares of E <= 64, one
+// single-wave workgroup each, so that a lane costs at most one candidate and
+// one query's patch gathers spread over many compute units (a single CU's
+// path to L2 would otherwise carry all of them). The workgroup stages the
+// target and its row masks in LDS, removes the duplicates of its share (LDS
+// hash set), costs them (staged_cost), and merges the least (cost, id) into the
+// query's packed minimum in global memory (64-bit atomic minimum); the last
+// of the query's workgroups to finish, by a ticket counter, writes the
+// answer. The packed minimum and the ticket are set to all-ones and zero by
+// the prologue. A candidate in two shares is costed twice with the same
+// result, so the minimum over the union is unchanged.
+template <int ND, int K, int C, int NORM>
+__global__ __launch_bounds__(64) void rescore_split_kernel(
+    QueryIndexView v, const float* __restrict__ vol, const float* __restrict__ t,
+    const uint32_t* __restrict__ rowmask, int64_t qpad, const int32_t* __restrict__ qsub,
+    const int64_t* __restrict__ wstart, int64_t Q, int P, int E, uint64_t* __restrict__ qbest,
+    int32_t* __restrict__ qticket, int64_t* __restrict__ best_id, float* __restrict__ best_cost) {
+    constexpr int ROWS = (ND == 2) ? K : K * K;
+    constexpr int NEL = ROWS * K * C;
+    constexpr int RB = split_row_group(ND, K, C);
+    constexpr int T = 128;   // hash slots: twice the largest share
+    __shared__ uint32_t tab[T];
+    __shared__ float st[NEL];
+    __shared__ uint32_t srm[ROWS];
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x / P;
+    const int part = (int)(blockIdx.x - q * P);
+    if (q >= Q) return;   // uniform: the grid is Q * P workgroups
+    const float* tq = t + q * (int64_t)NEL;
+    for (int i = lane; i < NEL; i += 64) st[i] = tq[i];
+    for (int r = lane; r < ROWS; r += 64) srm[r] = rowmask[(int64_t)r * qpad + q];
+    tab[lane] = 0xffffffffu;
+    tab[lane + 64] = 0xffffffffu;
+    const int LW = v.L * v.window;
+    const int i = part * E + lane;
+    uint32_t id = 0xffffffffu;
+    if (lane < E && i < LW) {
+        const int s = qsub[q];
+        const int j = i / v.window, k = i - j * v.window;
+        const int64_t pos = wstart[q * v.L + j] + k;
+        if (pos < v.n) id = v.ids[((int64_t)s * v.L + j) * v.n + pos];
+    }
+    __syncthreads();
+    uint64_t best = ~0ull;
+    if (id != 0xffffffffu) {
+        uint32_t h = (id * 0x9E3779B1u) >> (32 - 7);
+        bool mine = false;
+        while (true) {   // ends: at most 64 of the 128 slots are taken
+            const uint32_t old = atomicCAS(&tab[h], 0xffffffffu, id);
+            if (old == 0xffffffffu) {
+                mine = true;
+                break;
+            }
+            if (old == id) break;
+            h = (h + 1) & (uint32_t)(T - 1);
+        }
+        if (mine) {
+            const float cost = staged_cost<ND, K, C, NORM, RB>(v, vol, st, srm, id);
+            best = ((uint64_t)__float_as_uint(cost) << 32) | id;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = (uint64_t)__shfl_xor((long long)best, off, 64);
+        if (o < best) best = o;
+    }
+    if (lane != 0) return;
+    if (best != ~0ull) atomicMin(reinterpret_cast<unsigned long long*>(qbest + q), best);
+    __threadfence();
+    if (atomicAdd(qticket + q, 1) != P - 1) return;
+    __threadfence();
+    // the last workgroup: every other one's minimum is in place
+    const uint64_t r = atomicAdd(reinterpret_cast<unsigned long long*>(qbest + q), 0ull);
+    best_id[q] = r == ~0ull ? -1 : (int64_t)(r & 0xffffffffull);
+    best_cost[q] = r == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(r >> 32));
 }
 
 // One wave per query: exact cost of every listed candidate, (cost, id) min.
@@ -905,9 +1355,15 @@ using RescoreFn = void (*)(QueryIndexView, const float*, const float*, const uin
                            const int32_t*, const int64_t*, int64_t, int, int64_t*, float*,
                            int64_t*, int32_t*, int);
 
+using PrologueOneFn = void (*)(QueryIndexView, const float*, const uint8_t*, int64_t, int32_t*,
+                               double*, uint64_t*, uint32_t*, int64_t, uint64_t*, int32_t*);
+struct PrologueEntry {
+    PrologueFn many;
+    PrologueOneFn one;
+};
 template <int D>
-PrologueFn prologue_fn(bool wide) {
-    return wide ? prologue_kernel<D, 64> : prologue_kernel<D, kPrologueLanes>;
+PrologueEntry prologue_entry() {
+    return {prologue_kernel<D, kPrologueLanes>, prologue_one_kernel<D>};
 }
 
 using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
@@ -917,16 +1373,21 @@ using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32
 // fn / fn_l1: large batches (one row of a candidate per memory round
 // trip, few registers); gfn / gfn_l1: up to kRescoreSharedQ queries (rows
 // requested in groups, for the latency of small batches)
+using SplitFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
+                         const int32_t*, const int64_t*, int64_t, int, int, uint64_t*, int32_t*,
+                         int64_t*, float*);
 struct RescoreEntry {
     int nd, K, C;
     RescoreFn fn, fn_l1, gfn, gfn_l1;
     ListFn lfn, lfn_l1;
+    SplitFn sfn, sfn_l1;
 };
 #define SFC_RESCORE(ND, K, C)                                                                 \
     {ND, K, C, rescore_kernel<ND, K, C, 0>, rescore_kernel<ND, K, C, 1>,                     \
      rescore_kernel<ND, K, C, 0, cost_row_group(ND, K, C)>,                                 \
      rescore_kernel<ND, K, C, 1, cost_row_group(ND, K, C)>,                                 \
-     list_rescore_kernel<ND, K, C, 0>, list_rescore_kernel<ND, K, C, 1>}
+     list_rescore_kernel<ND, K, C, 0>, list_rescore_kernel<ND, K, C, 1>,                    \
+     rescore_split_kernel<ND, K, C, 0>, rescore_split_kernel<ND, K, C, 1>}
 const RescoreEntry kRescore[] = {
     SFC_RESCORE(2, 3, 1), SFC_RESCORE(2, 3, 2), SFC_RESCORE(2, 3, 3),
     SFC_RESCORE(2, 5, 1), SFC_RESCORE(2, 5, 2), SFC_RESCORE(2, 5, 3),
@@ -943,32 +1404,40 @@ const RescoreEntry kRescore[] = {
 
 sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const uint8_t* m,
                                  int64_t Q, int32_t* qsub, double* qcoords, uint64_t* qkeys,
-                                 uint32_t* rowmask, int64_t qpad, hipStream_t st) {
+                                 uint32_t* rowmask, int64_t qpad, uint64_t* qbest,
+                                 int32_t* qticket, hipStream_t st) {
     if (Q == 0) return SFC_OK;
-    // few queries: a whole wave per query shortens each one's serial sums
-    const bool wide = Q <= kPrologueWideQ;
-    const int G = wide ? 64 : kPrologueLanes;
-    PrologueFn fn = nullptr;
+    PrologueEntry fn{};
     switch (v.D) {
-    case 1: fn = prologue_fn<1>(wide); break;
-    case 2: fn = prologue_fn<2>(wide); break;
-    case 3: fn = prologue_fn<3>(wide); break;
-    case 4: fn = prologue_fn<4>(wide); break;
-    case 5: fn = prologue_fn<5>(wide); break;
-    case 6: fn = prologue_fn<6>(wide); break;
-    case 7: fn = prologue_fn<7>(wide); break;
-    case 8: fn = prologue_fn<8>(wide); break;
-    case 9: fn = prologue_fn<9>(wide); break;
-    case 10: fn = prologue_fn<10>(wide); break;
-    case 11: fn = prologue_fn<11>(wide); break;
-    case 12: fn = prologue_fn<12>(wide); break;
-    case 16: fn = prologue_fn<16>(wide); break;
+    case 1: fn = prologue_entry<1>(); break;
+    case 2: fn = prologue_entry<2>(); break;
+    case 3: fn = prologue_entry<3>(); break;
+    case 4: fn = prologue_entry<4>(); break;
+    case 5: fn = prologue_entry<5>(); break;
+    case 6: fn = prologue_entry<6>(); break;
+    case 7: fn = prologue_entry<7>(); break;
+    case 8: fn = prologue_entry<8>(); break;
+    case 9: fn = prologue_entry<9>(); break;
+    case 10: fn = prologue_entry<10>(); break;
+    case 11: fn = prologue_entry<11>(); break;
+    case 12: fn = prologue_entry<12>(); break;
+    case 16: fn = prologue_entry<16>(); break;
     default: return fail(SFC_EUNSUPPORTED, "index query: reduced dimension not in {1..12, 16}");
     }
     if (v.Kd > 64 * kMaxKnownWords || v.S > kMaxSubsets)
         return fail(SFC_EUNSUPPORTED, "index query: more than 1024 pixels or 26 subsets per patch");
-    hipLaunchKernelGGL(fn, dim3(blocks_for(Q, 256 / G)), dim3(256), 0, st, v, t, m, Q,
-                       qsub, qcoords, qkeys, rowmask, qpad);
+    if ((qbest == nullptr) != (qticket == nullptr))
+        return fail(SFC_EINVAL, "index query: packed best and ticket go together");
+    // few queries: a workgroup per query, whose loads go out phase by phase
+    // (the split rescoring, for at most kRescoreSplitQ <= kPrologueWideQ
+    // queries, relies on this kernel to clear its words)
+    if (Q <= kPrologueWideQ) {
+        hipLaunchKernelGGL(fn.one, dim3((unsigned)Q), dim3(256), 0, st, v, t, m, Q, qsub, qcoords,
+                           qkeys, rowmask, qpad, qbest, qticket);
+        return launched("prologue_one_kernel");
+    }
+    hipLaunchKernelGGL(fn.many, dim3(blocks_for(Q, 256 / kPrologueLanes)), dim3(256), 0, st, v, t,
+                       m, Q, qsub, qcoords, qkeys, rowmask, qpad);
     return launched("prologue_kernel");
 }
 
@@ -1017,7 +1486,7 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
                                 const uint32_t* rowmask, int64_t qpad, const int32_t* qsub,
                                 const int64_t* wstart, int64_t Q, int64_t* best_id,
                                 float* best_cost, int64_t* cand, int32_t* ncand, int norm,
-                                hipStream_t st) {
+                                uint64_t* qbest, int32_t* qticket, hipStream_t st) {
     if (Q == 0) return SFC_OK;
     const RescoreEntry* ent = nullptr;
     for (const auto& e : kRescore)
@@ -1026,6 +1495,20 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
     int cap = 64;
     while (cap < v.L * v.window) cap <<= 1;
     if (cap > kCap) return fail(SFC_EUNSUPPORTED, "n_curves * window above 2048");
+    // a handful of queries, best answer only: each query's windows split
+    // over workgroups (the prologue cleared the packed minima and tickets)
+    if (Q <= kRescoreSplitQ && !cand && !ncand && best_id && best_cost && qbest && qticket) {
+        // shares of E entries (a power of two, 8..64) whose patches hold
+        // about kSplitShareBytes
+        const int64_t patch = (int64_t)v.Kd * v.C * 4;
+        int E = 64;
+        while (E > 8 && E * patch > kSplitShareBytes) E >>= 1;
+        const int P = (v.L * v.window + E - 1) / E;
+        hipLaunchKernelGGL(norm == 1 ? ent->sfn_l1 : ent->sfn, dim3((unsigned)(Q * P)), dim3(64),
+                           0, st, v, vol, t, rowmask, qpad, qsub, wstart, Q, P, E, qbest, qticket,
+                           best_id, best_cost);
+        return launched("rescore_split_kernel");
+    }
     const size_t lds = (size_t)8 * cap * sizeof(uint32_t);
     // few queries: a workgroup per query (four waves split its candidates)
     // and candidate rows requested in groups; a multiple of 8 workgroups, so

@@ -26,20 +26,25 @@ struct QueryIndexView {
 
 // subset, real coordinates [Q][D] and keys [Q][L][W64] of each query; with
 // rowmask non-null also the rescoring's row masks [rows][qpad] (bit dx of
-// row r: pixel r*K + dx known), written for queries < Q only
+// row r: pixel r*K + dx known), written for queries < Q only; with qbest
+// and qticket non-null (both or neither) and Q <= 256 also qbest[q] =
+// all-ones and qticket[q] = 0, the split rescoring's starting words
 sfc_status launch_query_prologue(const QueryIndexView& v, const float* t, const uint8_t* m,
                                  int64_t Q, int32_t* qsub, double* qcoords, uint64_t* qkeys,
-                                 uint32_t* rowmask, int64_t qpad, hipStream_t st);
+                                 uint32_t* rowmask, int64_t qpad, uint64_t* qbest,
+                                 int32_t* qticket, hipStream_t st);
 // window start per (query, curve): wstart [Q][L]
 sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub,
                                const uint64_t* qkeys, int64_t Q, int64_t* wstart, hipStream_t st);
 // candidates = union of windows (sorted unique); best (cost, id) over them
 // under norm 0 (L2) or 1 (L1). best_id/best_cost or cand/ncand may be null.
+// qbest/qticket [Q]: as cleared by the prologue, or null (then a handful of
+// queries is not split over workgroups).
 sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const float* t,
                                 const uint32_t* rowmask, int64_t qpad, const int32_t* qsub,
                                 const int64_t* wstart, int64_t Q, int64_t* best_id,
                                 float* best_cost, int64_t* cand, int32_t* ncand, int norm,
-                                hipStream_t st);
+                                uint64_t* qbest, int32_t* qticket, hipStream_t st);
 
 // Exact k-NN query (Section II.D) on curve 0 of each query's subset: the k
 // nearest entries by (squared cell distance, id), ids ascending in list

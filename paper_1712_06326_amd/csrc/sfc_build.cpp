@@ -548,9 +548,10 @@ sfc_status curves_from_basis(sfc_index* ix, hipStream_t st) {
 
 namespace {
 // Layout of the index query's temporaries: row masks, coordinates, keys,
-// window starts, subsets (each at a 256-byte boundary).
+// window starts, subsets, packed minima and tickets of the split rescoring
+// (each at a 256-byte boundary).
 struct IndexQueryLayout {
-    size_t rm, co, k, w, s, total;
+    size_t rm, co, k, w, s, pb, tk, total;
     IndexQueryLayout(const sfc_index* ix, int64_t Q) {
         size_t off = 0;
         auto take = [&](size_t bytes) {
@@ -563,6 +564,8 @@ struct IndexQueryLayout {
         k = take((size_t)Q * 8 * ix->L * ix->W64);
         w = take((size_t)Q * 8 * ix->L);
         s = take((size_t)Q * 4);
+        pb = take((size_t)Q * 8);
+        tk = take((size_t)Q * 4);
         total = off;
     }
 };
@@ -588,16 +591,18 @@ sfc_status query_index_on(sfc_index* ix, const float* t, const uint8_t* m, int64
     uint64_t* qkeys = reinterpret_cast<uint64_t*>(base + lay.k);
     int64_t* wstart = reinterpret_cast<int64_t*>(base + lay.w);
     int32_t* qsub = reinterpret_cast<int32_t*>(base + lay.s);
+    uint64_t* qbest = reinterpret_cast<uint64_t*>(base + lay.pb);
+    int32_t* qticket = reinterpret_cast<int32_t*>(base + lay.tk);
     const QueryIndexView v = view_of(ix);
     SFC_TRY(ix->timer.begin("prologue_kernel", st));
-    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, rm, qpad, st));
+    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, rm, qpad, qbest, qticket, st));
     SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->timer.begin("search_kernel", st));
     SFC_TRY(launch_query_search(v, qsub, qkeys, Q, wstart, st));
     SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->timer.begin("rescore_kernel", st));
     SFC_TRY(launch_query_rescore(v, ix->vol, t, rm, qpad, qsub, wstart, Q, best_id, best_cost, cand,
-                                 ncand, ix->opt.norm, st));
+                                 ncand, ix->opt.norm, qbest, qticket, st));
     return ix->timer.end(st);
 }
 
@@ -627,7 +632,7 @@ sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
     SFC_TRY(launch_fill_u64(flag, 1, 0ull, st));
     const QueryIndexView v = view_of(ix);
     SFC_TRY(ix->timer.begin("prologue_kernel", st));
-    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, rm, qpad, st));
+    SFC_TRY(launch_query_prologue(v, t, m, Q, qsub, coords, qkeys, rm, qpad, nullptr, nullptr, st));
     SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->timer.begin("knn_kernel", st));
     SFC_TRY(launch_knn(v, qsub, coords, Q, k, mu, list, cnt, thr,
@@ -651,7 +656,8 @@ sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t
     SFC_TRY(ix->qtmp.reserve(need, "query scratch"));
     uint64_t* qkeys = static_cast<uint64_t*>(ix->qtmp.ptr);
     const QueryIndexView v = view_of(ix);
-    return launch_query_prologue(v, t, m, Q, subset, coords, qkeys, nullptr, 0, ix->st);
+    return launch_query_prologue(v, t, m, Q, subset, coords, qkeys, nullptr, 0, nullptr, nullptr,
+                                 ix->st);
 }
 
 }  // namespace sfc
