@@ -362,25 +362,44 @@ __global__ __launch_bounds__(256) void region_cand_kernel(const float* __restric
     }
     double* bx = box_lds[wave];
     double cs = 0.0;
+    // r / K as a multiply-high: exact while r * K < 2^32 (r < K^d <= 2197)
+    const uint32_t kinv = 0xffffffffu / (uint32_t)g.K + 1u;
     for (int base = 0; base < g.Kd; base += kBoxChunk) {
         const int n = g.Kd - base < kBoxChunk ? g.Kd - base : kBoxChunk;
         for (int i = lane; i < n; i += 64) {
             int64_t u = 0;
             bool inb = true;
-            int r = base + i;
+            uint32_t r = (uint32_t)(base + i);
             for (int a = g.nd - 1; a >= 0; a--) {
-                const int64_t x = c[a] + (r % g.K) - g.h;
-                r /= g.K;
+                const uint32_t rq = __umulhi(r, kinv);
+                const int64_t x = c[a] + (int64_t)(r - rq * (uint32_t)g.K) - g.h;
+                r = rq;
                 if (x < 0 || x >= g.shape[a]) inb = false;
                 u += x * g.stride[a];
             }
-            bx[i] = (inb && mask[u]) ? conf[u] : 0.0;
+            // mask and confidence requested together (an outside offset
+            // reads the voxel itself, then is dropped)
+            const int64_t uu = inb ? u : v;
+            const uint8_t mk = mask[uu];
+            const double cf = conf[uu];
+            bx[i] = (inb && mk) ? cf : 0.0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane == 0)
-            for (int i = 0; i < n; i++) cs += bx[i];
+        // the oracle's order, one add after another; the LDS reads go out
+        // 32 at a time ahead of their adds
+        if (lane == 0) {
+            int i = 0;
+            for (; i + 32 <= n; i += 32) {
+                double x[32];
+#pragma unroll
+                for (int k = 0; k < 32; k++) x[k] = bx[i + k];
+#pragma unroll
+                for (int k = 0; k < 32; k++) cs += x[k];
+            }
+            for (; i < n; i++) cs += bx[i];
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -553,20 +572,27 @@ __global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
     // extraction of the target at c
     int64_t cc[kMaxDims];
     coords_of(g, c, cc);
+    // r / K as a multiply-high: exact while r * K < 2^32 (r < K^d <= 2197)
+    const uint32_t kinv = 0xffffffffu / (uint32_t)g.K + 1u;
     for (int rho = threadIdx.x; rho < g.Kd; rho += kSelThreads) {
         int64_t v = 0;
         bool inb = true;
-        int r = rho;
+        uint32_t r = (uint32_t)rho;
         for (int a = g.nd - 1; a >= 0; a--) {
-            const int64_t xx = cc[a] + (r % g.K) - g.h;
-            r /= g.K;
+            const uint32_t rq = __umulhi(r, kinv);
+            const int64_t xx = cc[a] + (int64_t)(r - rq * (uint32_t)g.K) - g.h;
+            r = rq;
             if (xx < 0 || xx >= g.shape[a]) inb = false;
             v += xx * g.stride[a];
         }
-        const bool known = inb && mask[v];
+        // mask and values requested together (an outside offset reads the
+        // centre, then is dropped)
+        const int64_t vv = inb ? v : c;
+        const bool known = inb && mask[vv];
         m[rho] = known ? 1 : 0;
         for (int ch = 0; ch < g.C; ch++) {
-            const float val = known ? vol[v * g.C + ch] : 0.0f;
+            const float x = vol[vv * g.C + ch];
+            const float val = known ? x : 0.0f;
             t[rho * g.C + ch] = val;
             if (tp) tp[rho * g.C + ch] = val;
         }
@@ -587,7 +613,9 @@ __global__ __launch_bounds__(kSelThreads) void loop_select_kernel(
             const int f = g.nd - 1;
             for (int dx = 0; dx < g.K; dx++) {
                 const int64_t xx = cc[f] + dx - g.h;
-                if (inrow && xx >= 0 && xx < g.shape[f] && mask[base + xx]) bits |= 1u << dx;
+                const bool in = inrow && xx >= 0 && xx < g.shape[f];
+                const uint8_t mk = mask[in ? base + xx : c];   // loads not behind a branch
+                if (in && mk) bits |= 1u << dx;
             }
             rm[(int64_t)r * qpad] = bits;
         }

@@ -57,6 +57,28 @@ __device__ inline int64_t wave_sum_i64(int64_t x) {
     return x;
 }
 
+// Sums over each row of 16 lanes, returned to every lane of the row: a scan
+// by DPP row shifts leaves the row's total in its lane 15, which a
+// ds_swizzle (bit mode: lane -> (lane & 16) | 15 within each 32) copies to
+// the row. Integer sums, so exact in any order.
+__device__ inline int32_t row_sum_i32(int32_t x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    return __builtin_amdgcn_ds_swizzle(x, 0x01f0);   // and 0x10, or 0x0f
+}
+__device__ inline int64_t row_sum_i64(int64_t x) {
+    x += dpp_i64<0x111, 0xf, true>(x);
+    x += dpp_i64<0x112, 0xf, true>(x);
+    x += dpp_i64<0x114, 0xf, true>(x);
+    x += dpp_i64<0x118, 0xf, true>(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int32_t)(uint32_t)(uint64_t)x, 0x01f0);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_ds_swizzle((int32_t)(uint32_t)((uint64_t)x >> 32), 0x01f0);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // ------------------------------------------------------------ prologue
 // G lanes per query, 256/G queries per workgroup.
 //  1. The target's known pixels as a bit set (Kd <= 1024 bits), built with
@@ -186,15 +208,25 @@ __global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const f
             }
         }
     }
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
+    if (G == 16) {   // a query's group is one DPP row
 #pragma unroll
         for (int d = 0; d < D; d++) {
-            A[d] += __shfl_xor(A[d], off, 64);
-            T[d] += (int64_t)__shfl_xor((long long)T[d], off, 64);
+            A[d] = row_sum_i32(A[d]);
+            T[d] = row_sum_i64(T[d]);
         }
 #pragma unroll
-        for (int i = 0; i < NT; i++) Gk[i] += __shfl_xor(Gk[i], off, 64);
+        for (int i = 0; i < NT; i++) Gk[i] = row_sum_i32(Gk[i]);
+    } else {
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+                A[d] += __shfl_xor(A[d], off, 64);
+                T[d] += (int64_t)__shfl_xor((long long)T[d], off, 64);
+            }
+#pragma unroll
+            for (int i = 0; i < NT; i++) Gk[i] += __shfl_xor(Gk[i], off, 64);
+        }
     }
 
     // 4. imputation in float64, the oracle's order
