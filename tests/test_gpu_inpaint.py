@@ -67,3 +67,19 @@ def test_inpaint_many_rounds(order, mode):
 def test_inpaint_volume_index():
     d = synth.small_volume(18, 34, frac=0.04)
     _run(d["volume"], d["mask"], 5, "criminisi", "index", D=6, L=3, b=8, W=16)
+
+
+def test_inpaint_two_level_pick():
+    """Above 16,384 blocks of 256 voxels the pick reduces the block bests in
+    two levels (`loop_part2_kernel`): a 164 x 160 x 160 volume (4,198,400
+    voxels) of seeded noise with two small holes far apart, so that the
+    targets alternate between distant second-level blocks."""
+    rng = np.random.default_rng(41)
+    shape = (164, 160, 160)
+    vol = rng.random(shape, dtype=np.float32)[..., None]
+    mask = np.ones(shape, np.uint8)
+    mask[20:23, 20:23, 20:23] = 0
+    mask[140:142, 130:132, 150:152] = 0
+    assert mask.size > 16384 * 256
+    it = _run(vol, mask, 3, "criminisi", "fp32")
+    say(f"  {it} iterations")
