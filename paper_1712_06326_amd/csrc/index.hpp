@@ -155,10 +155,14 @@ void set_list_capacity_override(int32_t cap);
 sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                        int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
 // The index query on a caller buffer of index_query_bytes(ix, Q) bytes
-// (kernel launches only: no allocation, no synchronisation).
+// (kernel launches only: no allocation, no synchronisation). apply: the
+// fill loop's lone target (Q = 1, best answer only), whose answer the
+// rescoring's last workgroup also applies to the loop's state.
 size_t index_query_bytes(const sfc_index* ix, int64_t Q);
+struct LoopApply;
 sfc_status query_index_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, void* buf,
-                          int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand);
+                          int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand,
+                          const LoopApply* apply = nullptr);
 sfc_status query_coords(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q,
                         int32_t* subset, double* coords);
 sfc_status query_knn(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, int k, int mu,

@@ -19,6 +19,20 @@ struct LoopState {
     int32_t pad2;
 };
 
+// What the loop's apply step writes: the volume, the known mask and
+// confidences, the loop state and the iteration log (cap entries).
+struct LoopApply {
+    float* vol;
+    uint8_t* mask;
+    double* conf;
+    Grid g;
+    LoopState* ls;
+    int64_t cap;
+    int64_t* lc;
+    int64_t* lsrc;
+    float* lcost;
+};
+
 // entries of the two partial levels (nb1 = blocks of 256 voxels, nb2 =
 // blocks of 256 level-1 entries); bytes of one entry
 size_t loop_part_entries(const Grid& g, int64_t* nb1, int64_t* nb2);

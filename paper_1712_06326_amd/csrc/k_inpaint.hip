@@ -10,7 +10,7 @@
 //         indicator across p (out of bounds counts as known), normalised.
 // All arithmetic is float64 without fused operations, in the same order as
 // the reference implementation, so the chosen targets agree bit for bit.
-#include "inpaint.hpp"
+#include "loop_apply.hpp"
 
 namespace sfc {
 
@@ -23,12 +23,6 @@ sfc_status launched(const char* what) {
     return e == hipSuccess ? SFC_OK : check_hip(e, what);
 }
 
-__device__ inline void coords_of(const Grid& g, int64_t v, int64_t* c) {
-    for (int i = 0; i < g.nd; i++) {
-        c[i] = v / g.stride[i];
-        v -= c[i] * g.stride[i];
-    }
-}
 
 __device__ inline double mean_intensity(const float* vol, int64_t v, int C) {
     double s = 0.0;
@@ -415,83 +409,23 @@ __device__ inline Cand wave_best(Cand x, int order) {
     return x;
 }
 
-// Applies the previous iteration's answer (pending): copies the chosen patch
-// into the unknown in-bounds voxels of the target box, marks them known with
-// the target's confidence, logs the iteration and counts the filled voxels.
-// best: the float32 scan's packed (cost bits << 32 | id), or null when the
-// query wrote source and cost into the state. One workgroup.
-__global__ __launch_bounds__(256) void loop_apply_kernel(float* __restrict__ vol,
-                                                         uint8_t* __restrict__ mask,
-                                                         double* __restrict__ conf, Grid g,
-                                                         LoopState* __restrict__ ls,
-                                                         const uint64_t* __restrict__ best,
-                                                         int64_t cap, int64_t* __restrict__ lc,
-                                                         int64_t* __restrict__ lsrc,
-                                                         float* __restrict__ lcost) {
-    __shared__ int64_t sh_s;
-    __shared__ float sh_cost;
-    __shared__ int sh_filled;
-    const int64_t p = ls->centre;
-    // nothing pending: the last fill (applied by a standalone apply at the
-    // start of a round) keeps its region marked for the update that follows
-    if (!ls->pending) return;
+// Applies the previous iteration's answer (pending), apply_pending with
+// one workgroup. best: the float32 scan's packed (cost bits << 32 | id), or
+// null when the query wrote source and cost into the state.
+__global__ __launch_bounds__(256) void loop_apply_kernel(LoopApply a,
+                                                         const uint64_t* __restrict__ best) {
+    int64_t s0 = -1;
+    float c0 = 0.0f;
     if (threadIdx.x == 0) {
-        int64_t s = ls->source;
-        float c = ls->cost;
+        s0 = a.ls->source;
+        c0 = a.ls->cost;
         if (best) {
             const uint64_t b = best[0];
-            s = b == ~0ull ? -1 : (int64_t)(b & 0xffffffffull);
-            c = __uint_as_float((uint32_t)(b >> 32));
-        }
-        sh_s = s;
-        sh_cost = c;
-        sh_filled = 0;
-    }
-    __syncthreads();
-    const int64_t s = sh_s;
-    if (s >= 0) {
-        int64_t cp[kMaxDims], cs[kMaxDims];
-        coords_of(g, p, cp);
-        coords_of(g, s, cs);
-        const double cpick = ls->cpick;
-        int filled = 0;
-        for (int rho = threadIdx.x; rho < g.Kd; rho += blockDim.x) {
-            int64_t up = 0, us = 0;
-            bool inb = true;
-            int r = rho;
-            for (int a = g.nd - 1; a >= 0; a--) {
-                const int64_t o = (r % g.K) - g.h;
-                r /= g.K;
-                const int64_t x = cp[a] + o;
-                if (x < 0 || x >= g.shape[a]) inb = false;
-                up += x * g.stride[a];
-                us += (cs[a] + o) * g.stride[a];
-            }
-            if (!inb || mask[up]) continue;
-            for (int ch = 0; ch < g.C; ch++) vol[up * g.C + ch] = vol[us * g.C + ch];
-            mask[up] = 1;
-            conf[up] = cpick;
-            filled++;
-        }
-        if (filled) atomicAdd(&sh_filled, filled);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ls->pending = 0;
-        if (s >= 0) {
-            const int64_t it = ls->it;
-            if (it < cap) {
-                lc[it] = p;
-                lsrc[it] = s;
-                lcost[it] = sh_cost;
-            }
-            ls->it = it + 1;
-            ls->last = p;
-            ls->unknown -= (unsigned long long)sh_filled;
-        } else {
-            ls->last = -1;
+            s0 = b == ~0ull ? -1 : (int64_t)(b & 0xffffffffull);
+            c0 = __uint_as_float((uint32_t)(b >> 32));
         }
     }
+    apply_pending(a, s0, c0);
 }
 
 // level-1 partials of the blocks of 256 voxels that the last fill's region
@@ -679,7 +613,8 @@ sfc_status launch_loop_init(const float* vol, const uint8_t* mask, const double*
 sfc_status launch_loop_apply(float* vol, uint8_t* mask, double* conf, const Grid& g, LoopState* ls,
                              const uint64_t* best, int64_t cap, int64_t* lc, int64_t* lsrc,
                              float* lcost, hipStream_t st) {
-    loop_apply_kernel<<<1, 256, 0, st>>>(vol, mask, conf, g, ls, best, cap, lc, lsrc, lcost);
+    const LoopApply a{vol, mask, conf, g, ls, cap, lc, lsrc, lcost};
+    loop_apply_kernel<<<1, 256, 0, st>>>(a, best);
     return launched("loop_apply_kernel");
 }
 

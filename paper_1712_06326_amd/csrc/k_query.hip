@@ -4,6 +4,7 @@
 // of entries around it per curve, and rescore the union of the windows with
 // the exact masked cost (a full scan in image space over the candidates).
 #include "keys.hpp"
+#include "loop_apply.hpp"
 #include "mfma_scan.hpp"
 #include "query.hpp"
 
@@ -938,22 +939,27 @@ __device__ inline float staged_cost(const QueryIndexView& v, const float* __rest
 
 // A handful of queries (the fill loop's lone target, best answer only):
 // a query's L*W window entries are split into shares of E <= 64, one
-// single-wave workgroup each, so that a lane costs at most one candidate and
-// one query's patch gathers spread over many compute units (a single CU's
-// path to L2 would otherwise carry all of them). The workgroup stages the
+// workgroup each (the share in wave 0), so that a lane costs at most one
+// candidate and one query's patch gathers spread over many compute units (a
+// single CU's path to L2 would otherwise carry all of them). The workgroup
+// has 256 threads only for the apply below. The workgroup stages the
 // target and its row masks in LDS, removes the duplicates of its share (LDS
 // hash set), costs them (staged_cost), and merges the least (cost, id) into the
 // query's packed minimum in global memory (64-bit atomic minimum); the last
 // of the query's workgroups to finish, by a ticket counter, writes the
 // answer. The packed minimum and the ticket are set to all-ones and zero by
 // the prologue. A candidate in two shares is costed twice with the same
-// result, so the minimum over the union is unchanged.
+// result, so the minimum over the union is unchanged. With apply.ls
+// non-null (the fill loop's lone target) that last workgroup also applies
+// the answer (apply_pending): every other workgroup has finished reading
+// the volume by then.
 template <int ND, int K, int C, int NORM>
-__global__ __launch_bounds__(64) void rescore_split_kernel(
-    QueryIndexView v, const float* __restrict__ vol, const float* __restrict__ t,
+__global__ __launch_bounds__(256) void rescore_split_kernel(
+    QueryIndexView v, const float* vol, const float* __restrict__ t,
     const uint32_t* __restrict__ rowmask, int64_t qpad, const int32_t* __restrict__ qsub,
     const int64_t* __restrict__ wstart, int64_t Q, int P, int E, uint64_t* __restrict__ qbest,
-    int32_t* __restrict__ qticket, int64_t* __restrict__ best_id, float* __restrict__ best_cost) {
+    int32_t* __restrict__ qticket, int64_t* __restrict__ best_id, float* __restrict__ best_cost,
+    LoopApply apply) {
     constexpr int ROWS = (ND == 2) ? K : K * K;
     constexpr int NEL = ROWS * K * C;
     constexpr int RB = split_row_group(ND, K, C);
@@ -961,15 +967,14 @@ __global__ __launch_bounds__(64) void rescore_split_kernel(
     __shared__ uint32_t tab[T];
     __shared__ float st[NEL];
     __shared__ uint32_t srm[ROWS];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x;   // the share's entries are all in wave 0 (E <= 64)
     const int64_t q = blockIdx.x / P;
     const int part = (int)(blockIdx.x - q * P);
     if (q >= Q) return;   // uniform: the grid is Q * P workgroups
     const float* tq = t + q * (int64_t)NEL;
     for (int i = lane; i < NEL; i += 64) st[i] = tq[i];
     for (int r = lane; r < ROWS; r += 64) srm[r] = rowmask[(int64_t)r * qpad + q];
-    tab[lane] = 0xffffffffu;
-    tab[lane + 64] = 0xffffffffu;
+    if (lane < T) tab[lane] = 0xffffffffu;
     const int LW = v.L * v.window;
     const int i = part * E + lane;
     uint32_t id = 0xffffffffu;
@@ -998,19 +1003,34 @@ __global__ __launch_bounds__(64) void rescore_split_kernel(
             best = ((uint64_t)__float_as_uint(cost) << 32) | id;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = (uint64_t)__shfl_xor((long long)best, off, 64);
-        if (o < best) best = o;
+    if (lane < 64) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = (uint64_t)__shfl_xor((long long)best, off, 64);
+            if (o < best) best = o;
+        }
     }
-    if (lane != 0) return;
-    if (best != ~0ull) atomicMin(reinterpret_cast<unsigned long long*>(qbest + q), best);
-    __threadfence();
-    if (atomicAdd(qticket + q, 1) != P - 1) return;
-    __threadfence();
-    // the last workgroup: every other one's minimum is in place
-    const uint64_t r = atomicAdd(reinterpret_cast<unsigned long long*>(qbest + q), 0ull);
-    best_id[q] = r == ~0ull ? -1 : (int64_t)(r & 0xffffffffull);
-    best_cost[q] = r == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(r >> 32));
+    __shared__ int sh_last;
+    int64_t s_ans = -1;
+    float c_ans = 0.0f;
+    if (lane == 0) {
+        if (best != ~0ull) atomicMin(reinterpret_cast<unsigned long long*>(qbest + q), best);
+        __threadfence();
+        const bool last = atomicAdd(qticket + q, 1) == P - 1;
+        if (last) {
+            __threadfence();
+            // the last workgroup: every other one's minimum is in place
+            const uint64_t r = atomicAdd(reinterpret_cast<unsigned long long*>(qbest + q), 0ull);
+            s_ans = r == ~0ull ? -1 : (int64_t)(r & 0xffffffffull);
+            c_ans = r == ~0ull ? __builtin_inff() : __uint_as_float((uint32_t)(r >> 32));
+            best_id[q] = s_ans;
+            best_cost[q] = c_ans;
+        }
+        sh_last = last ? 1 : 0;
+    }
+    if (!apply.ls) return;
+    __syncthreads();
+    if (!sh_last) return;   // uniform over the workgroup
+    apply_pending(apply, s_ans, c_ans);
 }
 
 // One wave per query: exact cost of every listed candidate, (cost, id) min.
@@ -1407,7 +1427,7 @@ using ListFn = void (*)(QueryIndexView, const float*, const float*, const uint32
 // requested in groups, for the latency of small batches)
 using SplitFn = void (*)(QueryIndexView, const float*, const float*, const uint32_t*, int64_t,
                          const int32_t*, const int64_t*, int64_t, int, int, uint64_t*, int32_t*,
-                         int64_t*, float*);
+                         int64_t*, float*, LoopApply);
 struct RescoreEntry {
     int nd, K, C;
     RescoreFn fn, fn_l1, gfn, gfn_l1;
@@ -1518,7 +1538,8 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
                                 const uint32_t* rowmask, int64_t qpad, const int32_t* qsub,
                                 const int64_t* wstart, int64_t Q, int64_t* best_id,
                                 float* best_cost, int64_t* cand, int32_t* ncand, int norm,
-                                uint64_t* qbest, int32_t* qticket, hipStream_t st) {
+                                uint64_t* qbest, int32_t* qticket, const LoopApply* apply,
+                                hipStream_t st) {
     if (Q == 0) return SFC_OK;
     const RescoreEntry* ent = nullptr;
     for (const auto& e : kRescore)
@@ -1536,11 +1557,17 @@ sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const
         int E = 64;
         while (E > 8 && E * patch > kSplitShareBytes) E >>= 1;
         const int P = (v.L * v.window + E - 1) / E;
-        hipLaunchKernelGGL(norm == 1 ? ent->sfn_l1 : ent->sfn, dim3((unsigned)(Q * P)), dim3(64),
+        LoopApply la{};
+        if (apply) {
+            if (Q != 1) return fail(SFC_EINVAL, "index rescoring: the loop's apply takes one query");
+            la = *apply;
+        }
+        hipLaunchKernelGGL(norm == 1 ? ent->sfn_l1 : ent->sfn, dim3((unsigned)(Q * P)), dim3(256),
                            0, st, v, vol, t, rowmask, qpad, qsub, wstart, Q, P, E, qbest, qticket,
-                           best_id, best_cost);
+                           best_id, best_cost, la);
         return launched("rescore_split_kernel");
     }
+    if (apply) return fail(SFC_EUNSUPPORTED, "index rescoring: the loop's apply needs the split form");
     const size_t lds = (size_t)8 * cap * sizeof(uint32_t);
     // few queries: a workgroup per query (four waves split its candidates)
     // and candidate rows requested in groups; a multiple of 8 workgroups, so

@@ -39,12 +39,15 @@ sfc_status launch_query_search(const QueryIndexView& v, const int32_t* qsub,
 // candidates = union of windows (sorted unique); best (cost, id) over them
 // under norm 0 (L2) or 1 (L1). best_id/best_cost or cand/ncand may be null.
 // qbest/qticket [Q]: as cleared by the prologue, or null (then a handful of
-// queries is not split over workgroups).
+// queries is not split over workgroups). apply (the fill loop's lone target,
+// Q = 1, split form only): the answer is also applied to the loop's state.
+struct LoopApply;
 sfc_status launch_query_rescore(const QueryIndexView& v, const float* vol, const float* t,
                                 const uint32_t* rowmask, int64_t qpad, const int32_t* qsub,
                                 const int64_t* wstart, int64_t Q, int64_t* best_id,
                                 float* best_cost, int64_t* cand, int32_t* ncand, int norm,
-                                uint64_t* qbest, int32_t* qticket, hipStream_t st);
+                                uint64_t* qbest, int32_t* qticket, const LoopApply* apply,
+                                hipStream_t st);
 
 // Exact k-NN query (Section II.D) on curve 0 of each query's subset: the k
 // nearest entries by (squared cell distance, id), ids ascending in list

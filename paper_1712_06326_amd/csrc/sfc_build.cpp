@@ -581,7 +581,8 @@ sfc_status query_index(sfc_index* ix, const float* t, const uint8_t* m, int64_t 
 }
 
 sfc_status query_index_on(sfc_index* ix, const float* t, const uint8_t* m, int64_t Q, void* buf,
-                          int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand) {
+                          int64_t* best_id, float* best_cost, int64_t* cand, int32_t* ncand,
+                          const LoopApply* apply) {
     hipStream_t st = ix->st;
     const int64_t qpad = scan_qpad(Q);
     const IndexQueryLayout lay(ix, Q);
@@ -602,7 +603,7 @@ sfc_status query_index_on(sfc_index* ix, const float* t, const uint8_t* m, int64
     SFC_TRY(ix->timer.end(st));
     SFC_TRY(ix->timer.begin("rescore_kernel", st));
     SFC_TRY(launch_query_rescore(v, ix->vol, t, rm, qpad, qsub, wstart, Q, best_id, best_cost, cand,
-                                 ncand, ix->opt.norm, qbest, qticket, st));
+                                 ncand, ix->opt.norm, qbest, qticket, apply, st));
     return ix->timer.end(st);
 }
 

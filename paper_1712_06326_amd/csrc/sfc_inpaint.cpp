@@ -76,19 +76,23 @@ struct LoopBufs {
 
 // One iteration on the handle's stream (kernel launches only): apply the
 // previous iteration's answer, refresh the priorities around it, pick and
-// extract the next target, query it.
+// extract the next target, query it. With the index the query's last
+// workgroup applies its answer itself, so the iteration needs no apply
+// launch; the float32 scan's answer is applied at the next iteration's start.
 sfc_status loop_body(sfc_index* ix, const LoopBufs& b) {
     const Grid& g = ix->g;
     hipStream_t st = ix->st;
     const bool scan = b.mode == SFC_MODE_BRUTE_FP32;
-    SFC_TRY(launch_loop_apply(b.vol, b.mask, b.conf, g, b.state, scan ? b.best : nullptr, b.cap,
-                              b.lc, b.ls, b.lcost, st));
+    if (scan)
+        SFC_TRY(launch_loop_apply(b.vol, b.mask, b.conf, g, b.state, b.best, b.cap, b.lc, b.ls,
+                                  b.lcost, st));
     SFC_TRY(launch_loop_select(b.vol, b.mask, b.conf, g, b.order, b.pv, b.part1, b.part2, b.state,
                                b.t, b.m, scan ? b.tp : nullptr, scan ? b.rm : nullptr,
                                scan_qpad(1), scan ? b.best : nullptr, st));
     if (scan) return scan_fp32_prepared(ix, 1, b.rm, b.tp, b.best);
+    const LoopApply la{b.vol, b.mask, b.conf, g, b.state, b.cap, b.lc, b.ls, b.lcost};
     return query_index_on(ix, b.t, b.m, 1, b.qbuf, &b.state->source, &b.state->cost, nullptr,
-                          nullptr);
+                          nullptr, &la);
 }
 
 sfc_status capture(sfc_index* ix, const LoopBufs& b, int iters, hipGraphExec_t* out) {

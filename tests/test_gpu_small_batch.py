@@ -1,7 +1,7 @@
 """Index queries of a handful of targets, the fill loop's case: up to 256
 targets the prologue runs a workgroup per target, and up to 32 targets the
 rescoring splits each target's windows into shares of 8 to 64 entries, one
-single-wave workgroup each, merged by a 64-bit atomic minimum. Subsets,
+workgroup each, merged by a 64-bit atomic minimum. Subsets,
 coordinates and answers equal the oracle's for batch sizes on both sides of
 both switch points, in the L2 and L1 norms, on images and volumes, with
 2 to 128 shares per target and ragged last shares, and call after call on
