@@ -159,7 +159,8 @@ Scratch::~Scratch() { dev_free(ptr); }
 static sfc_status check_geometry(const sfc_geometry* g, int K) {
     if (!g) return fail(SFC_EINVAL, "geometry is NULL");
     if (g->ndim != 2 && g->ndim != 3) return fail(SFC_EINVAL, "ndim must be 2 or 3");
-    if (g->channels < 1 || g->channels > 16) return fail(SFC_EINVAL, "channels must be 1..16");
+    if (g->channels < 1 || g->channels > kMaxChannels)
+        return fail(SFC_EINVAL, "channels must be 1..16");
     int64_t nvox = 1;
     for (int i = 0; i < g->ndim; i++) {
         if (g->shape[i] < 1) return fail(SFC_EINVAL, "shape entries must be >= 1");

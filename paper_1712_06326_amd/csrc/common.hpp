@@ -11,6 +11,7 @@
 namespace sfc {
 
 constexpr int kMaxDims = 3;
+constexpr int kMaxChannels = 16;
 constexpr int kMaxKeyWords = 4;   // D*b <= 256 bits
 constexpr int kMaxD = 32;         // reduced dimension
 constexpr int kMaxSubsetElems = 518;

@@ -41,21 +41,34 @@ __device__ inline void apply_pending(const LoopApply& a, int64_t s0, float c0) {
         coords_of(g, p, cp);
         coords_of(g, s, cs);
         const double cpick = ls->cpick;
+        // r / K as a multiply-high: exact while r * K < 2^32 (r < K^d <= 2197)
+        const uint32_t kinv = 0xffffffffu / (uint32_t)g.K + 1u;
         int filled = 0;
         for (int rho = threadIdx.x; rho < g.Kd; rho += blockDim.x) {
             int64_t up = 0, us = 0;
             bool inb = true;
-            int r = rho;
+            uint32_t r = (uint32_t)rho;
             for (int ax = g.nd - 1; ax >= 0; ax--) {
-                const int64_t o = (r % g.K) - g.h;
-                r /= g.K;
+                const uint32_t rq = __umulhi(r, kinv);
+                const int64_t o = (int64_t)(r - rq * (uint32_t)g.K) - g.h;
+                r = rq;
                 const int64_t x = cp[ax] + o;
                 if (x < 0 || x >= g.shape[ax]) inb = false;
                 up += x * g.stride[ax];
                 us += (cs[ax] + o) * g.stride[ax];
             }
-            if (!inb || a.mask[up]) continue;
-            for (int ch = 0; ch < g.C; ch++) a.vol[up * g.C + ch] = a.vol[us * g.C + ch];
+            // the target voxel's mask and the source values requested
+            // together: the source patch lies inside the volume and is all
+            // known, so it never overlaps the voxels written here
+            const uint8_t known = a.mask[inb ? up : p];
+            float sv[kMaxChannels];
+#pragma unroll
+            for (int ch = 0; ch < kMaxChannels; ch++)
+                if (ch < g.C) sv[ch] = a.vol[us * g.C + ch];
+            if (!inb || known) continue;
+#pragma unroll
+            for (int ch = 0; ch < kMaxChannels; ch++)
+                if (ch < g.C) a.vol[up * g.C + ch] = sv[ch];
             a.mask[up] = 1;
             a.conf[up] = cpick;
             filled++;
