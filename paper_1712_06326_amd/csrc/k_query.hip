@@ -80,6 +80,14 @@ __device__ inline int64_t row_sum_i64(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Lane l's double, to every lane of the wave (two readlanes).
+__device__ inline double bcast_f64(double x, int l) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // ------------------------------------------------------------ prologue
 // G lanes per query, 256/G queries per workgroup.
 //  1. The target's known pixels as a bit set (Kd <= 1024 bits), built with
@@ -488,48 +496,75 @@ __global__ __launch_bounds__(256) void prologue_one_kernel(
     for (int i = 0; i < NT; i++)
         Gk[i] = red[0][3 * D + i] + red[1][3 * D + i] + red[2][3 * D + i] + red[3][3 * D + i];
 
-    // 4. imputation in float64, the oracle's order
-    double a[D][D], rr[D], z[D];
+    // 4. imputation in float64, the oracle's order, one row per lane: lane i
+    // < D holds row i of G_k + I and r_i; each pivot step broadcasts the
+    // pivot row (readlane) and the rows below it update themselves with the
+    // operations the serial elimination applies to them, in its order
+    // (lanes from D on mirror row D - 1 and are never read)
+    __shared__ int64_t stot[2 * D + NT];   // A, T, G_k
+    if (tid == 0) {
 #pragma unroll
-    for (int d = 0; d < D; d++) {
-#pragma unroll
-        for (int f = 0; f < D; f++) {
-            const int lo = d < f ? d : f, hi = d < f ? f : d;
-            const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-            // |entries of W^T W and G_k| <= 128^2 * (1024 * 16) = 2^28:
-            // exact through a 32-bit conversion
-            a[d][f] = (double)(Gk[k] + (d == f ? 1 : 0));
-        }
-        rr[d] = (double)(v.nsub * (int64_t)A[d] - T[d]);
-    }
-#pragma unroll
-    for (int k = 0; k < D; k++)
-#pragma unroll
-        for (int i = k + 1; i < D; i++) {
-            const double fct = a[i][k] / a[k][k];
-#pragma unroll
-            for (int j = k + 1; j < D; j++) a[i][j] = a[i][j] - fct * a[k][j];
-            rr[i] = rr[i] - fct * rr[k];
+        for (int d = 0; d < D; d++) {
+            stot[d] = A[d];
+            stot[D + d] = T[d];
         }
 #pragma unroll
-    for (int i = D - 1; i >= 0; i--) {
-        double s = rr[i];
-#pragma unroll
-        for (int j = i + 1; j < D; j++) s = s - a[i][j] * z[j];
-        z[i] = s / a[i][i];
+        for (int k = 0; k < NT; k++) stot[2 * D + k] = Gk[k];
     }
-    double y[D];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int row = lane < D ? lane : D - 1;
+    double ai[D], ri;
 #pragma unroll
-    for (int d = 0; d < D; d++) {
-        double f = (double)(sws[d] - T[d]);
+    for (int f = 0; f < D; f++) {
+        const int lo = row < f ? row : f, hi = row < f ? f : row;
+        const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
+        ai[f] = (double)((int32_t)stot[2 * D + k] + (row == f ? 1 : 0));
+    }
+    ri = (double)(v.nsub * stot[row] - stot[D + row]);
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const double akk = bcast_f64(ai[k], k), rk = bcast_f64(ri, k);
+        double akj[D];
+#pragma unroll
+        for (int jj = k + 1; jj < D; jj++) akj[jj] = bcast_f64(ai[jj], k);
+        if (row > k) {
+            const double fct = ai[k] / akk;
+#pragma unroll
+            for (int jj = k + 1; jj < D; jj++) ai[jj] = ai[jj] - fct * akj[jj];
+            ri = ri - fct * rk;
+        }
+    }
+    // back substitution, rows from the last: lane i finishes z_i, all take it
+    double z[D];
+#pragma unroll
+    for (int r = D - 1; r >= 0; r--) {
+        double zr = 0.0;
+        if (lane == r) {
+            double sacc = ri;
+#pragma unroll
+            for (int jj = r + 1; jj < D; jj++) sacc = sacc - ai[jj] * z[jj];
+            zr = sacc / ai[r];
+        }
+        z[r] = bcast_f64(zr, r);
+    }
+    // y_d on lane d, then to every lane
+    double yd;
+    {
+        const int d = row;
+        double f = (double)(sws[d] - stot[D + d]);
 #pragma unroll
         for (int e = 0; e < D; e++) {
             const int lo = d < e ? d : e, hi = d < e ? e : d;
             const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-            f = f + (double)(int32_t)(swtw[d * D + e] - (int64_t)Gk[k]) * z[e];
+            f = f + (double)(int32_t)(swtw[d * D + e] - stot[2 * D + k]) * z[e];
         }
-        y[d] = (double)A[d] + f / (double)v.nsub;
+        yd = (double)stot[d] + f / (double)v.nsub;
     }
+    double y[D];
+#pragma unroll
+    for (int d = 0; d < D; d++) y[d] = bcast_f64(yd, d);
     if (tid == 0) {
         qsub[q] = sb;
 #pragma unroll
