@@ -238,50 +238,75 @@ __global__ __launch_bounds__(256) void prologue_kernel(QueryIndexView v, const f
         }
     }
 
-    // 4. imputation in float64, the oracle's order
+    // 4. imputation in float64, the oracle's order, one row per lane of the
+    // group (D <= 16 = G): lane r holds row r of G_k + I and r_r; each
+    // pivot step shares the pivot row within the group and the rows below
+    // it apply the serial elimination's operations to themselves, in its
+    // order; back substitution stays serial, lane d forms y_d (lanes from D
+    // on mirror row D - 1 and are never read)
+    static_assert(G == 16 && D <= G, "one row per lane of a 16-lane group");
     const int64_t* wtw = v.wtw + (int64_t)sb * D * D;
     const int64_t* ws = v.ws + (int64_t)sb * D;
-    double a[D][D], rr[D], z[D];
+    const int row = gl < D ? gl : D - 1;
+    int32_t Ar = 0, grow[D];
+    int64_t Tr = 0;
 #pragma unroll
-    for (int d = 0; d < D; d++) {
+    for (int f = 0; f < D; f++) grow[f] = 0;
+#pragma unroll
+    for (int r = 0; r < D; r++) {
+        if (row != r) continue;
+        Ar = A[r];
+        Tr = T[r];
 #pragma unroll
         for (int f = 0; f < D; f++) {
-            const int lo = d < f ? d : f, hi = d < f ? f : d;
-            const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-            // |entries of W^T W and G_k| <= 128^2 * (1024 * 16) = 2^28:
-            // exact through a 32-bit conversion
-            a[d][f] = (double)(Gk[k] + (d == f ? 1 : 0));
+            const int lo = r < f ? r : f, hi = r < f ? f : r;
+            grow[f] = Gk[lo * D - lo * (lo - 1) / 2 + (hi - lo)];
         }
-        rr[d] = (double)(v.nsub * (int64_t)A[d] - T[d]);
     }
+    double ai[D], ri;
 #pragma unroll
-    for (int k = 0; k < D; k++)
+    for (int f = 0; f < D; f++) {
+        // |entries of W^T W and G_k| <= 128^2 * (1024 * 16) = 2^28:
+        // exact through a 32-bit conversion
+        ai[f] = (double)(grow[f] + (row == f ? 1 : 0));
+    }
+    ri = (double)(v.nsub * (int64_t)Ar - Tr);
 #pragma unroll
-        for (int i = k + 1; i < D; i++) {
-            const double fct = a[i][k] / a[k][k];
+    for (int k = 0; k < D; k++) {
+        const double akk = __shfl(ai[k], k, G), rk = __shfl(ri, k, G);
+        double akj[D];
 #pragma unroll
-            for (int j = k + 1; j < D; j++) a[i][j] = a[i][j] - fct * a[k][j];
-            rr[i] = rr[i] - fct * rr[k];
+        for (int jj = k + 1; jj < D; jj++) akj[jj] = __shfl(ai[jj], k, G);
+        if (row > k) {
+            const double fct = ai[k] / akk;
+#pragma unroll
+            for (int jj = k + 1; jj < D; jj++) ai[jj] = ai[jj] - fct * akj[jj];
+            ri = ri - fct * rk;
         }
+    }
+    double z[D];
 #pragma unroll
-    for (int i = D - 1; i >= 0; i--) {
-        double s = rr[i];
+    for (int r = D - 1; r >= 0; r--) {
+        double zr = 0.0;
+        if (gl == r) {
+            double sacc = ri;
 #pragma unroll
-        for (int j = i + 1; j < D; j++) s = s - a[i][j] * z[j];
-        z[i] = s / a[i][i];
+            for (int jj = r + 1; jj < D; jj++) sacc = sacc - ai[jj] * z[jj];
+            zr = sacc / ai[r];
+        }
+        z[r] = __shfl(zr, r, G);
+    }
+    double yd;
+    {
+        double f = (double)(ws[row] - Tr);
+#pragma unroll
+        for (int e = 0; e < D; e++)
+            f = f + (double)(int32_t)(wtw[row * D + e] - (int64_t)grow[e]) * z[e];
+        yd = (double)Ar + f / (double)v.nsub;
     }
     double y[D];
 #pragma unroll
-    for (int d = 0; d < D; d++) {
-        double f = (double)(ws[d] - T[d]);
-#pragma unroll
-        for (int e = 0; e < D; e++) {
-            const int lo = d < e ? d : e, hi = d < e ? e : d;
-            const int k = lo * D - lo * (lo - 1) / 2 + (hi - lo);
-            f = f + (double)(int32_t)(wtw[d * D + e] - (int64_t)Gk[k]) * z[e];
-        }
-        y[d] = (double)A[d] + f / (double)v.nsub;
-    }
+    for (int d = 0; d < D; d++) y[d] = __shfl(yd, d, G);
     if (!live) return;
     if (gl == 0) {
         qsub[q] = sb;
