@@ -53,33 +53,67 @@ __device__ inline Cand shfl_cand(const Cand& x, int off) {
 // The candidate of front voxel v (coordinates c) whose box confidence sum
 // is cs: (P, C, id) under order 0 (Criminisi), (-C, 0, id) under order 1
 // (raster: only the id ranks, C is carried for the confidence update).
-__device__ inline Cand cand_from_box(const float* __restrict__ vol, const uint8_t* __restrict__ mask,
-                                     const Grid& g, int order, int64_t v, const int64_t* c,
-                                     double cs) {
+// What the data term reads around voxel v: its channel mean and, per
+// axis, the two neighbours' mask bytes (0 outside) and channel means. All
+// of them are requested at once: a mean is read whether or not its
+// neighbour is known (an outside neighbour reads v itself) and dropped
+// when unused, so the values and the arithmetic are those of the reading
+// that branches first.
+struct Nbrs {
+    double I0, Ip[kMaxDims], Im[kMaxDims];
+    uint8_t mp[kMaxDims], mm[kMaxDims];
+};
+
+__device__ inline Nbrs load_nbrs(const float* __restrict__ vol, const uint8_t* __restrict__ mask,
+                                 const Grid& g, int64_t v, const int64_t* c) {
+    Nbrs n;
+    n.I0 = mean_intensity(vol, v, g.C);
+#pragma unroll
+    for (int i = 0; i < kMaxDims; i++) {   // static indices: the arrays stay in registers
+        n.mp[i] = n.mm[i] = 0;
+        n.Ip[i] = n.Im[i] = 0.0;
+        if (i >= g.nd) continue;
+        const bool hasp = c[i] + 1 < g.shape[i], hasm = c[i] > 0;
+        const int64_t vp = hasp ? v + g.stride[i] : v, vm = hasm ? v - g.stride[i] : v;
+        const uint8_t bp = mask[vp], bm = mask[vm];
+        n.mp[i] = hasp ? bp : 0;
+        n.mm[i] = hasm ? bm : 0;
+        n.Ip[i] = mean_intensity(vol, vp, g.C);
+        n.Im[i] = mean_intensity(vol, vm, g.C);
+    }
+    return n;
+}
+
+__device__ inline Cand cand_from_nbrs(const Nbrs& n, const Grid& g, int order, int64_t v,
+                                      const int64_t* c, double cs) {
     const double Cp = cs / (double)g.Kd;
     if (order != 0) return Cand{-Cp, 0.0, v};   // carried, not compared (see reduce with order 1)
     double gr[kMaxDims], nr[kMaxDims], nn = 0.0;
-    const double I0 = mean_intensity(vol, v, g.C);
-    for (int i = 0; i < g.nd; i++) {
+    const double I0 = n.I0;
+#pragma unroll
+    for (int i = 0; i < kMaxDims; i++) {
+        gr[i] = nr[i] = 0.0;
+        if (i >= g.nd) continue;
         const bool hasp = c[i] + 1 < g.shape[i], hasm = c[i] > 0;
-        const int64_t vp = v + g.stride[i], vm = v - g.stride[i];
-        const bool kp = hasp && mask[vp], km = hasm && mask[vm];
+        const bool kp = n.mp[i] != 0, km = n.mm[i] != 0;
         if (kp && km)
-            gr[i] = (mean_intensity(vol, vp, g.C) - mean_intensity(vol, vm, g.C)) / 2.0;
+            gr[i] = (n.Ip[i] - n.Im[i]) / 2.0;
         else if (kp)
-            gr[i] = mean_intensity(vol, vp, g.C) - I0;
+            gr[i] = n.Ip[i] - I0;
         else if (km)
-            gr[i] = I0 - mean_intensity(vol, vm, g.C);
+            gr[i] = I0 - n.Im[i];
         else
             gr[i] = 0.0;
-        const int ip = hasp ? mask[vp] : 1, im = hasm ? mask[vm] : 1;
+        const int ip = hasp ? n.mp[i] : 1, im = hasm ? n.mm[i] : 1;
         nr[i] = (double)(ip - im);
         nn += nr[i] * nr[i];
     }
     double Dp = 0.0;
     if (nn > 0.0) {
         const double len = sqrt(nn);
-        for (int i = 0; i < g.nd; i++) nr[i] = nr[i] / len;
+#pragma unroll
+        for (int i = 0; i < kMaxDims; i++)
+            if (i < g.nd) nr[i] = nr[i] / len;
         if (g.nd == 2) {
             Dp = fabs(gr[0] * nr[1] - gr[1] * nr[0]);
         } else {
@@ -90,6 +124,13 @@ __device__ inline Cand cand_from_box(const float* __restrict__ vol, const uint8_
         }
     }
     return Cand{Cp * Dp, Cp, v};
+}
+
+__device__ inline Cand cand_from_box(const float* __restrict__ vol, const uint8_t* __restrict__ mask,
+                                     const Grid& g, int order, int64_t v, const int64_t* c,
+                                     double cs) {
+    if (order != 0) return Cand{-(cs / (double)g.Kd), 0.0, v};
+    return cand_from_nbrs(load_nbrs(vol, mask, g, v, c), g, order, v, c, cs);
 }
 
 // The fill-order candidate of voxel v: cand_from_box for a front voxel,
@@ -354,6 +395,9 @@ __global__ __launch_bounds__(256) void region_cand_kernel(const float* __restric
         if (lane == 0) pv[v] = Cand{-1.0, -1.0, INT64_MAX};
         return;
     }
+    // the data term's neighbour values, requested with the box's loads
+    Nbrs nb;
+    if (lane == 0 && order == 0) nb = load_nbrs(vol, mask, g, v, c);
     double* bx = box_lds[wave];
     double cs = 0.0;
     // r / K as a multiply-high: exact while r * K < 2^32 (r < K^d <= 2197)
@@ -398,7 +442,7 @@ __global__ __launch_bounds__(256) void region_cand_kernel(const float* __restric
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (lane == 0) pv[v] = cand_from_box(vol, mask, g, order, v, c, cs);
+    if (lane == 0) pv[v] = cand_from_nbrs(nb, g, order, v, c, cs);
 }
 
 __device__ inline Cand wave_best(Cand x, int order) {
