@@ -382,14 +382,27 @@ __global__ __launch_bounds__(256) void region_cand_kernel(const float* __restric
         if (c[a] < 0 || c[a] >= g.shape[a]) return;
         v += c[a] * g.stride[a];
     }
-    if (!mask[v]) {
+    // the voxel's mask and its face neighbours' requested together (an
+    // outside neighbour reads the voxel itself and is not used)
+    const uint8_t mv = mask[v];
+    uint8_t mlo[kMaxDims], mhi[kMaxDims];
+#pragma unroll
+    for (int i = 0; i < kMaxDims; i++) {
+        mlo[i] = mhi[i] = 1;
+        if (i >= g.nd) continue;
+        mlo[i] = mask[c[i] > 0 ? v - g.stride[i] : v];
+        mhi[i] = mask[c[i] + 1 < g.shape[i] ? v + g.stride[i] : v];
+    }
+    if (!mv) {
         if (lane == 0) pv[v] = Cand{-1.0, -1.0, INT64_MAX};
         return;
     }
     bool front = false;
-    for (int i = 0; i < g.nd; i++) {
-        if (c[i] > 0 && !mask[v - g.stride[i]]) front = true;
-        if (c[i] + 1 < g.shape[i] && !mask[v + g.stride[i]]) front = true;
+#pragma unroll
+    for (int i = 0; i < kMaxDims; i++) {
+        if (i >= g.nd) continue;
+        if (c[i] > 0 && !mlo[i]) front = true;
+        if (c[i] + 1 < g.shape[i] && !mhi[i]) front = true;
     }
     if (!front) {
         if (lane == 0) pv[v] = Cand{-1.0, -1.0, INT64_MAX};
@@ -404,6 +417,7 @@ __global__ __launch_bounds__(256) void region_cand_kernel(const float* __restric
     const uint32_t kinv = 0xffffffffu / (uint32_t)g.K + 1u;
     for (int base = 0; base < g.Kd; base += kBoxChunk) {
         const int n = g.Kd - base < kBoxChunk ? g.Kd - base : kBoxChunk;
+#pragma unroll 4
         for (int i = lane; i < n; i += 64) {
             int64_t u = 0;
             bool inb = true;
